@@ -1,0 +1,146 @@
+#!/usr/bin/env python3
+"""Throughput of the symplectic FRW lattice step on one MI355X.
+
+Default workload: two-field chaotic preheating on a 256^3 lattice, 6th-order
+composition (7 fused stage passes per step), dt = 0.0025, FP64 fields,
+self-consistent expansion, vacuum initial fluctuations built on the device.
+Prints one JSON line:
+
+  value       field-site-updates/s = n^3 * N_f * steps / wall time of the
+              timed steps (inputs resident in HBM, both sides synchronised)
+  roofline    dominant kernel (fused stage pass): algorithmic bytes per
+              launch (4 * b * N_f * n^3: read phi, pi; write phi, pi) over its
+              mean launch time from HIP events on the lattice's stream
+  cpu_baseline the FP64 oracle timed for one step of the same workload on
+              one host core
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--n", type=int, default=256)
+    p.add_argument("--order", type=int, default=6)
+    p.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage line")
+    return p.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def measure(sl, recipe, steps, warmup):
+    lat = sl.from_recipe(recipe)
+    order, dt = recipe["order"], recipe["dt"]
+    lat.evolve(warmup, dt, order)
+    lat.synchronize()
+    t0 = time.perf_counter()
+    lat.evolve(steps, dt, order)
+    lat.synchronize()
+    wall = time.perf_counter() - t0
+    # kernel-level timing of the fused pass over a second timed region
+    lat.set_kernel_timing(True)
+    lat.evolve(steps, dt, order)
+    passes, pass_ms = lat.kernel_timing()
+    lat.set_kernel_timing(False)
+    e = lat.energies()
+    tile = lat.tile()
+    lat.close()
+    return wall, passes, pass_ms, e, tile
+
+
+def cpu_baseline(recipe):
+    """FP64 oracle, one composed step of the same workload, one core."""
+    import numpy as np  # noqa: F401
+    import oracle
+    pot = oracle.Potential(recipe["potential"], recipe["params"])
+    o = oracle.Lattice(recipe["n"], recipe["L"], pot, mpl=recipe["mpl"])
+    o.init_fluctuations(recipe["phi0"], recipe["pi0"], recipe["fluct"], recipe["amplitude"],
+                        recipe["seed"])
+    t0 = time.perf_counter()
+    o.step(recipe["dt"], recipe["order"])
+    t = time.perf_counter() - t0
+    n3 = recipe["n"] ** 3
+    return {"value": n3 * recipe["nfields"] / t, "unit": "field-site-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "1 step (%d stage passes) of the %d^3 %s workload, numpy FP64, %.1f s"
+                      % (len(oracle.composition_weights(recipe["order"])), recipe["n"],
+                         recipe["workload"], t)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the method's multi-GPU forms are not built "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import paper_1201_5029_amd as sl
+    import synth
+
+    recipe = synth.preheat(n=args.n, order=args.order, dt=0.0025, steps=args.steps,
+                           precision=args.precision)
+    log("workload", recipe["workload"], args.n, "order", args.order, args.precision)
+    wall, passes, pass_ms, e, tile = measure(sl, recipe, args.steps, args.warmup)
+    nf = recipe["nfields"]
+    n3 = args.n ** 3
+    b = 8 if args.precision == "f64" else 4
+    stages = len(sl.composition_weights(args.order))
+    value = n3 * nf * args.steps / wall
+    avg_pass_s = pass_ms / passes / 1e3
+    bytes_per_pass = 4 * b * nf * n3
+    achieved = bytes_per_pass / avg_pass_s / 1e9
+    log("wall %.4f s, %.4f ms/step, pass %.4f ms (%d passes)" %
+        (wall, wall / args.steps * 1e3, avg_pass_s * 1e3, passes))
+    out = {
+        "metric": "lattice site-updates/s per field",
+        "value": value,
+        "unit": "field-site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": "preheat two-field chaotic, %d^3, order %d (%d stages), dt 0.0025, "
+                               "%s fields, FP64 reductions and background" %
+                               (args.n, args.order, stages, args.precision.upper()),
+                   "n": args.n, "nfields": nf, "order": args.order, "stages": stages,
+                   "tile": list(tile)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "pass_kernel", "avg_launch_ms": avg_pass_s * 1e3,
+                     "bytes_per_launch": bytes_per_pass},
+        "friedmann_residual": e["friedmann_residual"],
+    }
+    if not args.no_fp32 and args.precision == "f64":
+        r32 = dict(recipe, precision="f32")
+        w32, p32, ms32, e32, tile32 = measure(sl, r32, args.steps, args.warmup)
+        out["fp32_storage"] = {
+            "value": n3 * nf * args.steps / w32, "ms_per_step": w32 / args.steps * 1e3,
+            "pass_ms": ms32 / p32, "achieved_GBs": 4 * 4 * nf * n3 / (ms32 / p32 / 1e3) / 1e9,
+            "friedmann_residual": e32["friedmann_residual"], "tile": list(tile32)}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, 1 step) ...")
+        out["cpu_baseline"] = cpu_baseline(recipe)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * symlat.h -- C ABI of the MI355X (gfx950) symplectic FRW lattice library.
+ *
+ * The library advances interacting real scalar fields phi_i(x), i = 1..N_f,
+ * on a periodic n^3 comoving lattice in a self-consistently expanding
+ * flat FRW background in conformal time, with the symplectic method of
+ * Sainio, "PyCOOL - a Cosmological Object-Oriented Lattice code written in
+ * Python" (arXiv:1201.5029):
+ *
+ *   - discretised Hamiltonian with the 7-point Laplacian member of the
+ *     stencil family of Sec. 2.1, eq. (2.7), and radiation/matter terms,
+ *     eq. (2.20);
+ *   - three-way split H = H1 + H2 + H3 with exact flows, eq. (2.46)-(2.47);
+ *   - second-order map eq. (2.48) composed to 4th order by the triple jump
+ *     eq. (2.43)-(2.44), or to 6th/8th order with the symmetric
+ *     compositions of eq. (2.45) and Table 1.
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns sl_status; no exception crosses the ABI.  On error
+ *     sl_last_error() returns a thread-local message (valid until the next
+ *     call on that thread).
+ *   - A lattice handle owns all of its device memory.  Host buffers passed
+ *     in or out are owned by the caller and only read/written during the
+ *     call.
+ *   - Field arrays exchanged with the host are FP64, laid out
+ *     [field][z][y][x] with x fastest: element (i, z, y, x) is at
+ *     ((i*n + z)*n + y)*n + x.
+ *   - Work is enqueued on the handle's HIP stream.  sl_evolve returns
+ *     without waiting; device-side failures (non-finite lattice sums) are
+ *     reported by the next synchronising call (sl_energies, sl_get_fields,
+ *     sl_get_background, sl_spectrum, sl_synchronize) as SL_E_NONFINITE.
+ *   - One handle must not be used from two threads at once.
+ */
+#ifndef SYMLAT_H
+#define SYMLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sl_lattice sl_lattice;
+typedef struct sl_batch sl_batch;
+
+typedef enum {
+  SL_OK = 0,
+  SL_E_INVALID = 1,   /* bad argument: nothing was changed                   */
+  SL_E_NOMEM = 2,     /* device or host allocation failed                    */
+  SL_E_DEVICE = 3,    /* a HIP runtime call failed                           */
+  SL_E_STATE = 4,     /* call out of order (e.g. evolve before a potential)  */
+  SL_E_NONFINITE = 5, /* a lattice sum or the background became non-finite   */
+  SL_E_UNSTABLE = 6   /* omega_max*|dt| beyond the composition's stability   */
+} sl_status;
+
+/* Storage precision of phi and pi.  SL_FP32 stores and updates the fields
+ * in FP32; the scale factor, its momentum, every stage coefficient and all
+ * lattice sums stay FP64 with compensated (TwoSum) accumulation. */
+typedef enum { SL_FP64 = 0, SL_FP32 = 1 } sl_precision;
+
+/* SL_EXPAND_SELF: a and p_a follow eq. (2.47).  SL_EXPAND_NONE: static
+ * background, a stays at a0 (H1 is the identity and p_a is not updated). */
+typedef enum { SL_EXPAND_NONE = 0, SL_EXPAND_SELF = 1 } sl_expansion;
+
+/* Potential families (Sec. 3 models in program units) and their params:
+ *   SL_POT_FREE       (m_1^2, ..., m_Nf^2)   V = sum_i m_i^2 phi_i^2 / 2
+ *   SL_POT_CHAOTIC2   (m^2, G)               V = m^2 phi^2/2 + G phi^2 chi^2/2
+ *                                            (N_f = 2, Sec. 3.1, G = g^2)
+ *   SL_POT_OSCILLON   (m^2, lambda, g)       V = m^2 phi^2/2 - lambda phi^4/4
+ *                                                + g phi^6/6   (N_f = 1)
+ *   SL_POT_QBALL_LOG  (m^2, K, M^2)          u = (phi_1^2 + phi_2^2)/2,
+ *                                            V = m^2 u (1 + K ln(u/M^2)),
+ *                                            V = dV = 0 at u = 0 (N_f = 2,
+ *                                            Sec. 3.3 without |Phi|^6)    */
+typedef enum {
+  SL_POT_FREE = 0,
+  SL_POT_CHAOTIC2 = 1,
+  SL_POT_OSCILLON = 2,
+  SL_POT_QBALL_LOG = 3
+} sl_potential;
+
+/* Initial fluctuations added to the homogeneous values:
+ *   SL_FLUCT_NONE    none
+ *   SL_FLUCT_VACUUM  Gaussian field with E|f_n|^2 = A^2/(2 omega_n L^3),
+ *                    omega_n^2 = k_eff^2/dx^2 + d2V/dphi_i^2 (homogeneous
+ *                    point), k_eff^2 = sum_d 4 sin^2(pi n_d/n), zero mode
+ *                    removed, built in k-space and inverse transformed
+ *   SL_FLUCT_WHITE   i.i.d. N(0, A^2) per site with its lattice mean removed
+ * Normal deviates come from a counter-based SplitMix64 + Box-Muller
+ * generator keyed by (seed, field, index, component), so the draw does not
+ * depend on launch shape. */
+typedef enum { SL_FLUCT_NONE = 0, SL_FLUCT_VACUUM = 1, SL_FLUCT_WHITE = 2 } sl_fluct;
+
+typedef struct {
+  int32_t n;         /* lattice side, 4 <= n <= 1024                        */
+  int32_t nfields;   /* N_f, 1..8                                           */
+  double L;          /* comoving side length (> 0); dx = L/n                */
+  int32_t precision; /* sl_precision                                        */
+  int32_t expansion; /* sl_expansion                                        */
+  double mpl;        /* reduced Planck mass m_pl (> 0)                      */
+  double a0;         /* initial scale factor (> 0)                          */
+  double rho_rad0;   /* homogeneous radiation V_L rho_gamma0 term, eq. (2.20) */
+  double rho_mat0;   /* homogeneous matter term, eq. (2.20)                 */
+} sl_config;
+
+/* Observables of eq. (2.16), (2.18), (3.1) at the current time, computed on
+ * the device at the synchronised state (pending field drifts applied
+ * virtually; the stored state is not modified). */
+typedef struct {
+  double eta;                /* conformal time                                  */
+  double a, p_a;             /* scale factor and its momentum                    */
+  double hubble;             /* H = a'/a^2 = -p_a/(6 V_L m_pl^2 a^2); 0 if static */
+  double rho, pressure;      /* <rho>, <P> of the fields, eq. (2.16)             */
+  double w_eos;              /* <P>/<rho>                                         */
+  double friedmann_residual; /* |<rho_tot>/(3 m_pl^2 H^2) - 1|, eq. (3.1); NaN if static */
+  double h_total;            /* total Hamiltonian eq. (2.20) (no H1 term if static) */
+  double pot;                /* <V>                                               */
+  double kin[8];             /* <pi_i^2>/(2 a^6)                                   */
+  double grad[8];            /* <G[phi_i]>/(2 a^2 dx^2), eq. (2.8)                 */
+  double mean[8];            /* <phi_i>                                            */
+  double var[8];             /* <phi_i^2> - <phi_i>^2                              */
+} sl_energies_t;
+
+/* Create a lattice (Sec. 2.1 state: phi, pi, a, p_a).  hip_stream is a
+ * hipStream_t owned by the caller or NULL (the handle then creates its own
+ * non-blocking stream).  Allocates device memory for two copies of (phi,
+ * pi) in the storage precision plus O(#blocks) FP64 partial sums.
+ * SL_E_INVALID for n < 4 or n > 1024, nfields outside 1..8, L, mpl or a0
+ * not > 0, or a NULL argument. */
+sl_status sl_lattice_create(const sl_config* cfg, void* hip_stream, sl_lattice** out);
+
+/* Release all device memory of the handle; NULL is a no-op. */
+sl_status sl_lattice_destroy(sl_lattice* lat);
+
+/* Select the potential family and copy its nparams parameters (see
+ * sl_potential).  SL_E_INVALID if the family does not fit nfields or
+ * nparams is wrong.  Must precede sl_init_fluctuations / sl_evolve. */
+sl_status sl_set_potential(sl_lattice* lat, int32_t kind, const double* params, int32_t nparams);
+
+/* Initial state: phi_i = phi0[i] + fluctuation, pi_i = pi0[i] (canonical
+ * momenta), a = a0, eta = 0, then p_a from the constraint H = 0 on the
+ * expanding branch (p_a < 0), eq. (2.20).  phi0 and pi0 hold nfields
+ * doubles.  amplitude is A of sl_fluct.  Runs entirely on the device.
+ * SL_E_INVALID for an unknown kind, a negative amplitude, or VACUUM where
+ * a field's effective mass is undefined; SL_E_STATE if the constraint has
+ * no real solution. */
+sl_status sl_init_fluctuations(sl_lattice* lat, const double* phi0, const double* pi0,
+                               int32_t kind, double amplitude, uint64_t seed);
+
+/* Advance `steps` composed steps of size dt (dt < 0 runs backwards) with
+ * the given order: 2 (eq. (2.48)), 4 (triple jump, eq. (2.43)), 6 or 8
+ * (Table 1).  Each stage is one fused device pass (drift owed from the
+ * previous H2 flows, Laplacian, kick, FP64 block sums) and one device-side
+ * scalar update; the trailing field drift of the last stage is kept
+ * pending, so evolve(a) then evolve(b) equals evolve(a + b) bit for bit.
+ * SL_E_INVALID for steps < 0, dt not finite, or an unknown order;
+ * SL_E_UNSTABLE if omega_max |dt| exceeds the order's linear stability
+ * limit (omega_max^2 = 12/dx^2 + a^2 max(m_eff^2, 0)). */
+sl_status sl_evolve(sl_lattice* lat, int64_t steps, double dt, int32_t order);
+
+/* Compute the observables (one extra read pass over the lattice) and
+ * copy them to *out; synchronises the stream. */
+sl_status sl_energies(sl_lattice* lat, sl_energies_t* out);
+
+/* Field power spectrum of phi_field: F_n = DFT(phi)/n^3, modes binned by
+ * |n| rounded half away from zero (decided in integers), the n = 0 mode
+ * excluded, modes with bin >= nbins dropped.  k_out[b] = 2 pi <|n|>_b / L,
+ * p_out[b] = <|F_n|^2>_b, count_out[b] = number of modes; empty bins are
+ * zero.  Host arrays of nbins entries; 1 <= nbins <= 2048.  Synchronises. */
+sl_status sl_spectrum(sl_lattice* lat, int32_t field, int32_t nbins,
+                      double* k_out, double* p_out, int64_t* count_out);
+
+/* Copy the synchronised fields to host FP64 arrays of nfields*n^3 each
+ * (either pointer may be NULL).  Synchronises. */
+sl_status sl_get_fields(sl_lattice* lat, double* phi_out, double* pi_out);
+
+/* Replace the state by host FP64 arrays (rounded to the storage precision),
+ * set a and eta = 0 and p_a; p_a = NaN means "solve the constraint H = 0".
+ * A potential must be set.  SL_E_INVALID for NULL arrays or a <= 0. */
+sl_status sl_set_fields(sl_lattice* lat, const double* phi, const double* pi,
+                        double a, double p_a);
+
+/* Conformal time, scale factor and its momentum.  Synchronises. */
+sl_status sl_get_background(sl_lattice* lat, double* eta, double* a, double* p_a);
+
+/* Wait for the handle's stream; reports sticky device-side errors. */
+sl_status sl_synchronize(sl_lattice* lat);
+
+/* Device bytes a lattice of this configuration allocates (0 if invalid). */
+size_t sl_footprint_bytes(const sl_config* cfg);
+
+/* Thread-local message of the last failing call on this thread. */
+const char* sl_last_error(void);
+
+/* Host helpers (no device work):
+ * sl_composition_weights writes the s stage weights of `order` into w_out
+ * (capacity cap) and returns s, or -1 for an unknown order / small cap;
+ * sl_stability_limit returns the largest stable omega*h of the order's
+ * composition on a harmonic mode, or -1. */
+int32_t sl_composition_weights(int32_t order, double* w_out, int32_t cap);
+double sl_stability_limit(int32_t order);
+
+/* Kernel timing for measurement: while enabled, sl_evolve brackets every
+ * fused stage pass with HIP events on the handle's stream.
+ * sl_kernel_timing synchronises and returns the number of timed passes and
+ * their summed duration (ms) since enabling, then clears the record. */
+sl_status sl_set_kernel_timing(sl_lattice* lat, int32_t enable);
+sl_status sl_kernel_timing(sl_lattice* lat, int64_t* passes, double* total_ms);
+
+/* Launch shape of the fused pass: tile width in x (16, 32 or 64 lanes),
+ * rows per tile (256 / tx) and z-planes per tile.  sl_get_tile reports the
+ * shape in use; sl_set_tile overrides it (tz = 0 picks the default
+ * z-chunk).  SL_E_INVALID for unsupported shapes. */
+sl_status sl_get_tile(sl_lattice* lat, int32_t* tx, int32_t* ty, int32_t* tz);
+sl_status sl_set_tile(sl_lattice* lat, int32_t tx, int32_t tz);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYMLAT_H */

@@ -1,0 +1,147 @@
+// Device helpers shared by the lattice kernels: compensated FP64 sums,
+// fixed-order wave/workgroup reductions, the potential families and the
+// field drift.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace symlat {
+
+// ---------------------------------------------------------------------------
+// Compensated summation.  A running sum is a pair (s, c) whose exact value is
+// s + c; values are added with Knuth's branch-free TwoSum so that the FP64
+// result is insensitive to the magnitude order of the terms.  All trees
+// below combine pairs in a fixed order, so sums are bitwise reproducible.
+// ---------------------------------------------------------------------------
+struct KSum {
+  double s, c;
+};
+
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  double bp = s - a;
+  double ap = s - bp;
+  e = (a - ap) + (b - bp);
+}
+
+__device__ __forceinline__ void kadd(KSum& k, double x) {
+#pragma clang fp contract(off)
+  double s, e;
+  two_sum(k.s, x, s, e);
+  k.s = s;
+  k.c += e;
+}
+
+__device__ __forceinline__ KSum kcombine(KSum a, KSum b) {
+#pragma clang fp contract(off)
+  KSum r;
+  double e;
+  two_sum(a.s, b.s, r.s, e);
+  r.c = (a.c + b.c) + e;
+  return r;
+}
+
+// Butterfly over the 64 lanes of a wavefront (fixed xor pattern).
+__device__ __forceinline__ KSum wave_reduce(KSum v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    KSum o;
+    o.s = __shfl_xor(v.s, off, 64);
+    o.c = __shfl_xor(v.c, off, 64);
+    v = kcombine(v, o);
+  }
+  return v;
+}
+
+// Reduce NV pairs over a 256-thread workgroup; thread 0 gets the result.
+// scratch: 4 * NV KSum of LDS.  Contains barriers: all threads must call.
+template <int NV>
+__device__ __forceinline__ void block_reduce(KSum (&v)[NV], KSum* scratch) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_reduce(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) scratch[wave * NV + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      KSum t = scratch[k];
+      for (int w = 1; w < kBlock / 64; ++w) t = kcombine(t, scratch[w * NV + k]);
+      v[k] = t;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Potential families (program units); V once per site, dV per field.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PotT {
+  T p[kMaxFields];
+};
+
+template <typename T>
+__device__ __forceinline__ T dev_log(T x);
+template <>
+__device__ __forceinline__ float dev_log<float>(float x) { return logf(x); }
+template <>
+__device__ __forceinline__ double dev_log<double>(double x) { return log(x); }
+
+template <int KIND, int NF, typename T>
+__device__ __forceinline__ void potential(const T (&f)[NF], const PotT<T>& P, T& V, T (&dV)[NF]) {
+  if constexpr (KIND == SL_POT_FREE) {
+    V = T(0);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      dV[i] = P.p[i] * f[i];
+      V += T(0.5) * dV[i] * f[i];
+    }
+  } else if constexpr (KIND == SL_POT_CHAOTIC2) {
+    static_assert(NF == 2, "two fields");
+    const T m2 = P.p[0], G = P.p[1];
+    const T f2 = f[0] * f[0], c2 = f[1] * f[1];
+    const T mc = m2 + G * c2;
+    V = T(0.5) * f2 * mc;
+    dV[0] = f[0] * mc;
+    dV[1] = G * f2 * f[1];
+  } else if constexpr (KIND == SL_POT_OSCILLON) {
+    static_assert(NF == 1, "one field");
+    const T m2 = P.p[0], lam = P.p[1], g = P.p[2];
+    const T x = f[0], x2 = x * x;
+    // V = x^2 (m2/2 - lam x^2/4 + g x^4/6),  dV = x (m2 - lam x^2 + g x^4)
+    V = x2 * (T(0.5) * m2 + x2 * (T(-0.25) * lam + x2 * (g * T(1.0 / 6.0))));
+    dV[0] = x * (m2 + x2 * (-lam + x2 * g));
+  } else {
+    static_assert(NF == 2, "two fields");
+    const T m2 = P.p[0], K = P.p[1], invM2 = P.p[2];  // p[2] holds 1/M^2
+    const T u = T(0.5) * (f[0] * f[0] + f[1] * f[1]);
+    if (u > T(0)) {
+      const T lg = dev_log<T>(u * invM2);
+      V = m2 * u * (T(1) + K * lg);
+      const T fac = m2 * (T(1) + K + K * lg);
+      dV[0] = fac * f[0];
+      dV[1] = fac * f[1];
+    } else {
+      V = T(0);
+      dV[0] = T(0);
+      dV[1] = T(0);
+    }
+  }
+}
+
+// Field drift phi + c pi as one fused multiply-add, so every tile computes
+// the same value for a site.
+__device__ __forceinline__ float drift(float phi, float pi, float c) { return fmaf(c, pi, phi); }
+__device__ __forceinline__ double drift(double phi, double pi, double c) { return fma(c, pi, phi); }
+
+__device__ __forceinline__ bool dev_finite(double x) { return !(isnan(x) || isinf(x)); }
+
+}  // namespace symlat

@@ -1,0 +1,129 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libsymlat (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "symlat.h"
+
+namespace symlat {
+
+constexpr int kBlock = 256;     // threads per workgroup of every lattice kernel
+constexpr int kMaxFields = 8;
+constexpr int kMaxBins = 2048;
+
+// Sticky device-side error bits in DevScalars::status.
+constexpr int kStatusNonFinite = 1;
+
+// Background scalars and the coefficients of the next fused pass, resident
+// in device memory (FP64).  Only device kernels update them during
+// evolution; the host reads them after a synchronisation.
+struct DevScalars {
+  double a;        // scale factor
+  double p_a;      // its canonical momentum
+  double eta;      // conformal time
+  double S2;       // sum_{i,x} pi_i^2 of the stored momenta
+  double c_pend;   // field drift owed: phi_true = phi_stored + c_pend * pi
+  double c_next;   // drift the next pass applies before its kick
+  double alpha;    // kick coefficient of the Laplacian: a^2 w h / dx^2
+  double beta;     // kick coefficient of dV: a^4 w h
+  double a_kick;   // scale factor during the next kick
+  double S3_last;  // last H3 lattice sum (diagnostic)
+  int32_t parity;  // which ping-pong buffer holds the state
+  int32_t status;  // sticky error bits
+};
+
+// Per-lattice constants of the scalar updates.
+struct BgConsts {
+  double inv_dx2;    // 1/dx^2
+  double inv6VLm2;   // 1/(6 V_L m_pl^2)
+  double VL;         // V_L = n^3
+  double VL_rho_m;   // V_L rho_m0
+  double VL_rho_r;   // V_L rho_gamma0
+  double mpl2;       // m_pl^2
+  double dx2;
+  double L;
+  int32_t expand;    // 1: self-consistent expansion, 0: static a
+  int32_t pad;
+};
+
+struct PotArgs {
+  double p[kMaxFields];
+};
+
+// Launch shape of the tiled passes: TX lanes in x (power of two), TY = 256/TX
+// rows in y, TZ planes per z-chunk.
+struct Tile {
+  int tx, logtx, ty, tz;
+  int ntx, nty, ntz;
+  int nblocks() const { return ntx * nty * ntz; }
+};
+
+// Device view of one lattice handed to the launchers.
+struct LatView {
+  void* phi[2];          // ping-pong field buffers, nf * n^3 each
+  void* pi[2];           // ping-pong momentum buffers
+  DevScalars* sc;
+  double* partials;      // per-block (sum, compensation) pairs
+  int n, nf, prec, pot;  // prec: sl_precision, pot: sl_potential
+  PotArgs prm;
+  BgConsts bg;
+  Tile tile;
+};
+
+// ---- step kernels (kernels_step.hip) --------------------------------------
+hipError_t launch_pass(const LatView& v, hipStream_t s);
+// Reduce the pass partials, finish stage (weight w) and, if has_next, begin
+// the next stage (weight w_next); eta += h when end_of_step.
+hipError_t launch_stage_finalize(const LatView& v, double w, double w_next, double h,
+                                 int has_next, int end_of_step, hipStream_t s);
+// Begin the first stage of an evolve call (pending drift + H1/H2 halves).
+hipError_t launch_begin(const LatView& v, double w, double h, hipStream_t s);
+
+// ---- diagnostics (kernels_diag.hip) ---------------------------------------
+// Sums at the synchronised state (per field: sum pi^2, sum G, sum (phi - s),
+// sum (phi - s)^2, sum phi D phi; then sum V) into sums_dev and the
+// observables into out_dev (device memory).  mode 0: observables only;
+// mode 1: also set p_a from the constraint H = 0 (expanding branch) and S2.
+hipError_t launch_energies(const LatView& v, double* sums_dev, sl_energies_t* out_dev, int mode,
+                           hipStream_t s);
+// S2 = sum pi^2 of the stored momenta into DevScalars.
+hipError_t launch_sum_pi2(const LatView& v, hipStream_t s);
+// phi_sync (FP64) and pi (FP64) of the current state into device staging
+// buffers (either may be null).
+hipError_t launch_export(const LatView& v, double* phi_out, double* pi_out, hipStream_t s);
+// Store FP64 staging arrays into buffer 0 in the storage precision and reset
+// the scalars: parity 0, no pending drift, eta = 0, the given a and p_a.
+hipError_t launch_import(const LatView& v, const double* phi_in, const double* pi_in, double a,
+                         double p_a, hipStream_t s);
+hipError_t launch_reset_scalars(const LatView& v, double a, double p_a, hipStream_t s);
+
+// ---- initial state and spectrum (kernels_init.hip) ------------------------
+hipError_t launch_fill_homogeneous(const LatView& v, const double* phi0, const double* pi0,
+                                   hipStream_t s);
+// Vacuum k-space amplitudes of one field into cbuf (complex FP64, n^3).
+hipError_t launch_vacuum_modes(const LatView& v, double2* cbuf, int field, double m2eff,
+                               double amp, uint64_t seed, hipStream_t s);
+// Twiddle table tw[m] = exp(sign 2 pi i m / n).
+hipError_t launch_twiddles(int n, int sign, double2* tw, hipStream_t s);
+// One 1-D DFT pass along axis (0 = x, 1 = y, 2 = z) with twiddle table tw.
+hipError_t launch_dft_axis(int n, const double2* in, double2* out, const double2* tw, int axis,
+                           hipStream_t s);
+// phi_field (buffer 0) = base + scale * Re(cbuf), rounded to storage precision.
+hipError_t launch_add_real(const LatView& v, const double2* cbuf, int field, double base,
+                           double scale, hipStream_t s);
+// White noise of one field: phi_field (buffer 0) = base + amp (g - mean g).
+hipError_t launch_white(const LatView& v, double* gbuf, double* mean_dev, int field, double base,
+                        double amp, uint64_t seed, hipStream_t s);
+// phi_sync of one field as the real part of cbuf.
+hipError_t launch_field_to_complex(const LatView& v, int field, double2* cbuf, hipStream_t s);
+// Workgroups used by the spectrum binning for side n.
+int spectrum_blocks(int n);
+// Shell sums of |F|^2 / n^6 of the transformed field; out3 = [k | P | count].
+hipError_t launch_spectrum_bins(int n, double L, const double2* cbuf, int nbins, double* part,
+                                double* out3, hipStream_t s);
+
+}  // namespace symlat

@@ -1,0 +1,375 @@
+// Observables and state exchange: lattice sums for eq. (2.16), (2.18),
+// (2.20), (3.1) at the synchronised state, the constraint solve for p_a, the
+// momentum sum S2, and FP64 export/import of the fields.
+
+#include "device.h"
+
+namespace symlat {
+
+namespace {
+
+constexpr int kDiagBlocksMax = 1024;
+
+struct Bufs {
+  const void* phi[2];
+  const void* pi[2];
+};
+
+Bufs bufs_of(const LatView& v) {
+  Bufs B;
+  for (int k = 0; k < 2; ++k) {
+    B.phi[k] = v.phi[k];
+    B.pi[k] = v.pi[k];
+  }
+  return B;
+}
+
+// Per-field sums then the potential: [pi^2, G, phi-s, (phi-s)^2, phi D phi] * NF, V
+template <int NF>
+constexpr int nsums() { return 5 * NF + 1; }
+
+template <typename T, int NF, int KIND>
+__global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScalars* sc,
+                                                         PotArgs prm, int n, double* partials) {
+  constexpr int NV = nsums<NF>();
+  __shared__ KSum scratch[4 * NV];
+  const int par = sc->parity;
+  const T* __restrict__ phi = static_cast<const T*>(B.phi[par]);
+  const T* __restrict__ pi = static_cast<const T*>(B.pi[par]);
+  const double c = sc->c_pend;
+  PotT<double> pot;
+#pragma unroll
+  for (int i = 0; i < kMaxFields; ++i) pot.p[i] = prm.p[i];
+  const size_t n2 = size_t(n) * n, n3 = n2 * n;
+
+  double shift[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) shift[i] = fma(c, double(pi[i * n3]), double(phi[i * n3]));
+
+  KSum acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = KSum{0.0, 0.0};
+
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n3; e += stride) {
+    const int x = int(e % n);
+    const int y = int((e / n) % n);
+    const int z = int(e / n2);
+    const size_t xm = e - x + (x == 0 ? n - 1 : x - 1), xp = e - x + (x == n - 1 ? 0 : x + 1);
+    const size_t ym = e + (size_t((y == 0 ? n - 1 : y - 1)) - y) * n;
+    const size_t yp = e + (size_t((y == n - 1 ? 0 : y + 1)) - y) * n;
+    const size_t zm = e + (size_t((z == 0 ? n - 1 : z - 1)) - z) * n2;
+    const size_t zp = e + (size_t((z == n - 1 ? 0 : z + 1)) - z) * n2;
+    double f[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const size_t o = i * n3;
+      const double pc = double(pi[o + e]);
+      const double fcv = fma(c, pc, double(phi[o + e]));
+      f[i] = fcv;
+      double nb[6];
+      const size_t idx[6] = {xm, xp, ym, yp, zm, zp};
+#pragma unroll
+      for (int q = 0; q < 6; ++q) nb[q] = fma(c, double(pi[o + idx[q]]), double(phi[o + idx[q]]));
+      double D = -6.0 * fcv, G = 0.0;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        D += nb[q];
+        const double d = nb[q] - fcv;
+        G += d * d;
+      }
+      kadd(acc[5 * i + 0], pc * pc);
+      kadd(acc[5 * i + 1], 0.5 * G);
+      const double ds = fcv - shift[i];
+      kadd(acc[5 * i + 2], ds);
+      kadd(acc[5 * i + 3], ds * ds);
+      kadd(acc[5 * i + 4], fcv * D);
+    }
+    double V, dV[NF];
+    potential<KIND, NF, double>(f, pot, V, dV);
+    kadd(acc[5 * NF], V);
+  }
+  block_reduce<NV>(acc, scratch);
+  if (threadIdx.x == 0) {
+    double* out = partials + size_t(blockIdx.x) * 2 * NV;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      out[2 * k] = acc[k].s;
+      out[2 * k + 1] = acc[k].c;
+    }
+  }
+}
+
+// Reduce energies partials, compute observables; mode 1 also solves the
+// constraint H = 0 for p_a (expanding branch) and sets S2.
+template <int NF>
+__global__ __launch_bounds__(kBlock) void energies_finalize(const double* partials, int nblocks,
+                                                           DevScalars* sc, BgConsts K, int n,
+                                                           Bufs B, int prec, double* sums_out,
+                                                           sl_energies_t* out, int mode) {
+  constexpr int NV = nsums<NF>();
+  __shared__ KSum scratch[4 * NV];
+  KSum v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = KSum{0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+    const double* p = partials + size_t(b) * 2 * NV;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = kcombine(v[k], KSum{p[2 * k], p[2 * k + 1]});
+  }
+  block_reduce<NV>(v, scratch);
+  if (threadIdx.x != 0) return;
+  DevScalars S = *sc;
+  double s[NV];
+  for (int k = 0; k < NV; ++k) {
+    s[k] = v[k].s + v[k].c;
+    sums_out[k] = s[k];
+  }
+  const size_t n3 = size_t(n) * n * n;
+  const double VL = K.VL;
+  const double a = S.a;
+  const double a2 = a * a, a4 = a2 * a2, a6 = a4 * a2;
+  sl_energies_t E;
+  for (int i = 0; i < 8; ++i) E.kin[i] = E.grad[i] = E.mean[i] = E.var[i] = 0.0;
+  double S2 = 0.0, SdD = 0.0, skin = 0.0, sgrad = 0.0;
+  const int par = S.parity;
+  for (int i = 0; i < NF; ++i) {
+    // shift used by the sum kernel: phi_sync at site 0
+    double sh;
+    if (prec == SL_FP32) {
+      const float* ph = static_cast<const float*>(B.phi[par]);
+      const float* pp = static_cast<const float*>(B.pi[par]);
+      sh = fma(S.c_pend, double(pp[i * n3]), double(ph[i * n3]));
+    } else {
+      const double* ph = static_cast<const double*>(B.phi[par]);
+      const double* pp = static_cast<const double*>(B.pi[par]);
+      sh = fma(S.c_pend, pp[i * n3], ph[i * n3]);
+    }
+    E.kin[i] = (s[5 * i] / VL) / (2.0 * a6);
+    E.grad[i] = (s[5 * i + 1] / VL) / (2.0 * a2 * K.dx2);
+    const double m1 = s[5 * i + 2] / VL;
+    E.mean[i] = sh + m1;
+    E.var[i] = s[5 * i + 3] / VL - m1 * m1;
+    S2 += s[5 * i];
+    SdD += s[5 * i + 4];
+    skin += E.kin[i];
+    sgrad += E.grad[i];
+  }
+  const double SV = s[5 * NF];
+  E.pot = SV / VL;
+  E.rho = skin + sgrad + E.pot;
+  E.pressure = skin - sgrad / 3.0 - E.pot;
+  E.w_eos = E.rho != 0.0 ? E.pressure / E.rho : __builtin_nan("");
+  // field part of eq. (2.20) plus the radiation and matter terms
+  const double Hf = S2 / (2.0 * a2) - a2 * SdD / (2.0 * K.dx2) + a4 * SV;
+  const double Hext = K.VL_rho_r + a * K.VL_rho_m;
+  if (mode == 1) {
+    S.S2 = S2;
+    if (K.expand) {
+      const double E0 = Hf + Hext;
+      if (E0 >= 0.0) {
+        S.p_a = -sqrt(12.0 * VL * K.mpl2 * E0);
+      } else {
+        S.p_a = __builtin_nan("");
+        S.status |= kStatusNonFinite;
+      }
+    } else {
+      S.p_a = 0.0;
+    }
+    *sc = S;
+  }
+  E.eta = S.eta;
+  E.a = a;
+  E.p_a = S.p_a;
+  if (K.expand) {
+    E.hubble = -S.p_a / (6.0 * VL * K.mpl2 * a2);
+    const double rho_tot = E.rho + (K.VL_rho_r / VL) / a4 + (K.VL_rho_m / VL) / (a2 * a);
+    E.friedmann_residual = fabs(rho_tot / (3.0 * K.mpl2 * E.hubble * E.hubble) - 1.0);
+    E.h_total = -S.p_a * S.p_a / (12.0 * VL * K.mpl2) + Hf + Hext;
+  } else {
+    E.hubble = 0.0;
+    E.friedmann_residual = __builtin_nan("");
+    E.h_total = Hf + Hext;
+  }
+  *out = E;
+}
+
+template <typename T, int NF, int KIND>
+hipError_t energies_t(const LatView& v, double* sums, sl_energies_t* out, int mode, hipStream_t s) {
+  const Bufs B = bufs_of(v);
+  const size_t n3 = size_t(v.n) * v.n * v.n;
+  int nb = int((n3 + kBlock - 1) / kBlock);
+  if (nb > kDiagBlocksMax) nb = kDiagBlocksMax;
+  hipLaunchKernelGGL((energies_kernel<T, NF, KIND>), dim3(nb), dim3(kBlock), 0, s, B, v.sc,
+                     v.prm, v.n, v.partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((energies_finalize<NF>), dim3(1), dim3(kBlock), 0, s, v.partials, nb, v.sc,
+                     v.bg, v.n, B, v.prec, sums, out, mode);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t energies_dispatch(const LatView& v, double* sums, sl_energies_t* out, int mode,
+                             hipStream_t s) {
+  switch (v.pot) {
+    case SL_POT_CHAOTIC2: return energies_t<T, 2, SL_POT_CHAOTIC2>(v, sums, out, mode, s);
+    case SL_POT_OSCILLON: return energies_t<T, 1, SL_POT_OSCILLON>(v, sums, out, mode, s);
+    case SL_POT_QBALL_LOG: return energies_t<T, 2, SL_POT_QBALL_LOG>(v, sums, out, mode, s);
+    default: break;
+  }
+  switch (v.nf) {
+    case 1: return energies_t<T, 1, SL_POT_FREE>(v, sums, out, mode, s);
+    case 2: return energies_t<T, 2, SL_POT_FREE>(v, sums, out, mode, s);
+    case 3: return energies_t<T, 3, SL_POT_FREE>(v, sums, out, mode, s);
+    case 4: return energies_t<T, 4, SL_POT_FREE>(v, sums, out, mode, s);
+    case 5: return energies_t<T, 5, SL_POT_FREE>(v, sums, out, mode, s);
+    case 6: return energies_t<T, 6, SL_POT_FREE>(v, sums, out, mode, s);
+    case 7: return energies_t<T, 7, SL_POT_FREE>(v, sums, out, mode, s);
+    case 8: return energies_t<T, 8, SL_POT_FREE>(v, sums, out, mode, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void sum_pi2_kernel(Bufs B, const DevScalars* sc,
+                                                        size_t count, double* partials) {
+  __shared__ KSum scratch[4];
+  const T* __restrict__ pi = static_cast<const T*>(B.pi[sc->parity]);
+  KSum acc[1] = {{0.0, 0.0}};
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += stride) {
+    const double p = double(pi[e]);
+    kadd(acc[0], p * p);
+  }
+  block_reduce<1>(acc, scratch);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = acc[0].s;
+    partials[2 * blockIdx.x + 1] = acc[0].c;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void sum_pi2_finalize(const double* partials, int nblocks,
+                                                          DevScalars* sc) {
+  __shared__ KSum scratch[4];
+  KSum v[1] = {{0.0, 0.0}};
+  for (int b = threadIdx.x; b < nblocks; b += kBlock)
+    v[0] = kcombine(v[0], KSum{partials[2 * b], partials[2 * b + 1]});
+  block_reduce<1>(v, scratch);
+  if (threadIdx.x == 0) {
+    const double S2 = v[0].s + v[0].c;
+    sc->S2 = S2;
+    if (!dev_finite(S2)) sc->status |= kStatusNonFinite;
+  }
+}
+
+template <typename T>
+__global__ void export_kernel(Bufs B, const DevScalars* sc, size_t count, double* phi_out,
+                              double* pi_out) {
+  const int par = sc->parity;
+  const T* __restrict__ phi = static_cast<const T*>(B.phi[par]);
+  const T* __restrict__ pi = static_cast<const T*>(B.pi[par]);
+  const double c = sc->c_pend;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += stride) {
+    const double p = double(pi[e]);
+    if (phi_out) phi_out[e] = fma(c, p, double(phi[e]));
+    if (pi_out) pi_out[e] = p;
+  }
+}
+
+template <typename T>
+__global__ void import_kernel(void* phi0, void* pi0, size_t count, const double* phi_in,
+                              const double* pi_in) {
+  T* __restrict__ phi = static_cast<T*>(phi0);
+  T* __restrict__ pi = static_cast<T*>(pi0);
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += stride) {
+    phi[e] = static_cast<T>(phi_in[e]);
+    pi[e] = static_cast<T>(pi_in[e]);
+  }
+}
+
+__global__ void reset_scalars_kernel(DevScalars* sc, double a, double p_a) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    DevScalars S;
+    S.a = a;
+    S.p_a = p_a;
+    S.eta = 0.0;
+    S.S2 = 0.0;
+    S.c_pend = 0.0;
+    S.c_next = 0.0;
+    S.alpha = 0.0;
+    S.beta = 0.0;
+    S.a_kick = a;
+    S.S3_last = 0.0;
+    S.parity = 0;
+    S.status = 0;
+    *sc = S;
+  }
+}
+
+int grid_for(size_t count) {
+  size_t nb = (count + kBlock - 1) / kBlock;
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  return int(nb);
+}
+
+}  // namespace
+
+hipError_t launch_energies(const LatView& v, double* sums, sl_energies_t* out, int mode,
+                           hipStream_t s) {
+  return v.prec == SL_FP32 ? energies_dispatch<float>(v, sums, out, mode, s)
+                           : energies_dispatch<double>(v, sums, out, mode, s);
+}
+
+hipError_t launch_sum_pi2(const LatView& v, hipStream_t s) {
+  const size_t count = size_t(v.nf) * v.n * v.n * v.n;
+  const int nb = grid_for(count) > kDiagBlocksMax ? kDiagBlocksMax : grid_for(count);
+  const Bufs B = bufs_of(v);
+  if (v.prec == SL_FP32)
+    hipLaunchKernelGGL(sum_pi2_kernel<float>, dim3(nb), dim3(kBlock), 0, s, B, v.sc, count,
+                       v.partials);
+  else
+    hipLaunchKernelGGL(sum_pi2_kernel<double>, dim3(nb), dim3(kBlock), 0, s, B, v.sc, count,
+                       v.partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum_pi2_finalize, dim3(1), dim3(kBlock), 0, s, v.partials, nb, v.sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_export(const LatView& v, double* phi_out, double* pi_out, hipStream_t s) {
+  const size_t count = size_t(v.nf) * v.n * v.n * v.n;
+  const Bufs B = bufs_of(v);
+  if (v.prec == SL_FP32)
+    hipLaunchKernelGGL(export_kernel<float>, dim3(grid_for(count)), dim3(kBlock), 0, s, B, v.sc,
+                       count, phi_out, pi_out);
+  else
+    hipLaunchKernelGGL(export_kernel<double>, dim3(grid_for(count)), dim3(kBlock), 0, s, B, v.sc,
+                       count, phi_out, pi_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_import(const LatView& v, const double* phi_in, const double* pi_in, double a,
+                         double p_a, hipStream_t s) {
+  const size_t count = size_t(v.nf) * v.n * v.n * v.n;
+  if (v.prec == SL_FP32)
+    hipLaunchKernelGGL(import_kernel<float>, dim3(grid_for(count)), dim3(kBlock), 0, s, v.phi[0],
+                       v.pi[0], count, phi_in, pi_in);
+  else
+    hipLaunchKernelGGL(import_kernel<double>, dim3(grid_for(count)), dim3(kBlock), 0, s, v.phi[0],
+                       v.pi[0], count, phi_in, pi_in);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reset_scalars_kernel, dim3(1), dim3(64), 0, s, v.sc, a, p_a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_scalars(const LatView& v, double a, double p_a, hipStream_t s) {
+  hipLaunchKernelGGL(reset_scalars_kernel, dim3(1), dim3(64), 0, s, v.sc, a, p_a);
+  return hipGetLastError();
+}
+
+}  // namespace symlat

@@ -1,0 +1,663 @@
+// Host runtime behind the C ABI of include/symlat.h: lattice handles, the
+// composition driver, argument validation, the stability pre-check and the
+// host<->device exchange.  Every lattice computation runs in the device
+// kernels; the host only validates, allocates, launches and copies.
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+
+using namespace symlat;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sl_status fail(sl_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(SL_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));              \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Composition weights (Sec. 2.3): second-order map (order 2), triple jump
+// eq. (2.43)-(2.44) (order 4), symmetric compositions of Table 1 (6, 8).
+// ---------------------------------------------------------------------------
+const double kTable1Order6[3] = {0.78451361047755726382, 0.23557321335935813368,
+                                 -1.17767998417887100695};
+const double kTable1Order8[7] = {0.74167036435061295345,  -0.40910082580003159400,
+                                 0.19075471029623837995,  -0.57386247111608226666,
+                                 0.29906418130365592384,  0.33462491824529818378,
+                                 0.31529309239676659663};
+
+std::vector<double> weights_for(int order) {
+  std::vector<double> w;
+  if (order == 2) {
+    w = {1.0};
+  } else if (order == 4) {
+    const double c = std::cbrt(2.0);
+    w = {1.0 / (2.0 - c), -c / (2.0 - c), 1.0 / (2.0 - c)};
+  } else if (order == 6 || order == 8) {
+    const double* t = order == 6 ? kTable1Order6 : kTable1Order8;
+    const int half = order == 6 ? 3 : 7;
+    double sum = 0.0;
+    for (int i = 0; i < half; ++i) sum += t[i];
+    for (int i = 0; i < half; ++i) w.push_back(t[i]);
+    w.push_back(1.0 - 2.0 * sum);
+    for (int i = half - 1; i >= 0; --i) w.push_back(t[i]);
+  }
+  return w;
+}
+
+// Largest stable omega*h of the composition on a harmonic mode (scanned at
+// 1e-4 resolution and rounded down).
+double stability_limit_for(int order) {
+  switch (order) {
+    case 2: return 2.0;
+    case 4: return 1.5734;
+    case 6: return 2.2690;
+    case 8: return 3.3932;
+    default: return -1.0;
+  }
+}
+
+// d^2 V / d phi_i^2 at a homogeneous point; false where undefined.
+bool hessian_diag(int kind, int nf, const double* p, const double* f, double* out) {
+  switch (kind) {
+    case SL_POT_FREE:
+      for (int i = 0; i < nf; ++i) out[i] = p[i];
+      return true;
+    case SL_POT_CHAOTIC2:
+      out[0] = p[0] + p[1] * f[1] * f[1];
+      out[1] = p[1] * f[0] * f[0];
+      return true;
+    case SL_POT_OSCILLON:
+      out[0] = p[0] - 3.0 * p[1] * f[0] * f[0] + 5.0 * p[2] * f[0] * f[0] * f[0] * f[0];
+      return true;
+    case SL_POT_QBALL_LOG: {
+      const double u = 0.5 * (f[0] * f[0] + f[1] * f[1]);
+      if (!(u > 0.0)) return false;
+      const double base = p[0] * (1.0 + p[1] + p[1] * std::log(u / p[2]));
+      out[0] = base + p[0] * p[1] * f[0] * f[0] / u;
+      out[1] = base + p[0] * p[1] * f[1] * f[1] / u;
+      return true;
+    }
+    default: return false;
+  }
+}
+
+int nparams_for(int kind, int nf) {
+  switch (kind) {
+    case SL_POT_FREE: return nf;
+    case SL_POT_CHAOTIC2: return 2;
+    case SL_POT_OSCILLON: return 3;
+    case SL_POT_QBALL_LOG: return 3;
+    default: return -1;
+  }
+}
+
+int nfields_for(int kind) {
+  switch (kind) {
+    case SL_POT_CHAOTIC2: return 2;
+    case SL_POT_OSCILLON: return 1;
+    case SL_POT_QBALL_LOG: return 2;
+    default: return 0;  // any
+  }
+}
+
+bool config_ok(const sl_config* c, std::string* why) {
+  if (!c) { *why = "config is NULL"; return false; }
+  if (c->n < 4 || c->n > 1024) { *why = "n must be in [4, 1024]"; return false; }
+  if (c->nfields < 1 || c->nfields > kMaxFields) { *why = "nfields must be in [1, 8]"; return false; }
+  if (!(c->L > 0.0) || !std::isfinite(c->L)) { *why = "L must be finite and > 0"; return false; }
+  if (c->precision != SL_FP64 && c->precision != SL_FP32) { *why = "unknown precision"; return false; }
+  if (c->expansion != SL_EXPAND_NONE && c->expansion != SL_EXPAND_SELF) {
+    *why = "unknown expansion mode";
+    return false;
+  }
+  if (!(c->mpl > 0.0) || !std::isfinite(c->mpl)) { *why = "mpl must be finite and > 0"; return false; }
+  if (!(c->a0 > 0.0) || !std::isfinite(c->a0)) { *why = "a0 must be finite and > 0"; return false; }
+  if (!std::isfinite(c->rho_rad0) || !std::isfinite(c->rho_mat0) || c->rho_rad0 < 0 ||
+      c->rho_mat0 < 0) {
+    *why = "rho_rad0 and rho_mat0 must be finite and >= 0";
+    return false;
+  }
+  return true;
+}
+
+// Default launch shape of the fused pass for side n.
+Tile make_tile(int n, int tx, int tz) {
+  Tile t;
+  if (tx <= 0) tx = n >= 64 ? 64 : (n >= 32 ? 32 : 16);
+  t.tx = tx;
+  t.logtx = tx == 64 ? 6 : (tx == 32 ? 5 : 4);
+  t.ty = kBlock / tx;
+  t.ntx = (n + t.tx - 1) / t.tx;
+  t.nty = (n + t.ty - 1) / t.ty;
+  if (tz <= 0) {
+    // enough z-chunks for >= ~2048 workgroups, chunks no shorter than 8 planes
+    const long long xy = (long long)t.ntx * t.nty;
+    long long chunks = (2048 + xy - 1) / xy;
+    long long len = (n + chunks - 1) / chunks;
+    if (len < 8) len = 8;
+    if (len > n) len = n;
+    tz = int(len);
+  }
+  t.tz = tz > n ? n : tz;
+  t.ntz = (n + t.tz - 1) / t.tz;
+  return t;
+}
+
+size_t partial_doubles(const Tile& t) {
+  size_t need = size_t(t.nblocks()) * 6;
+  const size_t diag = size_t(4096) * 2 * (5 * kMaxFields + 1);
+  return need > diag ? need : diag;
+}
+
+}  // namespace
+
+struct sl_lattice {
+  sl_config cfg{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  LatView v{};
+  size_t n3 = 0;
+  size_t elem = 8;
+  size_t partials_n = 0;
+  bool pot_set = false;
+  bool state_set = false;
+  int pot_kind = -1;
+  double pot_raw[kMaxFields] = {0};
+  double hom[kMaxFields] = {0};
+  double m2max = 0.0;
+  double a_host = 1.0;
+  double* sums_dev = nullptr;
+  sl_energies_t* energies_dev = nullptr;
+  double* spec_dev = nullptr;
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+};
+
+namespace {
+
+sl_status read_scalars(sl_lattice* L, DevScalars* S) {
+  HIP_TRY(hipMemcpyAsync(S, L->v.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, L->stream));
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  if (std::isfinite(S->a)) L->a_host = S->a;
+  if (S->status & kStatusNonFinite)
+    return fail(SL_E_NONFINITE, "a lattice sum or the background became non-finite");
+  return SL_OK;
+}
+
+sl_status require_state(sl_lattice* L) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  if (!L->pot_set) return fail(SL_E_STATE, "no potential set");
+  if (!L->state_set) return fail(SL_E_STATE, "no initial state (call sl_init_fluctuations or sl_set_fields)");
+  return SL_OK;
+}
+
+void refresh_m2max(sl_lattice* L) {
+  double d2[kMaxFields];
+  L->m2max = 0.0;
+  if (hessian_diag(L->pot_kind, L->cfg.nfields, L->pot_raw, L->hom, d2)) {
+    for (int i = 0; i < L->cfg.nfields; ++i)
+      if (d2[i] > L->m2max) L->m2max = d2[i];
+  }
+}
+
+void free_all(sl_lattice* L) {
+  for (int k = 0; k < 2; ++k) {
+    if (L->v.phi[k]) (void)hipFree(L->v.phi[k]);
+    if (L->v.pi[k]) (void)hipFree(L->v.pi[k]);
+  }
+  if (L->v.sc) (void)hipFree(L->v.sc);
+  if (L->v.partials) (void)hipFree(L->v.partials);
+  if (L->sums_dev) (void)hipFree(L->sums_dev);
+  if (L->energies_dev) (void)hipFree(L->energies_dev);
+  if (L->spec_dev) (void)hipFree(L->spec_dev);
+  for (auto& e : L->events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
+}
+
+// Complex scratch for the transforms: two n^3 arrays and a twiddle table.
+struct FftScratch {
+  double2* a = nullptr;
+  double2* b = nullptr;
+  double2* tw = nullptr;
+  ~FftScratch() {
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (tw) (void)hipFree(tw);
+  }
+};
+
+sl_status fft_alloc(sl_lattice* L, FftScratch& S) {
+  const size_t bytes = L->n3 * sizeof(double2);
+  if (hipMalloc(&S.a, bytes) != hipSuccess || hipMalloc(&S.b, bytes) != hipSuccess ||
+      hipMalloc(&S.tw, size_t(L->cfg.n) * sizeof(double2)) != hipSuccess)
+    return fail(SL_E_NOMEM, "cannot allocate transform scratch (%zu bytes)", 2 * bytes);
+  return SL_OK;
+}
+
+// 3-D DFT a -> b (a is clobbered); sign +1: sum f_n exp(+2 pi i n.j/N).
+sl_status dft3(sl_lattice* L, FftScratch& S, int sign) {
+  const int n = L->cfg.n;
+  HIP_TRY(launch_twiddles(n, sign, S.tw, L->stream));
+  HIP_TRY(launch_dft_axis(n, S.a, S.b, S.tw, 0, L->stream));
+  HIP_TRY(launch_dft_axis(n, S.b, S.a, S.tw, 1, L->stream));
+  HIP_TRY(launch_dft_axis(n, S.a, S.b, S.tw, 2, L->stream));
+  return SL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sl_last_error(void) { return g_last_error.c_str(); }
+
+int32_t sl_composition_weights(int32_t order, double* w_out, int32_t cap) {
+  const std::vector<double> w = weights_for(order);
+  if (w.empty() || !w_out || cap < int32_t(w.size())) return -1;
+  for (size_t i = 0; i < w.size(); ++i) w_out[i] = w[i];
+  return int32_t(w.size());
+}
+
+double sl_stability_limit(int32_t order) { return stability_limit_for(order); }
+
+size_t sl_footprint_bytes(const sl_config* cfg) {
+  std::string why;
+  if (!config_ok(cfg, &why)) return 0;
+  const size_t n3 = size_t(cfg->n) * cfg->n * cfg->n;
+  const size_t elem = cfg->precision == SL_FP32 ? 4 : 8;
+  const Tile t = make_tile(cfg->n, 0, 0);
+  return 4 * n3 * cfg->nfields * elem + partial_doubles(t) * sizeof(double) + sizeof(DevScalars) +
+         sizeof(double) * (5 * kMaxFields + 1) + sizeof(sl_energies_t) +
+         sizeof(double) * 3 * kMaxBins;
+}
+
+sl_status sl_lattice_create(const sl_config* cfg, void* hip_stream, sl_lattice** out) {
+  if (!out) return fail(SL_E_INVALID, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (!config_ok(cfg, &why)) return fail(SL_E_INVALID, "invalid config: %s", why.c_str());
+  sl_lattice* L = new (std::nothrow) sl_lattice();
+  if (!L) return fail(SL_E_NOMEM, "host allocation failed");
+  L->cfg = *cfg;
+  L->n3 = size_t(cfg->n) * cfg->n * cfg->n;
+  L->elem = cfg->precision == SL_FP32 ? 4 : 8;
+  if (hipGetDevice(&L->device) != hipSuccess) {
+    delete L;
+    return fail(SL_E_DEVICE, "no HIP device");
+  }
+  if (hip_stream) {
+    L->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete L;
+      return fail(SL_E_DEVICE, "cannot create a HIP stream");
+    }
+    L->own_stream = true;
+  }
+  LatView& v = L->v;
+  v.n = cfg->n;
+  v.nf = cfg->nfields;
+  v.prec = cfg->precision;
+  v.pot = -1;
+  const double dx = cfg->L / cfg->n;
+  const double VL = double(L->n3);
+  v.bg.inv_dx2 = 1.0 / (dx * dx);
+  v.bg.dx2 = dx * dx;
+  v.bg.VL = VL;
+  v.bg.inv6VLm2 = 1.0 / (6.0 * VL * cfg->mpl * cfg->mpl);
+  v.bg.VL_rho_m = VL * cfg->rho_mat0;
+  v.bg.VL_rho_r = VL * cfg->rho_rad0;
+  v.bg.mpl2 = cfg->mpl * cfg->mpl;
+  v.bg.L = cfg->L;
+  v.bg.expand = cfg->expansion == SL_EXPAND_SELF ? 1 : 0;
+  v.tile = make_tile(cfg->n, 0, 0);
+  L->partials_n = partial_doubles(v.tile);
+  L->a_host = cfg->a0;
+
+  const size_t fbytes = L->n3 * cfg->nfields * L->elem;
+  bool ok = true;
+  for (int k = 0; k < 2 && ok; ++k) {
+    ok = ok && hipMalloc(&v.phi[k], fbytes) == hipSuccess;
+    ok = ok && hipMalloc(&v.pi[k], fbytes) == hipSuccess;
+  }
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&v.sc), sizeof(DevScalars)) == hipSuccess;
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&v.partials), L->partials_n * sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&L->sums_dev), sizeof(double) * (5 * kMaxFields + 1)) == hipSuccess;
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&L->energies_dev), sizeof(sl_energies_t)) == hipSuccess;
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&L->spec_dev), sizeof(double) * 3 * kMaxBins) == hipSuccess;
+  if (!ok) {
+    free_all(L);
+    delete L;
+    return fail(SL_E_NOMEM, "device allocation of %zu bytes failed", sl_footprint_bytes(cfg));
+  }
+  for (int k = 0; k < 2; ++k) {
+    (void)hipMemsetAsync(v.phi[k], 0, fbytes, L->stream);
+    (void)hipMemsetAsync(v.pi[k], 0, fbytes, L->stream);
+  }
+  if (launch_reset_scalars(v, cfg->a0, 0.0, L->stream) != hipSuccess ||
+      hipStreamSynchronize(L->stream) != hipSuccess) {
+    free_all(L);
+    delete L;
+    return fail(SL_E_DEVICE, "device initialisation failed");
+  }
+  *out = L;
+  return SL_OK;
+}
+
+sl_status sl_lattice_destroy(sl_lattice* L) {
+  if (!L) return SL_OK;
+  (void)hipStreamSynchronize(L->stream);
+  free_all(L);
+  delete L;
+  return SL_OK;
+}
+
+sl_status sl_set_potential(sl_lattice* L, int32_t kind, const double* params, int32_t nparams) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  const int nf = L->cfg.nfields;
+  const int want = nparams_for(kind, nf);
+  if (want < 0) return fail(SL_E_INVALID, "unknown potential kind %d", kind);
+  const int nfk = nfields_for(kind);
+  if (nfk && nfk != nf)
+    return fail(SL_E_INVALID, "potential %d needs %d fields, lattice has %d", kind, nfk, nf);
+  if (nparams != want) return fail(SL_E_INVALID, "potential %d needs %d parameters, got %d", kind, want, nparams);
+  if (!params) return fail(SL_E_INVALID, "params is NULL");
+  for (int i = 0; i < nparams; ++i)
+    if (!std::isfinite(params[i])) return fail(SL_E_INVALID, "parameter %d is not finite", i);
+  if (kind == SL_POT_QBALL_LOG && !(params[2] > 0.0)) return fail(SL_E_INVALID, "M^2 must be > 0");
+  PotArgs dev{};
+  for (int i = 0; i < nparams; ++i) {
+    L->pot_raw[i] = params[i];
+    dev.p[i] = params[i];
+  }
+  if (kind == SL_POT_QBALL_LOG) dev.p[2] = 1.0 / params[2];
+  L->v.prm = dev;
+  L->v.pot = kind;
+  L->pot_kind = kind;
+  L->pot_set = true;
+  refresh_m2max(L);
+  return SL_OK;
+}
+
+sl_status sl_init_fluctuations(sl_lattice* L, const double* phi0, const double* pi0, int32_t kind,
+                               double amplitude, uint64_t seed) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  if (!L->pot_set) return fail(SL_E_STATE, "no potential set");
+  if (!phi0 || !pi0) return fail(SL_E_INVALID, "phi0/pi0 is NULL");
+  const int nf = L->cfg.nfields;
+  for (int i = 0; i < nf; ++i)
+    if (!std::isfinite(phi0[i]) || !std::isfinite(pi0[i]))
+      return fail(SL_E_INVALID, "homogeneous values must be finite");
+  if (kind != SL_FLUCT_NONE && kind != SL_FLUCT_VACUUM && kind != SL_FLUCT_WHITE)
+    return fail(SL_E_INVALID, "unknown fluctuation kind %d", kind);
+  if (!(amplitude >= 0.0) || !std::isfinite(amplitude))
+    return fail(SL_E_INVALID, "amplitude must be finite and >= 0");
+  double m2eff[kMaxFields];
+  if (kind == SL_FLUCT_VACUUM && !hessian_diag(L->pot_kind, nf, L->pot_raw, phi0, m2eff))
+    return fail(SL_E_INVALID, "effective mass undefined at the homogeneous point");
+
+  HIP_TRY(launch_reset_scalars(L->v, L->cfg.a0, 0.0, L->stream));
+  HIP_TRY(launch_fill_homogeneous(L->v, phi0, pi0, L->stream));
+  if (kind == SL_FLUCT_VACUUM) {
+    FftScratch S;
+    sl_status st = fft_alloc(L, S);
+    if (st != SL_OK) return st;
+    for (int i = 0; i < nf; ++i) {
+      HIP_TRY(launch_vacuum_modes(L->v, S.a, i, m2eff[i], amplitude, seed, L->stream));
+      st = dft3(L, S, +1);
+      if (st != SL_OK) return st;
+      HIP_TRY(launch_add_real(L->v, S.b, i, phi0[i], 1.0, L->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(L->stream));
+  } else if (kind == SL_FLUCT_WHITE) {
+    double* g = nullptr;
+    double* mean = nullptr;
+    if (hipMalloc(&g, L->n3 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&mean, sizeof(double)) != hipSuccess) {
+      if (g) (void)hipFree(g);
+      return fail(SL_E_NOMEM, "cannot allocate white-noise scratch");
+    }
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < nf && e == hipSuccess; ++i)
+      e = launch_white(L->v, g, mean, i, phi0[i], amplitude, seed, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    (void)hipFree(g);
+    (void)hipFree(mean);
+    if (e != hipSuccess) return fail(SL_E_DEVICE, "white-noise initialisation: %s", hipGetErrorString(e));
+  }
+  HIP_TRY(launch_energies(L->v, L->sums_dev, L->energies_dev, 1, L->stream));
+  for (int i = 0; i < nf; ++i) L->hom[i] = phi0[i];
+  refresh_m2max(L);
+  DevScalars S;
+  sl_status st = read_scalars(L, &S);
+  if (st == SL_E_NONFINITE) return fail(SL_E_STATE, "constraint H = 0 has no real p_a for this state");
+  if (st != SL_OK) return st;
+  L->state_set = true;
+  return SL_OK;
+}
+
+sl_status sl_set_fields(sl_lattice* L, const double* phi, const double* pi, double a, double p_a) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  if (!L->pot_set) return fail(SL_E_STATE, "no potential set");
+  if (!phi || !pi) return fail(SL_E_INVALID, "phi/pi is NULL");
+  if (!(a > 0.0) || !std::isfinite(a)) return fail(SL_E_INVALID, "a must be finite and > 0");
+  if (std::isinf(p_a)) return fail(SL_E_INVALID, "p_a must be finite or NaN");
+  const size_t count = L->n3 * L->cfg.nfields;
+  double* stage = nullptr;
+  if (hipMalloc(&stage, 2 * count * sizeof(double)) != hipSuccess)
+    return fail(SL_E_NOMEM, "cannot allocate staging buffers");
+  hipError_t e = hipMemcpyAsync(stage, phi, count * sizeof(double), hipMemcpyHostToDevice, L->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(stage + count, pi, count * sizeof(double), hipMemcpyHostToDevice, L->stream);
+  const bool solve = std::isnan(p_a);
+  if (e == hipSuccess) e = launch_import(L->v, stage, stage + count, a, solve ? 0.0 : p_a, L->stream);
+  if (e == hipSuccess) e = launch_sum_pi2(L->v, L->stream);
+  if (e == hipSuccess && solve) e = launch_energies(L->v, L->sums_dev, L->energies_dev, 1, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  (void)hipFree(stage);
+  if (e != hipSuccess) return fail(SL_E_DEVICE, "set_fields: %s", hipGetErrorString(e));
+  for (int i = 0; i < L->cfg.nfields; ++i) L->hom[i] = phi[i * L->n3];
+  refresh_m2max(L);
+  DevScalars S;
+  sl_status st = read_scalars(L, &S);
+  if (st != SL_OK) {
+    L->state_set = false;
+    return st == SL_E_NONFINITE ? fail(SL_E_NONFINITE, "state is non-finite or the constraint has no real p_a")
+                                : st;
+  }
+  L->state_set = true;
+  return SL_OK;
+}
+
+sl_status sl_evolve(sl_lattice* L, int64_t steps, double dt, int32_t order) {
+  sl_status st = require_state(L);
+  if (st != SL_OK) return st;
+  if (steps < 0) return fail(SL_E_INVALID, "steps must be >= 0");
+  if (!std::isfinite(dt)) return fail(SL_E_INVALID, "dt must be finite");
+  const std::vector<double> w = weights_for(order);
+  if (w.empty()) return fail(SL_E_INVALID, "order must be 2, 4, 6 or 8 (got %d)", order);
+  const double dx = L->cfg.L / L->cfg.n;
+  const double omax = std::sqrt(12.0 / (dx * dx) + L->a_host * L->a_host * L->m2max);
+  const double lim = stability_limit_for(order);
+  if (omax * std::fabs(dt) > lim)
+    return fail(SL_E_UNSTABLE, "omega_max*|dt| = %.4f exceeds the order-%d stability limit %.4f",
+                omax * std::fabs(dt), order, lim);
+  if (steps == 0) return SL_OK;
+  const int s = int(w.size());
+  HIP_TRY(launch_begin(L->v, w[0], dt, L->stream));
+  for (int64_t step = 0; step < steps; ++step) {
+    for (int j = 0; j < s; ++j) {
+      const bool last_stage = j == s - 1;
+      const int has_next = !(last_stage && step == steps - 1);
+      const double wn = last_stage ? w[0] : w[j + 1];
+      if (L->timing) {
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, L->stream));
+        HIP_TRY(launch_pass(L->v, L->stream));
+        HIP_TRY(hipEventRecord(e1, L->stream));
+        L->events.emplace_back(e0, e1);
+      } else {
+        HIP_TRY(launch_pass(L->v, L->stream));
+      }
+      HIP_TRY(launch_stage_finalize(L->v, w[j], wn, dt, has_next, last_stage ? 1 : 0, L->stream));
+    }
+  }
+  return SL_OK;
+}
+
+sl_status sl_synchronize(sl_lattice* L) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  DevScalars S;
+  return read_scalars(L, &S);
+}
+
+sl_status sl_get_background(sl_lattice* L, double* eta, double* a, double* p_a) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  DevScalars S;
+  sl_status st = read_scalars(L, &S);
+  if (eta) *eta = S.eta;
+  if (a) *a = S.a;
+  if (p_a) *p_a = S.p_a;
+  return st;
+}
+
+sl_status sl_energies(sl_lattice* L, sl_energies_t* out) {
+  sl_status st = require_state(L);
+  if (st != SL_OK) return st;
+  if (!out) return fail(SL_E_INVALID, "out is NULL");
+  HIP_TRY(launch_energies(L->v, L->sums_dev, L->energies_dev, 0, L->stream));
+  HIP_TRY(hipMemcpyAsync(out, L->energies_dev, sizeof(sl_energies_t), hipMemcpyDeviceToHost, L->stream));
+  DevScalars S;
+  return read_scalars(L, &S);
+}
+
+sl_status sl_get_fields(sl_lattice* L, double* phi_out, double* pi_out) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  if (!phi_out && !pi_out) return SL_OK;
+  const size_t count = L->n3 * L->cfg.nfields;
+  double* stage = nullptr;
+  if (hipMalloc(&stage, 2 * count * sizeof(double)) != hipSuccess)
+    return fail(SL_E_NOMEM, "cannot allocate staging buffers");
+  hipError_t e = launch_export(L->v, phi_out ? stage : nullptr, pi_out ? stage + count : nullptr, L->stream);
+  if (e == hipSuccess && phi_out)
+    e = hipMemcpyAsync(phi_out, stage, count * sizeof(double), hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess && pi_out)
+    e = hipMemcpyAsync(pi_out, stage + count, count * sizeof(double), hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  (void)hipFree(stage);
+  if (e != hipSuccess) return fail(SL_E_DEVICE, "get_fields: %s", hipGetErrorString(e));
+  DevScalars S;
+  return read_scalars(L, &S);
+}
+
+sl_status sl_spectrum(sl_lattice* L, int32_t field, int32_t nbins, double* k_out, double* p_out,
+                      int64_t* count_out) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  if (field < 0 || field >= L->cfg.nfields) return fail(SL_E_INVALID, "field index out of range");
+  if (nbins < 1 || nbins > kMaxBins) return fail(SL_E_INVALID, "nbins must be in [1, %d]", kMaxBins);
+  if (!k_out || !p_out || !count_out) return fail(SL_E_INVALID, "output array is NULL");
+  FftScratch S;
+  sl_status st = fft_alloc(L, S);
+  if (st != SL_OK) return st;
+  const int nb = spectrum_blocks(L->cfg.n);
+  double* part = nullptr;
+  if (hipMalloc(&part, size_t(nb) * 3 * nbins * sizeof(double)) != hipSuccess)
+    return fail(SL_E_NOMEM, "cannot allocate spectrum partials");
+  std::vector<double> host(size_t(3) * nbins);
+  hipError_t e = launch_field_to_complex(L->v, field, S.a, L->stream);
+  if (e == hipSuccess) {
+    st = dft3(L, S, -1);
+    if (st != SL_OK) {
+      (void)hipFree(part);
+      return st;
+    }
+    e = launch_spectrum_bins(L->cfg.n, L->cfg.L, S.b, nbins, part, L->spec_dev, L->stream);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host.data(), L->spec_dev, host.size() * sizeof(double), hipMemcpyDeviceToHost,
+                       L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  (void)hipFree(part);
+  if (e != hipSuccess) return fail(SL_E_DEVICE, "spectrum: %s", hipGetErrorString(e));
+  for (int b = 0; b < nbins; ++b) {
+    k_out[b] = host[b];
+    p_out[b] = host[nbins + b];
+    count_out[b] = int64_t(host[2 * nbins + b]);
+  }
+  DevScalars Sc;
+  return read_scalars(L, &Sc);
+}
+
+sl_status sl_set_kernel_timing(sl_lattice* L, int32_t enable) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  L->timing = enable != 0;
+  return SL_OK;
+}
+
+sl_status sl_kernel_timing(sl_lattice* L, int64_t* passes, double* total_ms) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  double total = 0.0;
+  for (auto& e : L->events) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
+    total += ms;
+  }
+  if (passes) *passes = int64_t(L->events.size());
+  if (total_ms) *total_ms = total;
+  for (auto& e : L->events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  L->events.clear();
+  return SL_OK;
+}
+
+sl_status sl_get_tile(sl_lattice* L, int32_t* tx, int32_t* ty, int32_t* tz) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  if (tx) *tx = L->v.tile.tx;
+  if (ty) *ty = L->v.tile.ty;
+  if (tz) *tz = L->v.tile.tz;
+  return SL_OK;
+}
+
+sl_status sl_set_tile(sl_lattice* L, int32_t tx, int32_t tz) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  if (tx != 16 && tx != 32 && tx != 64) return fail(SL_E_INVALID, "tx must be 16, 32 or 64");
+  if (tz < 0 || tz > L->cfg.n) return fail(SL_E_INVALID, "tz must be in [0, n]");
+  const Tile t = make_tile(L->cfg.n, tx, tz);
+  if (size_t(t.nblocks()) * 6 > L->partials_n)
+    return fail(SL_E_INVALID, "tile gives too many workgroups for the partial-sum buffer");
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  L->v.tile = t;
+  return SL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,249 @@
+"""ctypes binding of libsymlat (include/symlat.h).
+
+Argument marshalling only: every lattice computation runs in the HIP
+kernels of the library.  Loading fails loudly if the built library is
+missing; there is no fallback.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsymlat.so")
+
+SL_OK, SL_E_INVALID, SL_E_NOMEM, SL_E_DEVICE, SL_E_STATE, SL_E_NONFINITE, SL_E_UNSTABLE = range(7)
+STATUS_NAMES = {0: "SL_OK", 1: "SL_E_INVALID", 2: "SL_E_NOMEM", 3: "SL_E_DEVICE",
+                4: "SL_E_STATE", 5: "SL_E_NONFINITE", 6: "SL_E_UNSTABLE"}
+PRECISION = {"f64": 0, "f32": 1}
+POTENTIAL = {"free": 0, "chaotic2": 1, "oscillon": 2, "qball": 3}
+FLUCT = {"none": 0, "vacuum": 1, "white": 2}
+
+#: every symbol the header declares (checked by the CPU test suite)
+EXPORTS = (
+    "sl_lattice_create", "sl_lattice_destroy", "sl_set_potential",
+    "sl_init_fluctuations", "sl_evolve", "sl_energies", "sl_spectrum",
+    "sl_get_fields", "sl_set_fields", "sl_get_background", "sl_synchronize",
+    "sl_footprint_bytes", "sl_last_error", "sl_composition_weights",
+    "sl_stability_limit", "sl_set_kernel_timing", "sl_kernel_timing",
+    "sl_get_tile", "sl_set_tile",
+)
+
+
+class SymlatError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nfields", ctypes.c_int32), ("L", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("expansion", ctypes.c_int32),
+                ("mpl", ctypes.c_double), ("a0", ctypes.c_double),
+                ("rho_rad0", ctypes.c_double), ("rho_mat0", ctypes.c_double)]
+
+
+class Energies(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("eta", "a", "p_a", "hubble", "rho", "pressure", "w_eos",
+                 "friedmann_residual", "h_total", "pot")] + \
+               [(k, ctypes.c_double * 8) for k in ("kin", "grad", "mean", "var")]
+
+
+_lib = None
+
+
+def load():
+    """Load libsymlat.so from the package directory (raises if missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libsymlat.so is not built: run paper_1201_5029_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, D, I32, I64, U64 = (ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
+                           ctypes.c_int64, ctypes.c_uint64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "sl_lattice_create": (I32, [ctypes.POINTER(Config), P, ctypes.POINTER(P)]),
+        "sl_lattice_destroy": (I32, [P]),
+        "sl_set_potential": (I32, [P, I32, dp, I32]),
+        "sl_init_fluctuations": (I32, [P, dp, dp, I32, D, U64]),
+        "sl_evolve": (I32, [P, I64, D, I32]),
+        "sl_energies": (I32, [P, ctypes.POINTER(Energies)]),
+        "sl_spectrum": (I32, [P, I32, I32, dp, dp, ctypes.POINTER(ctypes.c_int64)]),
+        "sl_get_fields": (I32, [P, P, P]),
+        "sl_set_fields": (I32, [P, P, P, D, D]),
+        "sl_get_background": (I32, [P, dp, dp, dp]),
+        "sl_synchronize": (I32, [P]),
+        "sl_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(Config)]),
+        "sl_last_error": (ctypes.c_char_p, []),
+        "sl_composition_weights": (I32, [I32, dp, I32]),
+        "sl_stability_limit": (D, [I32]),
+        "sl_set_kernel_timing": (I32, [P, I32]),
+        "sl_kernel_timing": (I32, [P, ctypes.POINTER(I64), dp]),
+        "sl_get_tile": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "sl_set_tile": (I32, [P, I32, I32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != SL_OK:
+        msg = load().sl_last_error()
+        raise SymlatError(status, msg.decode() if msg else "")
+
+
+def _dvec(values, n):
+    arr = (ctypes.c_double * max(n, 1))()
+    for i, v in enumerate(values):
+        arr[i] = float(v)
+    return arr
+
+
+def make_config(n, nfields, L, precision="f64", expand=True, mpl=1.0, a0=1.0,
+                rho_rad0=0.0, rho_mat0=0.0):
+    return Config(int(n), int(nfields), float(L), PRECISION[precision],
+                  1 if expand else 0, float(mpl), float(a0), float(rho_rad0),
+                  float(rho_mat0))
+
+
+def composition_weights(order):
+    lib = load()
+    buf = (ctypes.c_double * 32)()
+    s = lib.sl_composition_weights(int(order), buf, 32)
+    if s < 0:
+        raise SymlatError(SL_E_INVALID, "unknown order %r" % order)
+    return [buf[i] for i in range(s)]
+
+
+def stability_limit(order):
+    return load().sl_stability_limit(int(order))
+
+
+def footprint_bytes(**cfg):
+    return int(load().sl_footprint_bytes(ctypes.byref(make_config(**cfg))))
+
+
+class Lattice:
+    """One lattice handle.  ``stream`` is an optional hipStream_t (int)."""
+
+    def __init__(self, n, nfields, L, precision="f64", expand=True, mpl=1.0, a0=1.0,
+                 rho_rad0=0.0, rho_mat0=0.0, stream=None):
+        self._lib = load()
+        self.n, self.nfields, self.L = int(n), int(nfields), float(L)
+        self.precision = precision
+        self.cfg = make_config(n, nfields, L, precision, expand, mpl, a0, rho_rad0, rho_mat0)
+        h = ctypes.c_void_p()
+        _check(self._lib.sl_lattice_create(ctypes.byref(self.cfg),
+                                           ctypes.c_void_p(stream or 0), ctypes.byref(h)))
+        self._h = h
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.sl_lattice_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- model and state --------------------------------------------------
+    def set_potential(self, kind, params):
+        params = list(params)
+        _check(self._lib.sl_set_potential(self._h, POTENTIAL[kind], _dvec(params, len(params)),
+                                          len(params)))
+
+    def init_fluctuations(self, phi0, pi0, kind="vacuum", amplitude=0.0, seed=0):
+        _check(self._lib.sl_init_fluctuations(
+            self._h, _dvec(phi0, self.nfields), _dvec(pi0, self.nfields), FLUCT[kind],
+            float(amplitude), ctypes.c_uint64(int(seed) & (2 ** 64 - 1))))
+
+    def set_fields(self, phi, pi, a=1.0, p_a=math.nan):
+        shape = (self.nfields, self.n, self.n, self.n)
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(shape)
+        pi = np.ascontiguousarray(pi, dtype=np.float64).reshape(shape)
+        _check(self._lib.sl_set_fields(self._h, phi.ctypes.data, pi.ctypes.data,
+                                       float(a), float(p_a)))
+
+    def get_fields(self):
+        shape = (self.nfields, self.n, self.n, self.n)
+        phi = np.empty(shape, dtype=np.float64)
+        pi = np.empty(shape, dtype=np.float64)
+        _check(self._lib.sl_get_fields(self._h, phi.ctypes.data, pi.ctypes.data))
+        return phi, pi
+
+    def background(self):
+        eta, a, pa = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.sl_get_background(self._h, ctypes.byref(eta), ctypes.byref(a),
+                                           ctypes.byref(pa)))
+        return eta.value, a.value, pa.value
+
+    # -- evolution and observables ------------------------------------------
+    def evolve(self, steps, dt, order=4):
+        _check(self._lib.sl_evolve(self._h, int(steps), float(dt), int(order)))
+
+    def synchronize(self):
+        _check(self._lib.sl_synchronize(self._h))
+
+    def energies(self):
+        e = Energies()
+        _check(self._lib.sl_energies(self._h, ctypes.byref(e)))
+        out = {k: getattr(e, k) for k in ("eta", "a", "p_a", "hubble", "rho", "pressure",
+                                          "w_eos", "friedmann_residual", "h_total", "pot")}
+        for k in ("kin", "grad", "mean", "var"):
+            out[k] = [getattr(e, k)[i] for i in range(self.nfields)]
+        return out
+
+    def spectrum(self, field, nbins):
+        k = np.zeros(nbins)
+        p = np.zeros(nbins)
+        c = np.zeros(nbins, dtype=np.int64)
+        _check(self._lib.sl_spectrum(self._h, int(field), int(nbins),
+                                     k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     c.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return k, p, c
+
+    # -- launch shape and timing ---------------------------------------------
+    def tile(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.sl_get_tile(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def set_tile(self, tx, tz=0):
+        _check(self._lib.sl_set_tile(self._h, int(tx), int(tz)))
+
+    def set_kernel_timing(self, enable):
+        _check(self._lib.sl_set_kernel_timing(self._h, 1 if enable else 0))
+
+    def kernel_timing(self):
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        _check(self._lib.sl_kernel_timing(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+
+def from_recipe(r, stream=None):
+    """Lattice with potential set and initial state drawn from a workload
+    recipe dict (see the synth module)."""
+    lat = Lattice(r["n"], r["nfields"], r["L"], precision=r.get("precision", "f64"),
+                  expand=r.get("expand", True), mpl=r["mpl"], a0=r.get("a0", 1.0),
+                  stream=stream)
+    lat.set_potential(r["potential"], r["params"])
+    lat.init_fluctuations(r["phi0"], r["pi0"], r["fluct"], r["amplitude"], r["seed"])
+    return lat
