@@ -36,6 +36,9 @@ def parse():
     p.add_argument("--precision", default="f64", choices=["f64", "f32"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage line")
+    p.add_argument("--no-serve", action="store_true", help="skip the served ensemble")
+    p.add_argument("--serve-runs", type=int, default=96)
+    p.add_argument("--serve-steps", type=int, default=500)
     return p.parse_args()
 
 
@@ -46,6 +49,8 @@ def log(*a):
 def measure(sl, recipe, steps, warmup):
     lat = sl.from_recipe(recipe)
     order, dt = recipe["order"], recipe["dt"]
+    shape, best = lat.autotune(reps=3)
+    log("autotuned pass shape (tx, vx, tz, pf) =", shape, "best pass %.4f ms" % best)
     lat.evolve(warmup, dt, order)
     lat.synchronize()
     t0 = time.perf_counter()
@@ -61,6 +66,49 @@ def measure(sl, recipe, steps, warmup):
     tile = lat.tile()
     lat.close()
     return wall, passes, pass_ms, e, tile
+
+
+def measure_served(sl, nruns, steps):
+    """Delta-N ensemble served by the request loop (FP32 storage, 4th order):
+    capacity from a burst (all requests at t = 0), then Poisson arrivals at
+    0.8x that capacity; beside it the plain FP64 single-run path (each run
+    alone, one after the other) on the same GPU."""
+    import numpy as np
+    import synth
+    from paper_1201_5029_amd import serve
+    recipes = synth.delta_n_scan(nruns=nruns, steps=steps)
+    dt, order = recipes[0]["dt"], recipes[0]["order"]
+
+    def reqs(arrivals):
+        return [serve.Request(j, r, t) for j, (r, t) in enumerate(zip(recipes, arrivals))]
+
+    burst_res, burst = serve.serve(reqs([0.0] * nruns), dt, order, max_slots=nruns, tick_steps=25)
+    capacity = nruns / burst["makespan_s"]
+    arrivals = synth.poisson_arrivals(nruns, 0.8 * capacity)
+    pois_res, pois = serve.serve(reqs(arrivals), dt, order, max_slots=nruns, tick_steps=25)
+    # FP64 single-run path, one run after the other; error of the served
+    # FP32 results against it (the FP64 path is the one pinned to the oracle)
+    t0 = time.perf_counter()
+    errs, sups = [], 0
+    for j, r in enumerate(recipes):
+        lat = sl.from_recipe(dict(r, precision="f64"))
+        lat.evolve(steps, dt, order)
+        _, a, _ = lat.background()
+        errs.append(abs(np.log(a) - burst_res[j]["efolds"]) / np.log(a))
+        sups += r["n"] ** 3 * r["nfields"] * steps
+        lat.close()
+    t64 = time.perf_counter() - t0
+    return {
+        "workload": "%d preheat runs, n in {32, 64, 96}, FP32 fields, order 4, %d steps" % (nruns, steps),
+        "burst": {"makespan_s": burst["makespan_s"], "value": burst["field_site_updates_per_s"],
+                  "p50_s": burst["p50_s"], "p99_s": burst["p99_s"]},
+        "poisson": {"rate_per_s": 0.8 * capacity, "makespan_s": pois["makespan_s"],
+                    "value": pois["field_site_updates_per_s"], "p50_s": pois["p50_s"],
+                    "p99_s": pois["p99_s"], "peak_resident": pois["peak_resident"]},
+        "fp64_single_runs": {"wall_s": t64, "value": sups / t64},
+        "efolds_rel_err_fp32_vs_fp64_max": float(max(errs)),
+        "unit": "field-site-updates/s",
+    }
 
 
 def cpu_baseline(recipe):
@@ -136,6 +184,9 @@ def main():
             "value": n3 * nf * args.steps / w32, "ms_per_step": w32 / args.steps * 1e3,
             "pass_ms": ms32 / p32, "achieved_GBs": 4 * 4 * nf * n3 / (ms32 / p32 / 1e3) / 1e9,
             "friedmann_residual": e32["friedmann_residual"], "tile": list(tile32)}
+    if not args.no_serve:
+        log("served ensemble ...")
+        out["served"] = measure_served(sl, args.serve_runs, args.serve_steps)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, 1 step) ...")
         out["cpu_baseline"] = cpu_baseline(recipe)

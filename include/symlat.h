@@ -208,12 +208,63 @@ double sl_stability_limit(int32_t order);
 sl_status sl_set_kernel_timing(sl_lattice* lat, int32_t enable);
 sl_status sl_kernel_timing(sl_lattice* lat, int64_t* passes, double* total_ms);
 
-/* Launch shape of the fused pass: tile width in x (16, 32 or 64 lanes),
- * rows per tile (256 / tx) and z-planes per tile.  sl_get_tile reports the
- * shape in use; sl_set_tile overrides it (tz = 0 picks the default
- * z-chunk).  SL_E_INVALID for unsupported shapes. */
-sl_status sl_get_tile(sl_lattice* lat, int32_t* tx, int32_t* ty, int32_t* tz);
-sl_status sl_set_tile(sl_lattice* lat, int32_t tx, int32_t tz);
+/* Launch shape of the fused pass: tx lanes along x (16, 32 or 64), each
+ * holding vx consecutive x-sites (1, 2 or 4; n must be divisible by vx),
+ * ty = 256/tx rows, tz z-planes per workgroup, and the prefetch depth pf of
+ * the z-march (1: next plane loaded each iteration; 2: own column two
+ * planes and halo one plane ahead).  Lattices with more than two fields run
+ * with vx = 1, pf = 1.  sl_get_tile reports the shape in use; sl_set_tile
+ * overrides it (tz = 0: z-chunk chosen from the kernel's occupancy so the
+ * grid fills whole rounds of resident workgroups).  SL_E_INVALID for
+ * unsupported shapes or more than 65536 workgroups. */
+sl_status sl_get_tile(sl_lattice* lat, int32_t* tx, int32_t* vx, int32_t* ty, int32_t* tz,
+                      int32_t* pf);
+sl_status sl_set_tile(sl_lattice* lat, int32_t tx, int32_t vx, int32_t tz, int32_t pf);
+
+/* Autotuner: time the fused pass in candidate shapes (tx in {16, 32, 64},
+ * vx in {1, 2, 4} dividing n, pf in {1, 2}, tz in {occupancy choice, n/16,
+ * n/8, n/4, n/2}), best of `reps` HIP-event timings each, on the lattice's
+ * current state, which the timing passes leave unchanged.  vx_only / pf_only
+ * (0 = free) restrict the search, e.g. to the per-lane shape of a batch.
+ * The winner is applied and remembered for this process: lattices created
+ * later with the same (device, n, fields, precision, potential family) start
+ * with it.  Outputs may be NULL.  sl_autotune_forget clears that memory. */
+sl_status sl_autotune(sl_lattice* lat, int32_t reps, int32_t vx_only, int32_t pf_only,
+                      int32_t* tx, int32_t* vx, int32_t* tz, int32_t* pf, double* best_ms);
+sl_status sl_autotune_forget(void);
+
+/* Batched form: many lattices advanced together, as in the ensemble of
+ * runs with different initial values that the separate-universe
+ * calculation needs (Sec. 2.4, Sec. 4).  Members share storage precision,
+ * potential family, field count and the per-lane shape (vx, pf) of the
+ * fused pass; sizes, parameters, tile widths and z-chunks may differ.  Each
+ * stage is one fused pass over the concatenated tiles of all members (each
+ * XCD strides through a contiguous range of them) and one finalize with a
+ * workgroup per member; an evolve call is captured as a HIP graph and
+ * replayed while (steps, dt, order, membership) are unchanged.  A member's
+ * result is bit-identical to evolving it alone with the same tile shape.
+ * The batch does not own its members: destroying a lattice removes it.
+ * hip_stream: caller-owned hipStream_t or NULL (own stream).  The batch
+ * orders itself after each member's stream and each member's stream after
+ * the batch.  SL_E_INVALID for a mismatched or duplicate member. */
+sl_status sl_batch_create(void* hip_stream, sl_batch** out);
+sl_status sl_batch_destroy(sl_batch* batch);
+sl_status sl_batch_add(sl_batch* batch, sl_lattice* lat);
+sl_status sl_batch_remove(sl_batch* batch, sl_lattice* lat);
+sl_status sl_batch_count(const sl_batch* batch, int32_t* count);
+/* Advance every member `steps` steps (same dt and order for all). */
+sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order);
+/* Wait for the batch and report members' sticky device errors. */
+sl_status sl_batch_synchronize(sl_batch* batch);
+
+/* Free and total device memory (for admission by sl_footprint_bytes). */
+sl_status sl_device_memory(size_t* free_bytes, size_t* total_bytes);
+
+/* Measurement helper: time `iters` plain device-to-device copies of `bytes`
+ * bytes (bytes a multiple of 32, >= 1024) on a private stream and return the
+ * achieved read+write bandwidth in GB/s.  Used to calibrate memory counters
+ * and to state the achievable HBM bandwidth beside the lattice kernels. */
+sl_status sl_hbm_copy_bench(size_t bytes, int32_t iters, double* gbs);
 
 #ifdef __cplusplus
 }

@@ -14,6 +14,9 @@ namespace symlat {
 constexpr int kBlock = 256;     // threads per workgroup of every lattice kernel
 constexpr int kMaxFields = 8;
 constexpr int kMaxBins = 2048;
+// Idle lanes of the fused pass store here: 256 threads x 2 arrays x 8 fields
+// x 4 sites x 8 bytes.
+constexpr size_t kSinkBytes = size_t(kBlock) * 2 * kMaxFields * 4 * 8;
 
 // Sticky device-side error bits in DevScalars::status.
 constexpr int kStatusNonFinite = 1;
@@ -54,12 +57,38 @@ struct PotArgs {
   double p[kMaxFields];
 };
 
-// Launch shape of the tiled passes: TX lanes in x (power of two), TY = 256/TX
-// rows in y, TZ planes per z-chunk.
+// Launch shape of the tiled passes: TX lanes in x (power of two) each
+// holding VX consecutive sites (tile width TX*VX), TY = 256/TX rows in y,
+// TZ planes per z-chunk.
 struct Tile {
-  int tx, logtx, ty, tz;
+  int tx, logtx, ty, tz, vx;
+  int pf;  // prefetch depth of the z-march (1 or 2 planes)
   int ntx, nty, ntz;
   int nblocks() const { return ntx * nty * ntz; }
+};
+
+// Kernel-side view of one lattice for the fused pass.
+struct PassParams {
+  const void* phi[2];
+  const void* pi[2];
+  void* phi_w[2];
+  void* pi_w[2];
+  const DevScalars* sc;
+  double* partials;
+  void* sink;  // per-thread slots that absorb the stores of idle lanes
+  PotArgs prm;
+  int n;
+  int tx, logtx, ty, tz;  // lanes in x, log2(lanes), rows, planes per chunk
+  int ntx, nty, ntz;
+};
+
+// One run of a batch for the finalize / begin kernels.
+struct BatchRun {
+  DevScalars* sc;
+  double* partials;
+  BgConsts bg;
+  int ntiles;
+  int pad;
 };
 
 // Device view of one lattice handed to the launchers.
@@ -68,6 +97,7 @@ struct LatView {
   void* pi[2];           // ping-pong momentum buffers
   DevScalars* sc;
   double* partials;      // per-block (sum, compensation) pairs
+  void* sink;            // kSinkBytes of store slots for idle lanes of the pass
   int n, nf, prec, pot;  // prec: sl_precision, pot: sl_potential
   PotArgs prm;
   BgConsts bg;
@@ -76,6 +106,20 @@ struct LatView {
 
 // ---- step kernels (kernels_step.hip) --------------------------------------
 hipError_t launch_pass(const LatView& v, hipStream_t s);
+// Resident workgroups per CU of the pass kernel for this shape.
+int pass_blocks_per_cu(int prec, int pot, int nf, const Tile& t);
+PassParams pass_params(const LatView& v);
+size_t pass_lds_bytes(int prec, int nf, const Tile& t);
+// Batched form: one fused pass over the tiles of nruns lattices (run table
+// and tile starts in device memory), then one finalize workgroup per run.
+hipError_t launch_batched_pass(int prec, int pot, int nf, const Tile& shape, size_t lds,
+                               const PassParams* runs_dev, const int* start_dev, int nruns,
+                               int grid, hipStream_t s);
+int batched_blocks_per_cu(int prec, int pot, int nf, const Tile& shape, size_t lds);
+hipError_t launch_batched_finalize(const BatchRun* runs_dev, int nruns, double w, double w_next,
+                                   double h, int has_next, int end_of_step, hipStream_t s);
+hipError_t launch_batched_begin(const BatchRun* runs_dev, int nruns, double w, double h,
+                                hipStream_t s);
 // Reduce the pass partials, finish stage (weight w) and, if has_next, begin
 // the next stage (weight w_next); eta += h when end_of_step.
 hipError_t launch_stage_finalize(const LatView& v, double w, double w_next, double h,

@@ -34,25 +34,73 @@ namespace symlat {
 
 namespace {
 
-struct PassParams {
-  const void* phi[2];
-  const void* pi[2];
-  void* phi_w[2];
-  void* pi_w[2];
-  const DevScalars* sc;
-  double* partials;
-  PotArgs prm;
-  int n;
-  int tx, logtx, ty, tz;
-  int ntx, nty, ntz;
+
+// VX consecutive x-sites per lane, moved with one vector load/store.
+template <typename T, int VX>
+struct Vec {
+  T v[VX];
 };
 
-template <typename T, int NF, int KIND>
-__global__ __launch_bounds__(kBlock) void pass_kernel(PassParams P) {
-  extern __shared__ unsigned char smem_raw[];
-  T* lds = reinterpret_cast<T*>(smem_raw);
-  __shared__ KSum red_scratch[4 * 3];
+template <typename T, int VX>
+__device__ __forceinline__ Vec<T, VX> ldv(const T* __restrict__ p) {
+  Vec<T, VX> r;
+  if constexpr (VX == 1) {
+    r.v[0] = p[0];
+  } else if constexpr (VX == 4 && sizeof(T) == 8) {
+    const double4 q = *reinterpret_cast<const double4*>(p);
+    r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
+  } else if constexpr (VX == 4) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
+  } else if constexpr (sizeof(T) == 8) {
+    const double2 q = *reinterpret_cast<const double2*>(p);
+    r.v[0] = q.x;
+    r.v[1] = q.y;
+  } else {
+    const float2 q = *reinterpret_cast<const float2*>(p);
+    r.v[0] = q.x;
+    r.v[1] = q.y;
+  }
+  return r;
+}
 
+template <typename T, int VX>
+__device__ __forceinline__ void stv(T* __restrict__ p, const T (&v)[VX]) {
+  if constexpr (VX == 1) {
+    p[0] = v[0];
+  } else if constexpr (VX == 4 && sizeof(T) == 8) {
+    *reinterpret_cast<double4*>(p) = make_double4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (VX == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (sizeof(T) == 8) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  } else {
+    *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+  }
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin (id mod 8).  Renumber them
+// so that each XCD receives a contiguous run of tiles: neighbouring tiles,
+// whose halos overlap, then share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  constexpr int kXcd = 8;
+  const int per = nb / kXcd, rem = nb % kXcd;
+  const int x = b % kXcd, i = b / kXcd;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
+// PF = 1: the next plane is loaded at the top of each z-iteration and used
+// at once.  PF = 2: software pipeline -- the loads for plane z+1 (own column
+// one plane further ahead, and the halo) are issued right after the barrier
+// of plane z, before plane z's stores.  Vector-memory counters retire in
+// issue order, so a wavefront does not wait for its own stores before it
+// uses the next plane's data -- provided every lane issues the same memory
+// instructions: in the PF = 2 kernel idle lanes load a clamped in-range
+// address and store into a private sink slot, and x-halo cells are fetched
+// as the aligned VX-wide group that contains them.
+template <typename T, int NF, int KIND, int VX, int PF>
+__device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* lds,
+                                          KSum* red_scratch) {
   const int par = P.sc->parity;
   const T* __restrict__ phi_in = static_cast<const T*>(P.phi[par]);
   const T* __restrict__ pi_in = static_cast<const T*>(P.pi[par]);
@@ -70,122 +118,253 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(PassParams P) {
   const size_t n3 = n2 * n;
 
   // tile of this workgroup (x tiles fastest, then y, then z chunks)
-  int b = blockIdx.x;
+  int b = tile_id;
   const int xt = b % P.ntx;
   b /= P.ntx;
   const int yt = b % P.nty;
   const int zt = b / P.nty;
-  const int x0 = xt * P.tx, y0 = yt * P.ty, z0 = zt * P.tz;
-  const int wx = min(P.tx, n - x0), wy = min(P.ty, n - y0), zc = min(P.tz, n - z0);
+  const int TW = P.tx * VX;  // tile width in sites
+  const int x0 = xt * TW, y0 = yt * P.ty, z0 = zt * P.tz;
+  const int wx = min(TW, n - x0), wy = min(P.ty, n - y0), zc = min(P.tz, n - z0);
+  const int zend = z0 + zc;  // exclusive; plane zend (mod n) is the upper halo
 
   const int tid = threadIdx.x;
   const int tx = tid & (P.tx - 1);
   const int ty = tid >> P.logtx;
-  const bool active = (tx < wx) && (ty < wy);
-  const int LX = P.tx + 2;
+  const bool active = (tx * VX < wx) && (ty < wy);
+  const int LX = TW + 2;
   const int plane = LX * (P.ty + 2);
-  const int own = (ty + 1) * LX + (tx + 1);
-  const size_t col = size_t(y0 + ty) * n + (x0 + tx);
+  const int own = (ty + 1) * LX + 1 + tx * VX;  // LDS index of the first own site
+  // own column; idle lanes read the tile's first column (in range, unused)
+  const size_t col = active ? size_t(y0 + ty) * n + (x0 + tx * VX) : size_t(y0) * n + x0;
 
-  // halo job of this thread: -1 if none
-  int hl = -1;
-  size_t hcol = 0;
+  // halo job: 1 = VX-wide row segment, 2 = left x-halo cell, 3 = right
+  // x-halo cell, 0 = none.  Every lane loads one aligned VX-wide group per
+  // field and plane (its own column when it has no job).
+  int hjob = 0, hl = 0;
+  size_t hcol = col;
   {
     const int TX = P.tx, TY = P.ty;
-    int hx = 0, hy = 0;
+    int hx = -1, hy = 0;
     if (tid < TX) {
-      if (tid < wx) { hx = x0 + tid; hy = (y0 - 1 + n) % n; hl = tid + 1; }
+      if (tid * VX < wx) { hjob = 1; hx = x0 + tid * VX; hy = (y0 - 1 + n) % n; hl = 1 + tid * VX; }
     } else if (tid < 2 * TX) {
       const int t = tid - TX;
-      if (t < wx) { hx = x0 + t; hy = (y0 + wy) % n; hl = (wy + 1) * LX + t + 1; }
+      if (t * VX < wx) { hjob = 1; hx = x0 + t * VX; hy = (y0 + wy) % n; hl = (wy + 1) * LX + 1 + t * VX; }
     } else if (tid < 2 * TX + TY) {
       const int r = tid - 2 * TX;
-      if (r < wy) { hx = (x0 - 1 + n) % n; hy = y0 + r; hl = (r + 1) * LX; }
+      // group [x0 - VX, x0) holds the left neighbour x0 - 1 as element VX - 1
+      if (r < wy) { hjob = 2; hx = (x0 - VX + n) % n; hy = y0 + r; hl = (r + 1) * LX; }
     } else if (tid < 2 * TX + 2 * TY) {
       const int r = tid - 2 * TX - TY;
-      if (r < wy) { hx = (x0 + wx) % n; hy = y0 + r; hl = (r + 1) * LX + wx + 1; }
+      // group [x0 + wx, x0 + wx + VX) holds the right neighbour as element 0
+      if (r < wy) { hjob = 3; hx = (x0 + wx) % n; hy = y0 + r; hl = (r + 1) * LX + wx + 1; }
     }
-    hcol = size_t(hy) * n + hx;
+    if (hx >= 0) hcol = size_t(hy) * n + hx;
   }
 
-  KSum acc_dd{0.0, 0.0}, acc_v{0.0, 0.0}, acc_p{0.0, 0.0};
-  T fm[NF], fc[NF], fp[NF], pc[NF], pp[NF];
+  auto wrap = [n](int z) { return z >= n ? z - n : z; };
 
-  if (active) {
-    const int zm = (z0 - 1 + n) % n;
+  KSum acc_dd{0.0, 0.0}, acc_v{0.0, 0.0}, acc_p{0.0, 0.0};
+  // drifted field at z-1, z, z+1 and momenta at z, z+1 of the own sites
+  T fm[NF][VX], fc[NF][VX], fp[NF][VX], pc[NF][VX], pp[NF][VX];
+  // raw loads in flight: own column and halo
+  T nph[NF][VX], npi[NF][VX], hph[NF][VX], hpi[NF][VX];
+
+  auto load_own = [&](int zz) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      const size_t om = i * n3 + size_t(zm) * n2 + col;
-      const size_t oc = i * n3 + size_t(z0) * n2 + col;
-      fm[i] = drift(phi_in[om], pi_in[om], c);
-      pc[i] = pi_in[oc];
-      fc[i] = drift(phi_in[oc], pc[i], c);
+      const size_t o = i * n3 + size_t(zz) * n2 + col;
+      const Vec<T, VX> u = ldv<T, VX>(phi_in + o), w = ldv<T, VX>(pi_in + o);
+#pragma unroll
+      for (int v = 0; v < VX; ++v) {
+        nph[i][v] = u.v[v];
+        npi[i][v] = w.v[v];
+      }
+    }
+  };
+  auto load_halo = [&](int zz) {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const size_t o = i * n3 + size_t(zz) * n2 + hcol;
+      const Vec<T, VX> u = ldv<T, VX>(phi_in + o), w = ldv<T, VX>(pi_in + o);
+#pragma unroll
+      for (int v = 0; v < VX; ++v) {
+        hph[i][v] = u.v[v];
+        hpi[i][v] = w.v[v];
+      }
+    }
+  };
+  auto halo_to_lds = [&](T* L) {
+    if (hjob == 1) {
+#pragma unroll
+      for (int i = 0; i < NF; ++i)
+#pragma unroll
+        for (int v = 0; v < VX; ++v) L[i * plane + hl + v] = drift(hph[i][v], hpi[i][v], c);
+    } else if (hjob >= 2) {
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        const T f = hjob == 2 ? hph[i][VX - 1] : hph[i][0];
+        const T q = hjob == 2 ? hpi[i][VX - 1] : hpi[i][0];
+        L[i * plane + hl] = drift(f, q, c);
+      }
+    }
+  };
+  auto take_next = [&]() {  // fp, pp from the raw own-column loads
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+      for (int v = 0; v < VX; ++v) {
+        pp[i][v] = npi[i][v];
+        fp[i][v] = drift(nph[i][v], npi[i][v], c);
+      }
+  };
+
+  // prologue: planes z0 - 1 and z0 of the own column
+  load_own((z0 - 1 + n) % n);
+#pragma unroll
+  for (int i = 0; i < NF; ++i)
+#pragma unroll
+    for (int v = 0; v < VX; ++v) fm[i][v] = drift(nph[i][v], npi[i][v], c);
+  load_own(z0);
+#pragma unroll
+  for (int i = 0; i < NF; ++i)
+#pragma unroll
+    for (int v = 0; v < VX; ++v) {
+      pc[i][v] = npi[i][v];
+      fc[i][v] = drift(nph[i][v], npi[i][v], c);
+    }
+  // store targets: the lattice for active lanes, the sink slot otherwise
+  T* sink = static_cast<T*>(P.sink) + size_t(tid) * (2 * NF * VX);
+
+  if constexpr (PF == 2) {
+    load_own(wrap(z0 + 1));
+    load_halo(z0);
+    // Same trailing sequence as a loop iteration (loads, then 2 NF stores),
+    // so the wait counts the compiler derives at the loop head do not cover
+    // the previous plane's stores.
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      stv<T, VX>(sink + (2 * i) * VX, fc[i]);
+      stv<T, VX>(sink + (2 * i + 1) * VX, pc[i]);
     }
   }
 
   int buf = 0;
-  for (int z = z0; z < z0 + zc; ++z) {
-    const int zp = (z + 1 == n) ? 0 : z + 1;
-    if (active) {
-#pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        const size_t op = i * n3 + size_t(zp) * n2 + col;
-        pp[i] = pi_in[op];
-        fp[i] = drift(phi_in[op], pp[i], c);
-      }
-    }
+  for (int z = z0; z < zend; ++z) {
     T* L = lds + size_t(buf) * NF * plane;
-    if (hl >= 0) {
-#pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        const size_t oh = i * n3 + size_t(z) * n2 + hcol;
-        L[i * plane + hl] = drift(phi_in[oh], pi_in[oh], c);
-      }
+    if constexpr (PF == 1) {
+      load_own(wrap(z + 1));
+      take_next();
+      load_halo(z);
+    } else {
+      take_next();  // loads issued before the previous plane's stores
     }
+    halo_to_lds(L);
     if (active) {
 #pragma unroll
-      for (int i = 0; i < NF; ++i) L[i * plane + own] = fc[i];
+      for (int i = 0; i < NF; ++i)
+#pragma unroll
+        for (int v = 0; v < VX; ++v) L[i * plane + own + v] = fc[i][v];
     }
     __syncthreads();
-    if (active) {
-      T D[NF], dV[NF], V;
+    if constexpr (PF == 2) {
+      // next plane's loads go out before this plane's stores; past the end
+      // of the chunk they re-read the last plane (in range, unused)
+      load_own(wrap(min(z + 2, zend)));
+      load_halo(min(z + 1, zend - 1));
+    }
+    {
+      double dd = 0.0, p2 = 0.0, vs = 0.0;
+      T pn[NF][VX];
 #pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        const T* Li = L + i * plane;
-        D[i] = ((Li[own - 1] + Li[own + 1]) + (Li[own - LX] + Li[own + LX])) + (fm[i] + fp[i]) -
-               T(6) * fc[i];
+      for (int v = 0; v < VX; ++v) {
+        T f[NF], D[NF], dV[NF], V;
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+          const T* Li = L + i * plane + own + v;
+          f[i] = fc[i][v];
+          D[i] = ((Li[-1] + Li[1]) + (Li[-LX] + Li[LX])) + (fm[i][v] + fp[i][v]) - T(6) * f[i];
+        }
+        potential<KIND, NF, T>(f, pot, V, dV);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+          pn[i][v] = pc[i][v] + alpha * D[i] - beta * dV[i];
+          dd += double(f[i]) * double(D[i]);
+          p2 += double(pn[i][v]) * double(pn[i][v]);
+        }
+        vs += double(V);
       }
-      potential<KIND, NF, T>(fc, pot, V, dV);
       const size_t oc = size_t(z) * n2 + col;
-      double dd = 0.0, p2 = 0.0;
 #pragma unroll
       for (int i = 0; i < NF; ++i) {
-        const T pn = pc[i] + alpha * D[i] - beta * dV[i];
-        phi_out[i * n3 + oc] = fc[i];
-        pi_out[i * n3 + oc] = pn;
-        dd += double(fc[i]) * double(D[i]);
-        p2 += double(pn) * double(pn);
+        T* po = active ? phi_out + i * n3 + oc : sink + (2 * i) * VX;
+        T* qo = active ? pi_out + i * n3 + oc : sink + (2 * i + 1) * VX;
+        stv<T, VX>(po, fc[i]);
+        stv<T, VX>(qo, pn[i]);
       }
-      kadd(acc_dd, dd);
-      kadd(acc_v, double(V));
-      kadd(acc_p, p2);
+      if (active) {
+        kadd(acc_dd, dd);
+        kadd(acc_v, vs);
+        kadd(acc_p, p2);
+      }
 #pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        fm[i] = fc[i];
-        fc[i] = fp[i];
-        pc[i] = pp[i];
-      }
+      for (int i = 0; i < NF; ++i)
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+          fm[i][v] = fc[i][v];
+          fc[i][v] = fp[i][v];
+          pc[i][v] = pp[i][v];
+        }
     }
     buf ^= 1;
   }
 
-  KSum v[3] = {acc_dd, acc_v, acc_p};
-  block_reduce<3>(v, red_scratch);
+  KSum v3[3] = {acc_dd, acc_v, acc_p};
+  block_reduce<3>(v3, red_scratch);
   if (threadIdx.x == 0) {
-    double* out = P.partials + size_t(blockIdx.x) * 6;
-    out[0] = v[0].s; out[1] = v[0].c;
-    out[2] = v[1].s; out[3] = v[1].c;
-    out[4] = v[2].s; out[5] = v[2].c;
+    double* out = P.partials + size_t(tile_id) * 6;
+    out[0] = v3[0].s; out[1] = v3[0].c;
+    out[2] = v3[1].s; out[3] = v3[1].c;
+    out[4] = v3[2].s; out[5] = v3[2].c;
+  }
+}
+
+template <typename T, int NF, int KIND, int VX, int PF>
+__global__ __launch_bounds__(kBlock) void pass_kernel(PassParams P) {
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ KSum red_scratch[4 * 3];
+  pass_tile<T, NF, KIND, VX, PF>(P, xcd_tile(blockIdx.x, gridDim.x), reinterpret_cast<T*>(smem_raw),
+                                 red_scratch);
+}
+
+// Batched form: the tiles of many lattices (same precision, potential family
+// and per-lane shape; any sizes) in one launch.  Global tile g belongs to run
+// r with start[r] <= g < start[r+1].  Each XCD takes a contiguous range of
+// global tiles and its workgroups stride through it, so one launch of about
+// the resident capacity covers any mix of lattice sizes.  A run's tiles and
+// partial sums are exactly those of the same lattice advanced alone.
+template <typename T, int NF, int KIND, int VX, int PF>
+__global__ __launch_bounds__(kBlock) void batched_pass_kernel(const PassParams* __restrict__ runs,
+                                                             const int* __restrict__ start,
+                                                             int nruns) {
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ KSum red_scratch[4 * 3];
+  constexpr int kXcd = 8;
+  const int total = start[nruns];
+  const int G = gridDim.x, b = blockIdx.x;
+  const int xcd = b % kXcd, i = b / kXcd;
+  const int nbx = (G - xcd + kXcd - 1) / kXcd;  // workgroups on this XCD
+  const int t0 = int((long long)total * xcd / kXcd);
+  const int t1 = int((long long)total * (xcd + 1) / kXcd);
+  for (int g = t0 + i; g < t1; g += nbx) {
+    int lo = 0, hi = nruns - 1;  // run with start[r] <= g < start[r + 1]
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (start[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    pass_tile<T, NF, KIND, VX, PF>(runs[lo], g - start[lo], reinterpret_cast<T*>(smem_raw),
+                                   red_scratch);
   }
 }
 
@@ -236,11 +415,9 @@ __device__ void begin_stage(DevScalars& S, const BgConsts& K, double w, double h
   S.beta = a * a * a * a * tau;
 }
 
-__global__ __launch_bounds__(kBlock) void stage_finalize_kernel(DevScalars* sc, const double* partials,
-                                                               int nblocks, BgConsts K, double w,
-                                                               double w_next, double h, int has_next,
-                                                               int end_of_step) {
-  __shared__ KSum scratch[4 * 3];
+__device__ void finalize_body(DevScalars* sc, const double* partials, int nblocks, const BgConsts& K,
+                              double w, double w_next, double h, int has_next, int end_of_step,
+                              KSum* scratch) {
   KSum v[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
   for (int b = threadIdx.x; b < nblocks; b += kBlock) {
     const double* p = partials + size_t(b) * 6;
@@ -264,6 +441,33 @@ __global__ __launch_bounds__(kBlock) void stage_finalize_kernel(DevScalars* sc, 
   }
 }
 
+__global__ __launch_bounds__(kBlock) void stage_finalize_kernel(DevScalars* sc, const double* partials,
+                                                               int nblocks, BgConsts K, double w,
+                                                               double w_next, double h, int has_next,
+                                                               int end_of_step) {
+  __shared__ KSum scratch[4 * 3];
+  finalize_body(sc, partials, nblocks, K, w, w_next, h, has_next, end_of_step, scratch);
+}
+
+// One workgroup per run of a batch.
+__global__ __launch_bounds__(kBlock) void batched_finalize_kernel(const BatchRun* __restrict__ runs,
+                                                                 double w, double w_next, double h,
+                                                                 int has_next, int end_of_step) {
+  __shared__ KSum scratch[4 * 3];
+  const BatchRun& R = runs[blockIdx.x];
+  finalize_body(R.sc, R.partials, R.ntiles, R.bg, w, w_next, h, has_next, end_of_step, scratch);
+}
+
+__global__ void batched_begin_kernel(const BatchRun* __restrict__ runs, int nruns, double w,
+                                     double h) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nruns) {
+    DevScalars S = *runs[r].sc;
+    begin_stage(S, runs[r].bg, w, h);
+    *runs[r].sc = S;
+  }
+}
+
 __global__ void begin_kernel(DevScalars* sc, BgConsts K, double w, double h) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     DevScalars S = *sc;
@@ -272,8 +476,7 @@ __global__ void begin_kernel(DevScalars* sc, BgConsts K, double w, double h) {
   }
 }
 
-template <typename T, int NF, int KIND>
-hipError_t launch_pass_t(const LatView& v, hipStream_t s) {
+PassParams make_params(const LatView& v) {
   PassParams P;
   for (int k = 0; k < 2; ++k) {
     P.phi[k] = v.phi[k];
@@ -283,6 +486,7 @@ hipError_t launch_pass_t(const LatView& v, hipStream_t s) {
   }
   P.sc = v.sc;
   P.partials = v.partials;
+  P.sink = v.sink;
   P.prm = v.prm;
   P.n = v.n;
   P.tx = v.tile.tx;
@@ -292,36 +496,118 @@ hipError_t launch_pass_t(const LatView& v, hipStream_t s) {
   P.ntx = v.tile.ntx;
   P.nty = v.tile.nty;
   P.ntz = v.tile.ntz;
-  const size_t lds = size_t(2) * NF * (P.tx + 2) * (P.ty + 2) * sizeof(T);
-  hipLaunchKernelGGL((pass_kernel<T, NF, KIND>), dim3(v.tile.nblocks()), dim3(kBlock), lds, s, P);
-  return hipGetLastError();
+  return P;
+}
+
+using PassFn = void (*)(PassParams);
+using BatchedFn = void (*)(const PassParams*, const int*, int);
+
+struct PassKernel {
+  PassFn fn;
+  BatchedFn bfn;
+  size_t lds;
+};
+
+template <typename T, int NF, int KIND>
+PassKernel pick_t(const Tile& t) {
+  PassKernel k;
+  k.lds = size_t(2) * NF * (t.tx * t.vx + 2) * (t.ty + 2) * sizeof(T);
+  if constexpr (NF <= 2) {
+    if (t.pf == 2) {
+      k.fn = t.vx == 4 ? pass_kernel<T, NF, KIND, 4, 2>
+                       : (t.vx == 2 ? pass_kernel<T, NF, KIND, 2, 2> : pass_kernel<T, NF, KIND, 1, 2>);
+      k.bfn = t.vx == 4 ? batched_pass_kernel<T, NF, KIND, 4, 2>
+                        : (t.vx == 2 ? batched_pass_kernel<T, NF, KIND, 2, 2>
+                                     : batched_pass_kernel<T, NF, KIND, 1, 2>);
+    } else {
+      k.fn = t.vx == 4 ? pass_kernel<T, NF, KIND, 4, 1>
+                       : (t.vx == 2 ? pass_kernel<T, NF, KIND, 2, 1> : pass_kernel<T, NF, KIND, 1, 1>);
+      k.bfn = t.vx == 4 ? batched_pass_kernel<T, NF, KIND, 4, 1>
+                        : (t.vx == 2 ? batched_pass_kernel<T, NF, KIND, 2, 1>
+                                     : batched_pass_kernel<T, NF, KIND, 1, 1>);
+    }
+  } else {
+    // more than two fields: one site per lane, no deep prefetch (register budget)
+    k.fn = pass_kernel<T, NF, KIND, 1, 1>;
+    k.bfn = batched_pass_kernel<T, NF, KIND, 1, 1>;
+  }
+  return k;
 }
 
 template <typename T>
-hipError_t dispatch_pass(const LatView& v, hipStream_t s) {
-  switch (v.pot) {
-    case SL_POT_CHAOTIC2: return launch_pass_t<T, 2, SL_POT_CHAOTIC2>(v, s);
-    case SL_POT_OSCILLON: return launch_pass_t<T, 1, SL_POT_OSCILLON>(v, s);
-    case SL_POT_QBALL_LOG: return launch_pass_t<T, 2, SL_POT_QBALL_LOG>(v, s);
+PassKernel pick_prec(int pot, int nf, const Tile& t) {
+  switch (pot) {
+    case SL_POT_CHAOTIC2: return pick_t<T, 2, SL_POT_CHAOTIC2>(t);
+    case SL_POT_OSCILLON: return pick_t<T, 1, SL_POT_OSCILLON>(t);
+    case SL_POT_QBALL_LOG: return pick_t<T, 2, SL_POT_QBALL_LOG>(t);
     default: break;
   }
-  switch (v.nf) {
-    case 1: return launch_pass_t<T, 1, SL_POT_FREE>(v, s);
-    case 2: return launch_pass_t<T, 2, SL_POT_FREE>(v, s);
-    case 3: return launch_pass_t<T, 3, SL_POT_FREE>(v, s);
-    case 4: return launch_pass_t<T, 4, SL_POT_FREE>(v, s);
-    case 5: return launch_pass_t<T, 5, SL_POT_FREE>(v, s);
-    case 6: return launch_pass_t<T, 6, SL_POT_FREE>(v, s);
-    case 7: return launch_pass_t<T, 7, SL_POT_FREE>(v, s);
-    case 8: return launch_pass_t<T, 8, SL_POT_FREE>(v, s);
-    default: return hipErrorInvalidValue;
+  switch (nf) {
+    case 1: return pick_t<T, 1, SL_POT_FREE>(t);
+    case 2: return pick_t<T, 2, SL_POT_FREE>(t);
+    case 3: return pick_t<T, 3, SL_POT_FREE>(t);
+    case 4: return pick_t<T, 4, SL_POT_FREE>(t);
+    case 5: return pick_t<T, 5, SL_POT_FREE>(t);
+    case 6: return pick_t<T, 6, SL_POT_FREE>(t);
+    case 7: return pick_t<T, 7, SL_POT_FREE>(t);
+    default: return pick_t<T, 8, SL_POT_FREE>(t);
   }
+}
+
+PassKernel pick(int prec, int pot, int nf, const Tile& t) {
+  return prec == SL_FP32 ? pick_prec<float>(pot, nf, t) : pick_prec<double>(pot, nf, t);
 }
 
 }  // namespace
 
 hipError_t launch_pass(const LatView& v, hipStream_t s) {
-  return v.prec == SL_FP32 ? dispatch_pass<float>(v, s) : dispatch_pass<double>(v, s);
+  if (v.nf < 1 || v.nf > kMaxFields) return hipErrorInvalidValue;
+  if (v.nf > 2 && (v.tile.vx != 1 || v.tile.pf != 1)) return hipErrorInvalidValue;
+  const PassKernel k = pick(v.prec, v.pot, v.nf, v.tile);
+  hipLaunchKernelGGL(k.fn, dim3(v.tile.nblocks()), dim3(kBlock), k.lds, s, make_params(v));
+  return hipGetLastError();
+}
+
+PassParams pass_params(const LatView& v) { return make_params(v); }
+
+hipError_t launch_batched_pass(int prec, int pot, int nf, const Tile& shape, size_t lds,
+                               const PassParams* runs_dev, const int* start_dev, int nruns,
+                               int grid, hipStream_t s) {
+  const PassKernel k = pick(prec, pot, nf, shape);
+  hipLaunchKernelGGL(k.bfn, dim3(grid), dim3(kBlock), lds, s, runs_dev, start_dev, nruns);
+  return hipGetLastError();
+}
+
+int batched_blocks_per_cu(int prec, int pot, int nf, const Tile& shape, size_t lds) {
+  const PassKernel k = pick(prec, pot, nf, shape);
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k.bfn, kBlock, lds) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+size_t pass_lds_bytes(int prec, int nf, const Tile& t) {
+  return size_t(2) * nf * (t.tx * t.vx + 2) * (t.ty + 2) * (prec == SL_FP32 ? 4 : 8);
+}
+
+hipError_t launch_batched_finalize(const BatchRun* runs_dev, int nruns, double w, double w_next,
+                                   double h, int has_next, int end_of_step, hipStream_t s) {
+  hipLaunchKernelGGL(batched_finalize_kernel, dim3(nruns), dim3(kBlock), 0, s, runs_dev, w, w_next,
+                     h, has_next, end_of_step);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_begin(const BatchRun* runs_dev, int nruns, double w, double h,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(batched_begin_kernel, dim3((nruns + 255) / 256), dim3(256), 0, s, runs_dev,
+                     nruns, w, h);
+  return hipGetLastError();
+}
+
+int pass_blocks_per_cu(int prec, int pot, int nf, const Tile& t) {
+  const PassKernel k = pick(prec, pot, nf, t);
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k.fn, kBlock, k.lds) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
 }
 
 hipError_t launch_stage_finalize(const LatView& v, double w, double w_next, double h, int has_next,

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <utility>
@@ -142,33 +143,83 @@ bool config_ok(const sl_config* c, std::string* why) {
   return true;
 }
 
-// Default launch shape of the fused pass for side n.
-Tile make_tile(int n, int tx, int tz) {
+constexpr long kMaxPassBlocks = 65536;  // bound of the per-block partial-sum buffer
+
+// Tile geometry for lanes tx (16/32/64), vx sites per lane, tz planes and
+// prefetch depth pf.
+Tile tile_geometry(int n, int tx, int vx, int tz, int pf) {
   Tile t;
-  if (tx <= 0) tx = n >= 64 ? 64 : (n >= 32 ? 32 : 16);
   t.tx = tx;
+  t.vx = vx;
+  t.pf = pf;
   t.logtx = tx == 64 ? 6 : (tx == 32 ? 5 : 4);
   t.ty = kBlock / tx;
-  t.ntx = (n + t.tx - 1) / t.tx;
+  t.ntx = (n + tx * vx - 1) / (tx * vx);
   t.nty = (n + t.ty - 1) / t.ty;
-  if (tz <= 0) {
-    // enough z-chunks for >= ~2048 workgroups, chunks no shorter than 8 planes
-    const long long xy = (long long)t.ntx * t.nty;
-    long long chunks = (2048 + xy - 1) / xy;
-    long long len = (n + chunks - 1) / chunks;
-    if (len < 8) len = 8;
-    if (len > n) len = n;
-    tz = int(len);
-  }
   t.tz = tz > n ? n : tz;
   t.ntz = (n + t.tz - 1) / t.tz;
   return t;
 }
 
-size_t partial_doubles(const Tile& t) {
-  size_t need = size_t(t.nblocks()) * 6;
+// z-chunk length for a shape: the grid should fill the resident capacity
+// (blocks_per_cu * cus) in as few full rounds as possible, since a partial
+// last round leaves most CUs idle; cost = rounds * (chunk + 2 halo planes).
+int pick_tz(int n, int nxy, long resident) {
+  double best = 1e300;
+  int best_len = n;
+  for (int nz = 1; nz <= n; ++nz) {
+    const int len = (n + nz - 1) / nz;
+    const long z = (n + len - 1) / len;
+    const long blocks = long(nxy) * z;
+    if (blocks > kMaxPassBlocks) break;
+    const long rounds = (blocks + resident - 1) / resident;
+    double est = double(rounds) * (len + 2.0);
+    if (blocks * 2 < resident) est *= double(resident) / double(2 * blocks);  // too few waves
+    if (est < best - 1e-9) {
+      best = est;
+      best_len = len;
+    }
+  }
+  return best_len;
+}
+
+// Default lanes / sites-per-lane / prefetch depth for side n.
+void default_shape(int n, int prec, int nf, int* tx, int* vx, int* pf) {
+  *vx = (nf <= 2 && n % 2 == 0 && n >= 32) ? 2 : 1;
+  *pf = nf <= 2 ? 2 : 1;
+  (void)prec;
+  const int width = n / *vx;
+  *tx = width >= 64 ? 64 : (width >= 32 ? 32 : 16);
+}
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return 256;
+  return cus;
+}
+
+size_t partial_doubles() {
+  const size_t pass = size_t(kMaxPassBlocks) * 6;
   const size_t diag = size_t(4096) * 2 * (5 * kMaxFields + 1);
-  return need > diag ? need : diag;
+  return pass > diag ? pass : diag;
+}
+
+// Process-wide cache of autotuned pass shapes keyed by (device, n, fields,
+// precision, potential family).
+struct TuneKey {
+  int dev, n, nf, prec, pot;
+  bool operator==(const TuneKey& o) const {
+    return dev == o.dev && n == o.n && nf == o.nf && prec == o.prec && pot == o.pot;
+  }
+};
+struct TuneVal {
+  int tx, vx, tz, pf;
+};
+std::vector<std::pair<TuneKey, TuneVal>>& tune_cache() {
+  static std::vector<std::pair<TuneKey, TuneVal>> c;
+  return c;
 }
 
 }  // namespace
@@ -193,6 +244,8 @@ struct sl_lattice {
   sl_energies_t* energies_dev = nullptr;
   double* spec_dev = nullptr;
   bool timing = false;
+  sl_batch* batch = nullptr;  // batch this lattice belongs to, if any
+  int tz_user = 0;  // 0: z-chunk chosen from the occupancy of the pass kernel
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
 };
 
@@ -214,6 +267,17 @@ sl_status require_state(sl_lattice* L) {
   return SL_OK;
 }
 
+// Apply a pass shape; tz = 0 picks the z-chunk from the kernel's occupancy.
+void retile(sl_lattice* L, int tx, int vx, int tz, int pf) {
+  const int n = L->cfg.n;
+  Tile t = tile_geometry(n, tx, vx, n, pf);
+  if (tz <= 0) {
+    const int bpc = L->pot_set ? pass_blocks_per_cu(L->cfg.precision, L->v.pot, L->cfg.nfields, t) : 1;
+    tz = pick_tz(n, t.ntx * t.nty, long(bpc) * device_cus());
+  }
+  L->v.tile = tile_geometry(n, tx, vx, tz, pf);
+}
+
 void refresh_m2max(sl_lattice* L) {
   double d2[kMaxFields];
   L->m2max = 0.0;
@@ -230,6 +294,7 @@ void free_all(sl_lattice* L) {
   }
   if (L->v.sc) (void)hipFree(L->v.sc);
   if (L->v.partials) (void)hipFree(L->v.partials);
+  if (L->v.sink) (void)hipFree(L->v.sink);
   if (L->sums_dev) (void)hipFree(L->sums_dev);
   if (L->energies_dev) (void)hipFree(L->energies_dev);
   if (L->spec_dev) (void)hipFree(L->spec_dev);
@@ -290,8 +355,7 @@ size_t sl_footprint_bytes(const sl_config* cfg) {
   if (!config_ok(cfg, &why)) return 0;
   const size_t n3 = size_t(cfg->n) * cfg->n * cfg->n;
   const size_t elem = cfg->precision == SL_FP32 ? 4 : 8;
-  const Tile t = make_tile(cfg->n, 0, 0);
-  return 4 * n3 * cfg->nfields * elem + partial_doubles(t) * sizeof(double) + sizeof(DevScalars) +
+  return 4 * n3 * cfg->nfields * elem + partial_doubles() * sizeof(double) + kSinkBytes + sizeof(DevScalars) +
          sizeof(double) * (5 * kMaxFields + 1) + sizeof(sl_energies_t) +
          sizeof(double) * 3 * kMaxBins;
 }
@@ -335,8 +399,12 @@ sl_status sl_lattice_create(const sl_config* cfg, void* hip_stream, sl_lattice**
   v.bg.mpl2 = cfg->mpl * cfg->mpl;
   v.bg.L = cfg->L;
   v.bg.expand = cfg->expansion == SL_EXPAND_SELF ? 1 : 0;
-  v.tile = make_tile(cfg->n, 0, 0);
-  L->partials_n = partial_doubles(v.tile);
+  {
+    int tx, vx, pf;
+    default_shape(cfg->n, cfg->precision, cfg->nfields, &tx, &vx, &pf);
+    v.tile = tile_geometry(cfg->n, tx, vx, cfg->n, pf);
+  }
+  L->partials_n = partial_doubles();
   L->a_host = cfg->a0;
 
   const size_t fbytes = L->n3 * cfg->nfields * L->elem;
@@ -347,6 +415,7 @@ sl_status sl_lattice_create(const sl_config* cfg, void* hip_stream, sl_lattice**
   }
   ok = ok && hipMalloc(reinterpret_cast<void**>(&v.sc), sizeof(DevScalars)) == hipSuccess;
   ok = ok && hipMalloc(reinterpret_cast<void**>(&v.partials), L->partials_n * sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc(&v.sink, kSinkBytes) == hipSuccess;
   ok = ok && hipMalloc(reinterpret_cast<void**>(&L->sums_dev), sizeof(double) * (5 * kMaxFields + 1)) == hipSuccess;
   ok = ok && hipMalloc(reinterpret_cast<void**>(&L->energies_dev), sizeof(sl_energies_t)) == hipSuccess;
   ok = ok && hipMalloc(reinterpret_cast<void**>(&L->spec_dev), sizeof(double) * 3 * kMaxBins) == hipSuccess;
@@ -371,6 +440,7 @@ sl_status sl_lattice_create(const sl_config* cfg, void* hip_stream, sl_lattice**
 
 sl_status sl_lattice_destroy(sl_lattice* L) {
   if (!L) return SL_OK;
+  if (L->batch) (void)sl_batch_remove(L->batch, L);
   (void)hipStreamSynchronize(L->stream);
   free_all(L);
   delete L;
@@ -401,6 +471,15 @@ sl_status sl_set_potential(sl_lattice* L, int32_t kind, const double* params, in
   L->pot_kind = kind;
   L->pot_set = true;
   refresh_m2max(L);
+  const TuneKey key{L->device, L->cfg.n, L->cfg.nfields, L->cfg.precision, kind};
+  for (const auto& kv : tune_cache()) {
+    if (kv.first == key) {
+      L->tz_user = kv.second.tz;
+      retile(L, kv.second.tx, kv.second.vx, kv.second.tz, kv.second.pf);
+      return SL_OK;
+    }
+  }
+  retile(L, L->v.tile.tx, L->v.tile.vx, L->tz_user, L->v.tile.pf);
   return SL_OK;
 }
 
@@ -494,6 +573,18 @@ sl_status sl_set_fields(sl_lattice* L, const double* phi, const double* pi, doub
   return SL_OK;
 }
 
+namespace {
+sl_status check_stable(sl_lattice* L, double dt, int order) {
+  const double dx = L->cfg.L / L->cfg.n;
+  const double omax = std::sqrt(12.0 / (dx * dx) + L->a_host * L->a_host * L->m2max);
+  const double lim = stability_limit_for(order);
+  if (omax * std::fabs(dt) > lim)
+    return fail(SL_E_UNSTABLE, "omega_max*|dt| = %.4f exceeds the order-%d stability limit %.4f",
+                omax * std::fabs(dt), order, lim);
+  return SL_OK;
+}
+}  // namespace
+
 sl_status sl_evolve(sl_lattice* L, int64_t steps, double dt, int32_t order) {
   sl_status st = require_state(L);
   if (st != SL_OK) return st;
@@ -501,12 +592,8 @@ sl_status sl_evolve(sl_lattice* L, int64_t steps, double dt, int32_t order) {
   if (!std::isfinite(dt)) return fail(SL_E_INVALID, "dt must be finite");
   const std::vector<double> w = weights_for(order);
   if (w.empty()) return fail(SL_E_INVALID, "order must be 2, 4, 6 or 8 (got %d)", order);
-  const double dx = L->cfg.L / L->cfg.n;
-  const double omax = std::sqrt(12.0 / (dx * dx) + L->a_host * L->a_host * L->m2max);
-  const double lim = stability_limit_for(order);
-  if (omax * std::fabs(dt) > lim)
-    return fail(SL_E_UNSTABLE, "omega_max*|dt| = %.4f exceeds the order-%d stability limit %.4f",
-                omax * std::fabs(dt), order, lim);
+  st = check_stable(L, dt, order);
+  if (st != SL_OK) return st;
   if (steps == 0) return SL_OK;
   const int s = int(w.size());
   HIP_TRY(launch_begin(L->v, w[0], dt, L->stream));
@@ -640,23 +727,395 @@ sl_status sl_kernel_timing(sl_lattice* L, int64_t* passes, double* total_ms) {
   return SL_OK;
 }
 
-sl_status sl_get_tile(sl_lattice* L, int32_t* tx, int32_t* ty, int32_t* tz) {
-  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
-  if (tx) *tx = L->v.tile.tx;
-  if (ty) *ty = L->v.tile.ty;
-  if (tz) *tz = L->v.tile.tz;
+
+sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_only,
+                      int32_t* tx_out, int32_t* vx_out, int32_t* tz_out, int32_t* pf_out,
+                      double* best_ms) {
+  sl_status st = require_state(L);
+  if (st != SL_OK) return st;
+  if (reps < 1 || reps > 100) return fail(SL_E_INVALID, "reps must be in [1, 100]");
+  if (vx_only != 0 && vx_only != 1 && vx_only != 2 && vx_only != 4)
+    return fail(SL_E_INVALID, "vx_only must be 0, 1, 2 or 4");
+  if (pf_only != 0 && pf_only != 1 && pf_only != 2) return fail(SL_E_INVALID, "pf_only must be 0, 1 or 2");
+  const int n = L->cfg.n;
+  const bool many = L->cfg.nfields > 2;
+  struct Cand {
+    int tx, vx, tz, pf;
+  };
+  std::vector<Cand> cands;
+  for (int vx : {1, 2, 4}) {
+    if (n % vx != 0 || (many && vx != 1) || (vx_only && vx != vx_only)) continue;
+    for (int tx : {16, 32, 64}) {
+      if (tx * vx > 2 * n && tx != 16) continue;  // tile far wider than the lattice
+      for (int pf : {1, 2}) {
+        if ((many && pf != 1) || (pf_only && pf != pf_only)) continue;
+        std::vector<int> tzs = {0};
+        for (int d : {16, 8, 4, 2}) {
+          const int tz = n / d;
+          if (tz >= 8 && std::find(tzs.begin(), tzs.end(), tz) == tzs.end()) tzs.push_back(tz);
+        }
+        for (int tz : tzs) {
+          const Tile t = tile_geometry(n, tx, vx, tz > 0 ? tz : n, pf);
+          if (long(t.nblocks()) > kMaxPassBlocks) continue;
+          cands.push_back({tx, vx, tz, pf});
+        }
+      }
+    }
+  }
+  if (cands.empty()) return fail(SL_E_INVALID, "no pass shape fits these constraints");
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  const Tile saved = L->v.tile;
+  const int saved_tz = L->tz_user;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  double best = 1e300;
+  Cand win = cands[0];
+  hipError_t err = hipSuccess;
+  for (const Cand& c : cands) {
+    retile(L, c.tx, c.vx, c.tz, c.pf);
+    // a pass without its finalize leaves the state untouched: it reads the
+    // current buffer and overwrites only the spare buffer and the partials
+    err = launch_pass(L->v, L->stream);
+    if (err != hipSuccess) break;
+    double t_min = 1e300;
+    for (int r = 0; r < reps && err == hipSuccess; ++r) {
+      err = hipEventRecord(e0, L->stream);
+      if (err == hipSuccess) err = launch_pass(L->v, L->stream);
+      if (err == hipSuccess) err = hipEventRecord(e1, L->stream);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err == hipSuccess && ms < t_min) t_min = ms;
+    }
+    if (err != hipSuccess) break;
+    if (t_min < best) {
+      best = t_min;
+      win = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) {
+    L->v.tile = saved;
+    L->tz_user = saved_tz;
+    return fail(SL_E_DEVICE, "autotune: %s", hipGetErrorString(err));
+  }
+  L->tz_user = win.tz;
+  retile(L, win.tx, win.vx, win.tz, win.pf);
+  const TuneKey key{L->device, n, L->cfg.nfields, L->cfg.precision, L->v.pot};
+  bool found = false;
+  for (auto& kv : tune_cache()) {
+    if (kv.first == key) {
+      kv.second = {win.tx, win.vx, win.tz, win.pf};
+      found = true;
+    }
+  }
+  if (!found) tune_cache().push_back({key, {win.tx, win.vx, win.tz, win.pf}});
+  if (tx_out) *tx_out = win.tx;
+  if (vx_out) *vx_out = win.vx;
+  if (tz_out) *tz_out = L->v.tile.tz;
+  if (pf_out) *pf_out = win.pf;
+  if (best_ms) *best_ms = best;
   return SL_OK;
 }
 
-sl_status sl_set_tile(sl_lattice* L, int32_t tx, int32_t tz) {
+sl_status sl_autotune_forget(void) {
+  tune_cache().clear();
+  return SL_OK;
+}
+
+sl_status sl_get_tile(sl_lattice* L, int32_t* tx, int32_t* vx, int32_t* ty, int32_t* tz,
+                      int32_t* pf) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  if (tx) *tx = L->v.tile.tx;
+  if (vx) *vx = L->v.tile.vx;
+  if (ty) *ty = L->v.tile.ty;
+  if (tz) *tz = L->v.tile.tz;
+  if (pf) *pf = L->v.tile.pf;
+  return SL_OK;
+}
+
+sl_status sl_set_tile(sl_lattice* L, int32_t tx, int32_t vx, int32_t tz, int32_t pf) {
   if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
   if (tx != 16 && tx != 32 && tx != 64) return fail(SL_E_INVALID, "tx must be 16, 32 or 64");
+  if (vx != 1 && vx != 2 && vx != 4) return fail(SL_E_INVALID, "vx must be 1, 2 or 4");
+  if (L->cfg.n % vx != 0) return fail(SL_E_INVALID, "vx = %d needs n divisible by %d", vx, vx);
+  if (pf != 1 && pf != 2) return fail(SL_E_INVALID, "pf must be 1 or 2");
+  if (L->cfg.nfields > 2 && (vx != 1 || pf != 1))
+    return fail(SL_E_INVALID, "more than two fields run with vx = 1 and pf = 1 only");
   if (tz < 0 || tz > L->cfg.n) return fail(SL_E_INVALID, "tz must be in [0, n]");
-  const Tile t = make_tile(L->cfg.n, tx, tz);
-  if (size_t(t.nblocks()) * 6 > L->partials_n)
-    return fail(SL_E_INVALID, "tile gives too many workgroups for the partial-sum buffer");
+  const Tile t = tile_geometry(L->cfg.n, tx, vx, tz > 0 ? tz : L->cfg.n, pf);
+  if (long(t.nblocks()) > kMaxPassBlocks)
+    return fail(SL_E_INVALID, "tile gives %d workgroups (limit %ld)", t.nblocks(), kMaxPassBlocks);
   HIP_TRY(hipStreamSynchronize(L->stream));
-  L->v.tile = t;
+  L->tz_user = tz;
+  retile(L, tx, vx, tz, pf);
+  return SL_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Batches: many lattices (same storage precision, potential family, field
+// count and per-lane shape; any sizes and parameters) advanced together.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct sl_batch {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<sl_lattice*> runs;
+  int prec = -1, pot = -1, nf = -1;
+  Tile shape{};  // carries vx and pf of every member
+  PassParams* pass_dev = nullptr;
+  BatchRun* run_dev = nullptr;
+  int* start_dev = nullptr;
+  int cap = 0;
+  bool dirty = true;
+  int total_tiles = 0;
+  size_t lds = 0;
+  int grid = 0;
+  uint64_t version = 0;
+  hipEvent_t ev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int64_t g_steps = -1;
+  double g_dt = 0.0;
+  int g_order = 0;
+  uint64_t g_version = ~0ull;
+};
+
+namespace {
+
+void batch_drop_graph(sl_batch* B) {
+  if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  B->gexec = nullptr;
+  B->graph = nullptr;
+  B->g_version = ~0ull;
+}
+
+sl_status batch_upload(sl_batch* B) {
+  const int R = int(B->runs.size());
+  if (R > B->cap) {
+    batch_drop_graph(B);
+    if (B->pass_dev) (void)hipFree(B->pass_dev);
+    if (B->run_dev) (void)hipFree(B->run_dev);
+    if (B->start_dev) (void)hipFree(B->start_dev);
+    B->pass_dev = nullptr;
+    B->run_dev = nullptr;
+    B->start_dev = nullptr;
+    int cap = B->cap ? B->cap : 16;
+    while (cap < R) cap *= 2;
+    if (hipMalloc(&B->pass_dev, sizeof(PassParams) * cap) != hipSuccess ||
+        hipMalloc(&B->run_dev, sizeof(BatchRun) * cap) != hipSuccess ||
+        hipMalloc(&B->start_dev, sizeof(int) * (cap + 1)) != hipSuccess) {
+      B->cap = 0;
+      return fail(SL_E_NOMEM, "cannot allocate the batch run table");
+    }
+    B->cap = cap;
+  }
+  std::vector<PassParams> pp(R);
+  std::vector<BatchRun> br(R);
+  std::vector<int> start(R + 1, 0);
+  size_t lds = 0;
+  for (int r = 0; r < R; ++r) {
+    sl_lattice* L = B->runs[r];
+    pp[r] = pass_params(L->v);
+    br[r].sc = L->v.sc;
+    br[r].partials = L->v.partials;
+    br[r].bg = L->v.bg;
+    br[r].ntiles = L->v.tile.nblocks();
+    br[r].pad = 0;
+    start[r + 1] = start[r] + br[r].ntiles;
+    const size_t l = pass_lds_bytes(B->prec, B->nf, L->v.tile);
+    if (l > lds) lds = l;
+  }
+  HIP_TRY(hipMemcpyAsync(B->pass_dev, pp.data(), sizeof(PassParams) * R, hipMemcpyHostToDevice, B->stream));
+  HIP_TRY(hipMemcpyAsync(B->run_dev, br.data(), sizeof(BatchRun) * R, hipMemcpyHostToDevice, B->stream));
+  HIP_TRY(hipMemcpyAsync(B->start_dev, start.data(), sizeof(int) * (R + 1), hipMemcpyHostToDevice, B->stream));
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  B->total_tiles = start[R];
+  B->lds = lds;
+  const long resident = long(batched_blocks_per_cu(B->prec, B->pot, B->nf, B->shape, lds)) * device_cus();
+  B->grid = int(B->total_tiles < resident ? B->total_tiles : resident);
+  if (B->grid < 1) B->grid = 1;
+  B->dirty = false;
+  return SL_OK;
+}
+
+// Enqueue one batched evolve call on the batch stream.
+sl_status batch_enqueue(sl_batch* B, int64_t steps, double dt, const std::vector<double>& w) {
+  const int R = int(B->runs.size());
+  const int s = int(w.size());
+  HIP_TRY(launch_batched_begin(B->run_dev, R, w[0], dt, B->stream));
+  for (int64_t step = 0; step < steps; ++step) {
+    for (int j = 0; j < s; ++j) {
+      const bool last_stage = j == s - 1;
+      const int has_next = !(last_stage && step == steps - 1);
+      const double wn = last_stage ? w[0] : w[j + 1];
+      HIP_TRY(launch_batched_pass(B->prec, B->pot, B->nf, B->shape, B->lds, B->pass_dev,
+                                  B->start_dev, R, B->grid, B->stream));
+      HIP_TRY(launch_batched_finalize(B->run_dev, R, w[j], wn, dt, has_next, last_stage ? 1 : 0,
+                                      B->stream));
+    }
+  }
+  return SL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sl_status sl_batch_create(void* hip_stream, sl_batch** out) {
+  if (!out) return fail(SL_E_INVALID, "out is NULL");
+  *out = nullptr;
+  sl_batch* B = new (std::nothrow) sl_batch();
+  if (!B) return fail(SL_E_NOMEM, "host allocation failed");
+  if (hip_stream) {
+    B->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete B;
+      return fail(SL_E_DEVICE, "cannot create a HIP stream");
+    }
+    B->own_stream = true;
+  }
+  if (hipEventCreateWithFlags(&B->ev, hipEventDisableTiming) != hipSuccess) {
+    if (B->own_stream) (void)hipStreamDestroy(B->stream);
+    delete B;
+    return fail(SL_E_DEVICE, "cannot create a HIP event");
+  }
+  *out = B;
+  return SL_OK;
+}
+
+sl_status sl_batch_destroy(sl_batch* B) {
+  if (!B) return SL_OK;
+  (void)hipStreamSynchronize(B->stream);
+  for (sl_lattice* L : B->runs) L->batch = nullptr;
+  batch_drop_graph(B);
+  if (B->pass_dev) (void)hipFree(B->pass_dev);
+  if (B->run_dev) (void)hipFree(B->run_dev);
+  if (B->start_dev) (void)hipFree(B->start_dev);
+  if (B->ev) (void)hipEventDestroy(B->ev);
+  if (B->own_stream) (void)hipStreamDestroy(B->stream);
+  delete B;
+  return SL_OK;
+}
+
+sl_status sl_batch_add(sl_batch* B, sl_lattice* L) {
+  if (!B || !L) return fail(SL_E_INVALID, "batch or lattice handle is NULL");
+  sl_status st = require_state(L);
+  if (st != SL_OK) return st;
+  if (L->batch) return fail(SL_E_INVALID, "lattice already belongs to a batch");
+  if (B->runs.empty()) {
+    B->prec = L->cfg.precision;
+    B->pot = L->v.pot;
+    B->nf = L->cfg.nfields;
+    B->shape = L->v.tile;
+  } else if (L->cfg.precision != B->prec || L->v.pot != B->pot || L->cfg.nfields != B->nf ||
+             L->v.tile.vx != B->shape.vx || L->v.tile.pf != B->shape.pf) {
+    return fail(SL_E_INVALID,
+                "batch members share precision, potential family, field count, vx and pf");
+  }
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  B->runs.push_back(L);
+  L->batch = B;
+  B->dirty = true;
+  ++B->version;
+  return SL_OK;
+}
+
+sl_status sl_batch_remove(sl_batch* B, sl_lattice* L) {
+  if (!B || !L) return fail(SL_E_INVALID, "batch or lattice handle is NULL");
+  for (size_t i = 0; i < B->runs.size(); ++i) {
+    if (B->runs[i] == L) {
+      HIP_TRY(hipStreamSynchronize(B->stream));
+      B->runs.erase(B->runs.begin() + long(i));
+      L->batch = nullptr;
+      B->dirty = true;
+      ++B->version;
+      if (B->runs.empty()) B->prec = B->pot = B->nf = -1;
+      return SL_OK;
+    }
+  }
+  return fail(SL_E_INVALID, "lattice is not in this batch");
+}
+
+sl_status sl_batch_count(const sl_batch* B, int32_t* count) {
+  if (!B || !count) return fail(SL_E_INVALID, "batch handle or count is NULL");
+  *count = int32_t(B->runs.size());
+  return SL_OK;
+}
+
+sl_status sl_batch_step(sl_batch* B, int64_t steps, double dt, int32_t order) {
+  if (!B) return fail(SL_E_INVALID, "batch handle is NULL");
+  if (steps < 0) return fail(SL_E_INVALID, "steps must be >= 0");
+  if (!std::isfinite(dt)) return fail(SL_E_INVALID, "dt must be finite");
+  const std::vector<double> w = weights_for(order);
+  if (w.empty()) return fail(SL_E_INVALID, "order must be 2, 4, 6 or 8 (got %d)", order);
+  if (B->runs.empty() || steps == 0) return SL_OK;
+  for (sl_lattice* L : B->runs) {
+    sl_status st = check_stable(L, dt, order);
+    if (st != SL_OK) return st;
+  }
+  if (B->dirty) {
+    sl_status st = batch_upload(B);
+    if (st != SL_OK) return st;
+  }
+  // order after each member's own stream
+  for (sl_lattice* L : B->runs) {
+    if (L->stream == B->stream) continue;
+    HIP_TRY(hipEventRecord(B->ev, L->stream));
+    HIP_TRY(hipStreamWaitEvent(B->stream, B->ev, 0));
+  }
+  // one captured graph per (steps, dt, order, membership); replayed when unchanged
+  if (!(B->gexec && B->g_steps == steps && B->g_dt == dt && B->g_order == order &&
+        B->g_version == B->version)) {
+    batch_drop_graph(B);
+    HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+    sl_status st = batch_enqueue(B, steps, dt, w);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(B->stream, &g);
+    if (st != SL_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(SL_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    B->graph = g;
+    HIP_TRY(hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
+    B->g_steps = steps;
+    B->g_dt = dt;
+    B->g_order = order;
+    B->g_version = B->version;
+  }
+  HIP_TRY(hipGraphLaunch(B->gexec, B->stream));
+  // members' later work waits for the batch
+  HIP_TRY(hipEventRecord(B->ev, B->stream));
+  for (sl_lattice* L : B->runs) {
+    if (L->stream == B->stream) continue;
+    HIP_TRY(hipStreamWaitEvent(L->stream, B->ev, 0));
+  }
+  return SL_OK;
+}
+
+sl_status sl_batch_synchronize(sl_batch* B) {
+  if (!B) return fail(SL_E_INVALID, "batch handle is NULL");
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  for (sl_lattice* L : B->runs) {
+    DevScalars S;
+    sl_status st = read_scalars(L, &S);
+    if (st != SL_OK) return st;
+  }
+  return SL_OK;
+}
+
+sl_status sl_device_memory(size_t* free_bytes, size_t* total_bytes) {
+  size_t f = 0, t = 0;
+  HIP_TRY(hipMemGetInfo(&f, &t));
+  if (free_bytes) *free_bytes = f;
+  if (total_bytes) *total_bytes = t;
   return SL_OK;
 }
 

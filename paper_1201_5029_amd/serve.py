@@ -1,0 +1,121 @@
+"""Serving loop: continuous batching of lattice runs on one GPU.
+
+Requests (a workload recipe, a step count and an arrival time) are admitted
+while a slot is free and their device footprint fits the memory budget; an
+admitted run's state stays resident on the device, joins the shared batch at
+the next tick and leaves it when its steps are done.  Every tick advances all
+resident runs by the same number of steps with one captured batch step (one
+fused pass per stage over every run's tiles), so work of runs that arrived at
+different times overlaps on the device.  A run's result is bit-identical to
+evolving it alone (same tile shape), because a batch step and an evolve call
+apply the same per-tile arithmetic and the pending-drift bookkeeping makes
+evolve(a) + evolve(b) equal to evolve(a + b).
+
+The ensemble use is the separate-universe (Delta N) scan over initial
+homogeneous values that the paper names (Sec. 2.4 and Sec. 4): each result
+carries N = ln a at the end of its run.
+"""
+import math
+import time
+from collections import deque
+
+import numpy as np
+
+from .symlat import Batch, device_memory, footprint_bytes, from_recipe
+
+
+class Request:
+    def __init__(self, rid, recipe, arrival, steps=None):
+        self.id = rid
+        self.recipe = recipe
+        self.arrival = float(arrival)
+        self.steps = int(steps if steps is not None else recipe["steps"])
+        self.footprint = footprint_bytes(n=recipe["n"], nfields=recipe["nfields"], L=recipe["L"],
+                                         precision=recipe.get("precision", "f64"))
+
+
+def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
+          keep_fields=False, clock=time.perf_counter, sleep=time.sleep):
+    """Run the request loop to completion.  Returns (results, stats).
+
+    results: one dict per request with id, n, arrival, admitted, completed,
+    latency (s, completion - arrival), eta, a, p_a, efolds = ln a, and the
+    final fields when keep_fields.  stats: p50/p99 latency, makespan, field
+    site-updates, aggregate field-site-updates/s, admissions deferred for
+    memory, peak resident runs."""
+    pending = deque(sorted(requests, key=lambda r: r.arrival))
+    waiting = deque()
+    active = {}  # id -> [request, lattice, steps_done, admitted_at]
+    results = []
+    if hbm_budget is None:
+        free, _ = device_memory()
+        hbm_budget = int(0.9 * free)
+    used = 0
+    deferred = 0
+    peak = 0
+    batch = Batch()
+    t0 = clock()
+    try:
+        while pending or waiting or active:
+            now = clock() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            # admission: arrival order, a free slot and the footprint must fit
+            while waiting and len(active) < max_slots:
+                req = waiting[0]
+                if req.footprint > hbm_budget:
+                    raise ValueError("request %r needs %d bytes, more than the budget %d"
+                                     % (req.id, req.footprint, hbm_budget))
+                if used + req.footprint > hbm_budget:
+                    deferred += 1
+                    break
+                waiting.popleft()
+                lat = from_recipe(req.recipe)
+                batch.add(lat)
+                used += req.footprint
+                active[req.id] = [req, lat, 0, clock() - t0]
+            peak = max(peak, len(active))
+            if not active:
+                if pending:
+                    sleep(max(0.0, pending[0].arrival - (clock() - t0)))
+                continue
+            k = min(tick_steps, min(a[0].steps - a[2] for a in active.values()))
+            batch.step(k, dt, order)
+            batch.synchronize()
+            done_at = clock() - t0
+            for rid in list(active):
+                entry = active[rid]
+                entry[2] += k
+                req, lat = entry[0], entry[1]
+                if entry[2] >= req.steps:
+                    eta, a, p_a = lat.background()
+                    res = dict(id=rid, n=req.recipe["n"], arrival=req.arrival,
+                               admitted=entry[3], completed=done_at,
+                               latency=done_at - req.arrival, eta=eta, a=a, p_a=p_a,
+                               efolds=math.log(a), steps=req.steps)
+                    if keep_fields:
+                        res["phi"], res["pi"] = lat.get_fields()
+                    results.append(res)
+                    batch.remove(lat)
+                    lat.close()
+                    used -= req.footprint
+                    del active[rid]
+    finally:
+        for entry in active.values():
+            entry[1].close()
+        batch.close()
+    makespan = clock() - t0
+    lat_s = np.array([r["latency"] for r in results]) if results else np.zeros(1)
+    sups = sum(r["n"] ** 3 * req_nf(requests, r["id"]) * r["steps"] for r in results)
+    stats = dict(p50_s=float(np.percentile(lat_s, 50)), p99_s=float(np.percentile(lat_s, 99)),
+                 makespan_s=makespan, field_site_updates=sups,
+                 field_site_updates_per_s=sups / makespan if makespan > 0 else float("nan"),
+                 deferred_for_memory=deferred, peak_resident=peak, runs=len(results))
+    return sorted(results, key=lambda r: r["id"]), stats
+
+
+def req_nf(requests, rid):
+    for r in requests:
+        if r.id == rid:
+            return r.recipe["nfields"]
+    return 0

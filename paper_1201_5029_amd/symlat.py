@@ -27,7 +27,10 @@ EXPORTS = (
     "sl_get_fields", "sl_set_fields", "sl_get_background", "sl_synchronize",
     "sl_footprint_bytes", "sl_last_error", "sl_composition_weights",
     "sl_stability_limit", "sl_set_kernel_timing", "sl_kernel_timing",
-    "sl_get_tile", "sl_set_tile",
+    "sl_get_tile", "sl_set_tile", "sl_hbm_copy_bench",
+    "sl_batch_create", "sl_batch_destroy", "sl_batch_add", "sl_batch_remove",
+    "sl_batch_count", "sl_batch_step", "sl_batch_synchronize", "sl_device_memory",
+    "sl_autotune", "sl_autotune_forget",
 )
 
 
@@ -83,8 +86,19 @@ def load():
         "sl_stability_limit": (D, [I32]),
         "sl_set_kernel_timing": (I32, [P, I32]),
         "sl_kernel_timing": (I32, [P, ctypes.POINTER(I64), dp]),
-        "sl_get_tile": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
-        "sl_set_tile": (I32, [P, I32, I32]),
+        "sl_get_tile": (I32, [P] + [ctypes.POINTER(I32)] * 5),
+        "sl_set_tile": (I32, [P, I32, I32, I32, I32]),
+        "sl_hbm_copy_bench": (I32, [ctypes.c_size_t, I32, dp]),
+        "sl_batch_create": (I32, [P, ctypes.POINTER(P)]),
+        "sl_batch_destroy": (I32, [P]),
+        "sl_batch_add": (I32, [P, P]),
+        "sl_batch_remove": (I32, [P, P]),
+        "sl_batch_count": (I32, [P, ctypes.POINTER(I32)]),
+        "sl_batch_step": (I32, [P, I64, D, I32]),
+        "sl_batch_synchronize": (I32, [P]),
+        "sl_device_memory": (I32, [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+        "sl_autotune": (I32, [P, I32, I32, I32] + [ctypes.POINTER(I32)] * 4 + [dp]),
+        "sl_autotune_forget": (I32, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -127,8 +141,26 @@ def stability_limit(order):
     return load().sl_stability_limit(int(order))
 
 
+def hbm_copy_bench(nbytes, iters=20):
+    """Achieved read+write GB/s of a plain device copy of nbytes."""
+    g = ctypes.c_double()
+    _check(load().sl_hbm_copy_bench(int(nbytes), int(iters), ctypes.byref(g)))
+    return g.value
+
+
 def footprint_bytes(**cfg):
     return int(load().sl_footprint_bytes(ctypes.byref(make_config(**cfg))))
+
+
+def autotune_forget():
+    _check(load().sl_autotune_forget())
+
+
+def device_memory():
+    """(free, total) device bytes."""
+    f, t = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load().sl_device_memory(ctypes.byref(f), ctypes.byref(t)))
+    return f.value, t.value
 
 
 class Lattice:
@@ -222,12 +254,23 @@ class Lattice:
 
     # -- launch shape and timing ---------------------------------------------
     def tile(self):
-        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(self._lib.sl_get_tile(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return a.value, b.value, c.value
+        """(tx lanes, vx sites per lane, ty rows, tz planes, pf prefetch depth)
+        of the fused pass."""
+        v = [ctypes.c_int32() for _ in range(5)]
+        _check(self._lib.sl_get_tile(self._h, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
-    def set_tile(self, tx, tz=0):
-        _check(self._lib.sl_set_tile(self._h, int(tx), int(tz)))
+    def set_tile(self, tx, vx=1, tz=0, pf=1):
+        _check(self._lib.sl_set_tile(self._h, int(tx), int(vx), int(tz), int(pf)))
+
+    def autotune(self, reps=3, vx_only=0, pf_only=0):
+        """Pick the fastest pass shape for this lattice; returns
+        ((tx, vx, tz, pf), best pass ms)."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        ms = ctypes.c_double()
+        _check(self._lib.sl_autotune(self._h, int(reps), int(vx_only), int(pf_only),
+                                     *[ctypes.byref(x) for x in v], ctypes.byref(ms)))
+        return tuple(x.value for x in v), ms.value
 
     def set_kernel_timing(self, enable):
         _check(self._lib.sl_set_kernel_timing(self._h, 1 if enable else 0))
@@ -236,6 +279,48 @@ class Lattice:
         n, ms = ctypes.c_int64(), ctypes.c_double()
         _check(self._lib.sl_kernel_timing(self._h, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+
+class Batch:
+    """Many lattices advanced together by one fused pass per stage."""
+
+    def __init__(self, stream=None):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        _check(self._lib.sl_batch_create(ctypes.c_void_p(stream or 0), ctypes.byref(h)))
+        self._h = h
+        self.members = []
+
+    def add(self, lat):
+        _check(self._lib.sl_batch_add(self._h, lat._h))
+        self.members.append(lat)
+
+    def remove(self, lat):
+        _check(self._lib.sl_batch_remove(self._h, lat._h))
+        self.members.remove(lat)
+
+    def __len__(self):
+        c = ctypes.c_int32()
+        _check(self._lib.sl_batch_count(self._h, ctypes.byref(c)))
+        return c.value
+
+    def step(self, steps, dt, order=4):
+        _check(self._lib.sl_batch_step(self._h, int(steps), float(dt), int(order)))
+
+    def synchronize(self):
+        _check(self._lib.sl_batch_synchronize(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.sl_batch_destroy(self._h)
+            self._h = None
+            self.members = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def from_recipe(r, stream=None):

@@ -167,7 +167,8 @@ def test_static_background_and_rad_matter_terms():
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n,tile", [(4, None), (20, None), (36, None), (70, None),
-                                    (36, (16, 5)), (36, (64, 7)), (33, (32, 1))])
+                                    (36, (16, 1, 5)), (36, (64, 1, 7)), (33, (32, 1, 1)),
+                                    (36, (32, 2, 5)), (20, (16, 2, 3)), (70, (64, 2, 9))])
 def test_ragged_tiles(n, tile):
     c, phi, pi = _preheat_state(n, seed=n)
     o, g = _pair(c, phi, pi, tile=tile)
@@ -179,11 +180,23 @@ def test_ragged_tiles(n, tile):
     assert max(ef, ep, ea, epa) <= FP64_TOL
 
 
+@pytest.mark.parametrize("n,tile", [(36, (32, 2, 5)), (38, (16, 1, 4)), (64, None)])
+def test_ragged_tiles_fp32(n, tile):
+    c, phi, pi = _preheat_state(n, seed=n + 1)
+    o, g = _pair(c, phi, pi, precision="f32", tile=tile)
+    g.evolve(20, c["dt"], 4)
+    o.evolve(20, c["dt"], 4)
+    gphi, gpi = g.get_fields()
+    e1, e2 = rel_l2(gphi, o.phi), rel_l2(gpi, o.pi)
+    say("ragged fp32", n, tile, g.tile(), e1, e2)
+    assert max(e1, e2) <= FP32_L2_TOL
+
+
 def test_tile_shapes_agree_bitwise_on_fields():
     """The field update at a site does not depend on the tile shape."""
     c, phi, pi = _preheat_state(40, seed=5)
     outs = []
-    for tile in [(16, 3), (32, 40), (64, 8)]:
+    for tile in [(16, 1, 3), (32, 2, 40), (64, 1, 8), (16, 2, 7), (64, 2, 0)]:
         g = gpu_lattice(40, c["L"], c["potential"], c["params"], phi, pi, mpl=c["mpl"],
                         expand=False, tile=tile)
         g.evolve(3, c["dt"], 4)
@@ -322,3 +335,24 @@ def test_error_paths():
     with pytest.raises(sl.SymlatError) as e:
         g.synchronize()
     assert e.value.status == 5  # SL_E_NONFINITE
+
+
+def test_autotune_keeps_state_and_parity():
+    """The autotuner's timing passes leave the state untouched, and the
+    tuned shape keeps FP64 parity with the oracle."""
+    c, phi, pi = _preheat_state(48, seed=48)
+    o, g = _pair(c, phi, pi)
+    f0, p0 = g.get_fields()
+    b0 = g.background()
+    shape, ms = g.autotune(reps=2)
+    say("autotuned", shape, ms, g.tile())
+    f1, p1 = g.get_fields()
+    assert np.array_equal(f0, f1) and np.array_equal(p0, p1) and g.background() == b0
+    g.evolve(20, c["dt"], 4)
+    o.evolve(20, c["dt"], 4)
+    ef, ep, ea, epa, _ = compare_state(g, o)
+    assert max(ef, ep, ea, epa) <= FP64_TOL
+    # lattices created later with the same key start with the tuned shape
+    g2 = gpu_lattice(48, c["L"], c["potential"], c["params"], phi, pi, mpl=c["mpl"])
+    assert g2.tile() == g.tile()
+    sl.symlat.autotune_forget()
