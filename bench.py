@@ -39,6 +39,8 @@ def parse():
     p.add_argument("--no-serve", action="store_true", help="skip the served ensemble")
     p.add_argument("--serve-runs", type=int, default=96)
     p.add_argument("--serve-steps", type=int, default=500)
+    p.add_argument("--tile", default=None,
+                   help="tx,vx,tz,pf pass shape instead of the autotuner's choice")
     return p.parse_args()
 
 
@@ -46,11 +48,44 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measure(sl, recipe, steps, warmup):
+def kernel_source_hash():
+    import hashlib
+    m = hashlib.sha1()
+    for f in ("kernels_step.hip", "device.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1201_5029_amd", "csrc", f), "rb") as fh:
+            m.update(fh.read())
+    return m.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision, tile):
+    """Calibrated FETCH_SIZE + WRITE_SIZE bytes per pass recorded under
+    profiles/ for this workload, precision and pass shape, or None when no
+    record matches or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "pass_kernel_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    h = kernel_source_hash()
+    tx, vx, _, tz, pf = tile
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if (f[0] == workload and f[1] == precision and [int(x) for x in f[2:6]] == [tx, vx, tz, pf]
+                and f[6] == h):
+            return int(f[7])
+    return None
+
+
+def measure(sl, recipe, steps, warmup, tile=None):
     lat = sl.from_recipe(recipe)
     order, dt = recipe["order"], recipe["dt"]
-    shape, best = lat.autotune(reps=3)
-    log("autotuned pass shape (tx, vx, tz, pf) =", shape, "best pass %.4f ms" % best)
+    if tile:
+        tx, vx, tz, pf = (int(x) for x in tile.split(","))
+        lat.set_tile(tx, vx, tz, pf)
+        log("pass shape fixed to", lat.tile())
+    else:
+        shape, best = lat.autotune(reps=5)
+        log("autotuned pass shape (tx, vx, tz, pf) =", shape, "best pass %.4f ms" % best)
     lat.evolve(warmup, dt, order)
     lat.synchronize()
     t0 = time.perf_counter()
@@ -142,7 +177,7 @@ def main():
     recipe = synth.preheat(n=args.n, order=args.order, dt=0.0025, steps=args.steps,
                            precision=args.precision)
     log("workload", recipe["workload"], args.n, "order", args.order, args.precision)
-    wall, passes, pass_ms, e, tile = measure(sl, recipe, args.steps, args.warmup)
+    wall, passes, pass_ms, e, tile = measure(sl, recipe, args.steps, args.warmup, args.tile)
     nf = recipe["nfields"]
     n3 = args.n ** 3
     b = 8 if args.precision == "f64" else 4
@@ -172,7 +207,9 @@ def main():
                    "n": args.n, "nfields": nf, "order": args.order, "stages": stages,
                    "tile": list(tile)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("preheat%d_order%d" % (args.n, args.order),
+                                                 args.precision, tile),
                      "kernel": "pass_kernel", "avg_launch_ms": avg_pass_s * 1e3,
                      "bytes_per_launch": bytes_per_pass},
         "friedmann_residual": e["friedmann_residual"],

@@ -223,7 +223,8 @@ sl_status sl_set_tile(sl_lattice* lat, int32_t tx, int32_t vx, int32_t tz, int32
 
 /* Autotuner: time the fused pass in candidate shapes (tx in {16, 32, 64},
  * vx in {1, 2, 4} dividing n, pf in {1, 2}, tz in {occupancy choice, n/16,
- * n/8, n/4, n/2}), best of `reps` HIP-event timings each, on the lattice's
+ * n/8, n/4, n/2}), best of `reps` HIP-event timings of two back-to-back
+ * passes each, on the lattice's
  * current state, which the timing passes leave unchanged.  vx_only / pf_only
  * (0 = free) restrict the search, e.g. to the per-lane shape of a batch.
  * The winner is applied and remembered for this process: lattices created

@@ -57,3 +57,54 @@ def test_fullsize_fp32_vs_fp64_and_residual():
     say("256^3 100 steps: residual f64", r64, "f32", r32, "rel-L2", rel_l2(f32, f64), rel_l2(p32, p64))
     assert r64 < 1e-9 and r32 < 1e-3
     assert rel_l2(f32, f64) < 1e-4 and rel_l2(p32, p64) < 1e-4
+
+
+def test_oscillon128_fp32_vs_oracle():
+    """Oscillon configuration at its full size (128^3, FP32 fields, 4th order,
+    white initial fluctuations built on the device) against the oracle's own
+    initial state and evolution, 20 steps."""
+    c = synth.oscillon(n=128, precision="f32")
+    g = sl.from_recipe(c)
+    g.evolve(20, c["dt"], c["order"])
+    gphi, gpi = g.get_fields()
+    resid = g.energies()["friedmann_residual"]
+    o = oracle.Lattice(128, c["L"], oracle.Potential(c["potential"], c["params"]), mpl=c["mpl"])
+    o.init_fluctuations(c["phi0"], c["pi0"], c["fluct"], c["amplitude"], c["seed"])
+    o.evolve(20, c["dt"], c["order"])
+    e1, e2 = rel_l2(gphi, o.phi), rel_l2(gpi, o.pi)
+    # the fluctuation part alone, to see FP32 storage error on the small field
+    e3 = rel_l2(gphi - gphi.mean(), o.phi - o.phi.mean())
+    say("oscillon 128^3 fp32 rel-L2", e1, e2, "fluct", e3, "residual", resid)
+    assert max(e1, e2) <= 1e-4 and resid <= 1e-3
+
+
+def test_qball512_fp32():
+    """Q-ball configuration at its full size (512^3, FP32 fields, 6th order):
+    FP32 against the FP64 library path (which is pinned to the oracle), the
+    Friedmann residual, and the same model at 32^3 with the same dx and dt
+    against the oracle."""
+    c = synth.qball(n=512, precision="f32")
+    g32 = sl.from_recipe(c)
+    g32.evolve(20, c["dt"], c["order"])
+    r32 = g32.energies()["friedmann_residual"]
+    f32, p32 = g32.get_fields()
+    g32.close()
+    g64 = sl.from_recipe(dict(c, precision="f64"))
+    g64.evolve(20, c["dt"], c["order"])
+    f64, p64 = g64.get_fields()
+    g64.close()
+    e1, e2 = rel_l2(f32, f64), rel_l2(p32, p64)
+    say("qball 512^3 fp32 vs fp64", e1, e2, "residual", r32)
+    assert max(e1, e2) <= 1e-4 and r32 <= 1e-3
+    del f32, p32, f64, p64
+    # same dx and dt on a 32^3 lattice, FP64 against the oracle
+    small = dict(c, n=32, L=c["L"] * 32 / 512, precision="f64")
+    g = sl.from_recipe(small)
+    g.evolve(20, c["dt"], c["order"])
+    o = oracle.Lattice(32, small["L"], oracle.Potential(c["potential"], c["params"]), mpl=c["mpl"])
+    o.init_fluctuations(c["phi0"], c["pi0"], c["fluct"], c["amplitude"], c["seed"])
+    o.evolve(20, c["dt"], c["order"])
+    gphi, gpi = g.get_fields()
+    ef, ep = max_rel(gphi, o.phi), max_rel(gpi, o.pi)
+    say("qball 32^3 same dx fp64 vs oracle", ef, ep)
+    assert max(ef, ep) <= 1e-10
