@@ -37,6 +37,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage line")
     p.add_argument("--no-serve", action="store_true", help="skip the served ensemble")
+    p.add_argument("--no-512", action="store_true", help="skip the 512^3 FP32 line")
     p.add_argument("--serve-runs", type=int, default=96)
     p.add_argument("--serve-steps", type=int, default=500)
     p.add_argument("--tile", default=None,
@@ -146,6 +147,37 @@ def measure_served(sl, nruns, steps):
     }
 
 
+def measure_qball512(sl, steps=20, warmup=3):
+    """Q-ball configuration at 512^3 (FP32 fields, 6th order): the headline
+    roofline point whose working set (4.3 GB) is far beyond the 256 MB MALL."""
+    import synth
+    r = synth.qball(n=512, precision="f32")
+    wall, passes, pass_ms, e, tile = measure(sl, r, steps, warmup)
+    n3 = 512 ** 3
+    avg = pass_ms / passes / 1e3
+    return {"workload": "Q-ball log potential, 512^3, two fields, order 6, dt 0.005, FP32 fields",
+            "value": n3 * 2 * steps / wall, "ms_per_step": wall / steps * 1e3,
+            "pass_ms": avg * 1e3, "achieved_GBs": 4 * 4 * 2 * n3 / avg / 1e9,
+            "frac": 4 * 4 * 2 * n3 / avg / 1e9 / HBM_PEAK_GBS, "tile": list(tile),
+            "friedmann_residual": e["friedmann_residual"]}
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "affinity_cpus": affinity}
+
+
 def cpu_baseline(recipe):
     """FP64 oracle, one composed step of the same workload, one core."""
     import numpy as np  # noqa: F401
@@ -159,7 +191,7 @@ def cpu_baseline(recipe):
     t = time.perf_counter() - t0
     n3 = recipe["n"] ** 3
     return {"value": n3 * recipe["nfields"] / t, "unit": "field-site-updates/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "host": host_cpu(),
             "sample": "1 step (%d stage passes) of the %d^3 %s workload, numpy FP64, %.1f s"
                       % (len(oracle.composition_weights(recipe["order"])), recipe["n"],
                          recipe["workload"], t)}
@@ -213,7 +245,11 @@ def main():
                      "kernel": "pass_kernel", "avg_launch_ms": avg_pass_s * 1e3,
                      "bytes_per_launch": bytes_per_pass},
         "friedmann_residual": e["friedmann_residual"],
+        "stage_updates_per_s": value * stages,
     }
+    copy_gbs = sl.symlat.hbm_copy_bench(1 << 31, 10)
+    out["roofline"]["copy_GBs"] = copy_gbs
+    out["roofline"]["frac_of_copy"] = achieved / copy_gbs
     if not args.no_fp32 and args.precision == "f64":
         r32 = dict(recipe, precision="f32")
         w32, p32, ms32, e32, tile32 = measure(sl, r32, args.steps, args.warmup)
@@ -221,6 +257,9 @@ def main():
             "value": n3 * nf * args.steps / w32, "ms_per_step": w32 / args.steps * 1e3,
             "pass_ms": ms32 / p32, "achieved_GBs": 4 * 4 * nf * n3 / (ms32 / p32 / 1e3) / 1e9,
             "friedmann_residual": e32["friedmann_residual"], "tile": list(tile32)}
+    if not args.no_512 and args.precision == "f64" and args.n == 256:
+        log("512^3 FP32 Q-ball ...")
+        out["qball512_fp32"] = measure_qball512(sl)
     if not args.no_serve:
         log("served ensemble ...")
         out["served"] = measure_served(sl, args.serve_runs, args.serve_steps)

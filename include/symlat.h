@@ -262,7 +262,8 @@ sl_status sl_batch_synchronize(sl_batch* batch);
 sl_status sl_device_memory(size_t* free_bytes, size_t* total_bytes);
 
 /* Measurement helper: time `iters` plain device-to-device copies of `bytes`
- * bytes (bytes a multiple of 32, >= 1024) on a private stream and return the
+ * bytes (bytes a multiple of 16, >= 1024; one 16-byte element per lane) on a
+ * private stream and return the
  * achieved read+write bandwidth in GB/s.  Used to calibrate memory counters
  * and to state the achievable HBM bandwidth beside the lattice kernels. */
 sl_status sl_hbm_copy_bench(size_t bytes, int32_t iters, double* gbs);
