@@ -24,5 +24,7 @@ invariant, a printed constant or brute force; see the test modules named
 from .lattice import (  # noqa: F401
     TABLE1_ORDER6, TABLE1_ORDER8, composition_weights, lap, grad_energy,
     Potential, Lattice, spectrum, stability_limit, linear_stage_matrix,
+    STENCIL_7, STENCIL_19, STENCIL_27, isotropic_stencil, stencil_symbol,
+    stencil_ok, stencil_max_keff2, keff2_modes,
 )
 from . import rng  # noqa: F401

@@ -58,22 +58,104 @@ def composition_weights(order):
 # Stencils, Sec. 2.1 eq. (2.7)-(2.8)
 # ---------------------------------------------------------------------------
 
-def lap(f):
-    """D[f](x): sum of the six face neighbours minus 6 f(x), periodic."""
-    out = -6.0 * f
-    for ax in (-3, -2, -1):
-        out = out + np.roll(f, 1, axis=ax) + np.roll(f, -1, axis=ax)
+#: 7-point member of the family of eq. (2.7): (c0, c1, c2, c3) = weights of
+#: the centre, the 6 face, the 12 edge and the 8 corner neighbours.
+STENCIL_7 = (-6.0, 1.0, 0.0, 0.0)
+
+
+def _neighbour_classes():
+    """Offsets of the 26 neighbours grouped by class: 1 = face (one nonzero
+    component), 2 = edge (two), 3 = corner (three)."""
+    out = {1: [], 2: [], 3: []}
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                k = abs(dz) + abs(dy) + abs(dx)
+                if k:
+                    out[k].append((dz, dy, dx))
     return out
 
 
-def grad_energy(f):
-    """G[f](x) = 1/2 sum over the six face neighbours of (f(nbr) - f(x))^2."""
+_NEIGHBOURS = _neighbour_classes()
+
+
+def _shifted(f, off):
+    """f(x + off) on the periodic lattice (arrays indexed [..., z, y, x])."""
+    dz, dy, dx = off
+    return np.roll(f, (-dz, -dy, -dx), axis=(-3, -2, -1))
+
+
+def lap(f, c=STENCIL_7):
+    """D[f](x) of eq. (2.7): c0 f(x) + sum over the neighbour classes of
+    c_class times the sum of f over that class, periodic."""
+    out = c[0] * f
+    for cls in (1, 2, 3):
+        if c[cls] != 0.0:
+            acc = np.zeros_like(f)
+            for off in _NEIGHBOURS[cls]:
+                acc = acc + _shifted(f, off)
+            out = out + c[cls] * acc
+    return out
+
+
+def grad_energy(f, c=STENCIL_7):
+    """G[f](x) of eq. (2.8) with the coefficients of D: one half of the sum
+    over neighbours of c_class (f(nbr) - f(x))^2."""
     out = np.zeros_like(f)
-    for ax in (-3, -2, -1):
-        for sh in (1, -1):
-            d = np.roll(f, sh, axis=ax) - f
-            out = out + d * d
+    for cls in (1, 2, 3):
+        if c[cls] != 0.0:
+            acc = np.zeros_like(f)
+            for off in _NEIGHBOURS[cls]:
+                d = _shifted(f, off) - f
+                acc = acc + d * d
+            out = out + c[cls] * acc
     return 0.5 * out
+
+
+def stencil_symbol(c, kz, ky, kx):
+    """Eigenvalue of D on the plane wave exp(i k.x) with k in lattice units
+    (radians per site): c0 + 2 c1 sum cos + 4 c2 sum_{d<e} cos cos +
+    8 c3 prod cos.  For the 7-point member it equals -sum 4 sin^2(k_d/2)."""
+    cz, cy, cx = np.cos(kz), np.cos(ky), np.cos(kx)
+    return (c[0] + 2.0 * c[1] * (cz + cy + cx)
+            + 4.0 * c[2] * (cz * cy + cz * cx + cy * cx)
+            + 8.0 * c[3] * cz * cy * cx)
+
+
+def stencil_ok(c, tol=1e-12):
+    """The family's two conditions: D annihilates constants (c0 + 6 c1 +
+    12 c2 + 8 c3 = 0) and tends to the Laplacian (c1 + 4 c2 + 4 c3 = 1)."""
+    return (abs(c[0] + 6 * c[1] + 12 * c[2] + 8 * c[3]) <= tol
+            and abs(c[1] + 4 * c[2] + 4 * c[3] - 1.0) <= tol)
+
+
+def isotropic_stencil(c3):
+    """Member of the family whose leading (k^4) error term is isotropic:
+    Taylor-expanding the symbol gives, at fourth order,
+    S4 (c1/12 + c2/3 + c3/3) + P (c2 + 2 c3) with S4 = sum k_d^4 and
+    P = sum_{d<e} k_d^2 k_e^2, which is a multiple of |k|^4 = S4 + 2P when
+    c1 = 2 c2 + 8 c3.  With the two family conditions this leaves c3 free:
+    c1 = 1/3 + 4 c3, c2 = 1/6 - 2 c3, c0 = -4 - 8 c3 (and the symbol is
+    -|k|^2 + |k|^4/12 + O(k^6) for every member)."""
+    c3 = float(c3)
+    return (-4.0 - 8.0 * c3, 1.0 / 3.0 + 4.0 * c3, 1.0 / 6.0 - 2.0 * c3, c3)
+
+
+#: 19-point (no corners) and 27-point isotropic members, c3 = 0 and 1/30.
+STENCIL_19 = isotropic_stencil(0.0)
+STENCIL_27 = isotropic_stencil(1.0 / 30.0)
+
+
+def stencil_max_keff2(c):
+    """Largest -symbol over the Brillouin zone.  The symbol is multilinear
+    in (cos kz, cos ky, cos kx) in [-1, 1]^3, so its extremes sit at the 8
+    vertices k_d in {0, pi}."""
+    best = -np.inf
+    for kz in (0.0, np.pi):
+        for ky in (0.0, np.pi):
+            for kx in (0.0, np.pi):
+                best = max(best, -float(stencil_symbol(c, kz, ky, kx)))
+    return best
 
 
 # ---------------------------------------------------------------------------
@@ -193,7 +275,10 @@ class Lattice:
     """
 
     def __init__(self, n, L, potential, mpl=1.0, a0=1.0, rho_rad0=0.0,
-                 rho_mat0=0.0, expand=True, dtype=np.float64):
+                 rho_mat0=0.0, expand=True, dtype=np.float64, stencil=STENCIL_7):
+        if not stencil_ok(stencil):
+            raise ValueError("stencil coefficients outside the family of eq. (2.7)")
+        self.c = tuple(float(v) for v in stencil)
         self.n = int(n)
         self.L = float(L)
         self.dx = self.L / self.n
@@ -229,7 +314,7 @@ class Lattice:
         H1 = -p_a ** 2 / (12.0 * VL * m2pl)
         H2 = np.sum(pi * pi) / (2.0 * a * a) \
             + VL * self.rho_rad0 + a * VL * self.rho_mat0
-        grad = sum(np.sum(phi[i] * lap(phi[i])) for i in range(self.nf))
+        grad = sum(np.sum(phi[i] * lap(phi[i], self.c)) for i in range(self.nf))
         H3 = -a * a * grad / (2.0 * dx2) + a ** 4 * np.sum(self.pot.V(phi))
         return H1, H2, H3
 
@@ -256,7 +341,7 @@ class Lattice:
         """p_a -> p_a + sum_x [sum_i a phi_i D phi_i / dx^2 - 4 a^3 V] tau,
         pi_i -> pi_i + (a^2 D phi_i / dx^2 - a^4 dV/dphi_i) tau."""
         a, dx2 = self.a, self.dx ** 2
-        D = np.stack([lap(self.phi[i]) for i in range(self.nf)])
+        D = np.stack([lap(self.phi[i], self.c) for i in range(self.nf)])
         dV = self.pot.dV(self.phi)
         if self.expand:
             S3 = a * np.sum(self.phi * D) / dx2 \
@@ -302,7 +387,7 @@ class Lattice:
         a, dx2 = self.a, self.dx ** 2
         kin = [float(np.mean(self.pi[i] ** 2)) / (2.0 * a ** 6)
                for i in range(self.nf)]
-        grad = [float(np.mean(grad_energy(self.phi[i]))) / (2.0 * a * a * dx2)
+        grad = [float(np.mean(grad_energy(self.phi[i], self.c))) / (2.0 * a * a * dx2)
                 for i in range(self.nf)]
         pot = float(np.mean(self.pot.V(self.phi)))
         rho = sum(kin) + sum(grad) + pot
@@ -334,7 +419,7 @@ class Lattice:
             m2eff = self.pot.d2V_diag(phi0)
             for i in range(self.nf):
                 self.phi[i] += vacuum_field(self.n, self.L, m2eff[i],
-                                            amplitude, seed, i, self.nf)
+                                            amplitude, seed, i, self.nf, self.c)
         elif kind == "white":
             for i in range(self.nf):
                 self.phi[i] += white_field(self.n, amplitude, seed, i)
@@ -352,17 +437,28 @@ def _mode_indices(n):
     return nz, ny, nx, (nz * n + ny) * n + nx
 
 
-def vacuum_field(n, L, m2eff, eps, seed, field, nfields):
+def keff2_modes(n, c=STENCIL_7):
+    """k_eff^2 of every mode (n_z, n_y, n_x): minus the stencil's symbol at
+    k_d = 2 pi n_d / N; for the 7-point member written as
+    sum_d 4 sin^2(pi n_d / N)."""
+    nz, ny, nx, _ = _mode_indices(n)
+    if tuple(c) == STENCIL_7:
+        return sum(4.0 * np.sin(np.pi * m / n) ** 2 for m in (nz, ny, nx))
+    t = 2.0 * np.pi / n
+    return -stencil_symbol(c, t * nz, t * ny, t * nx)
+
+
+def vacuum_field(n, L, m2eff, eps, seed, field, nfields, c=STENCIL_7):
     """delta phi(x_j) = sum_n f_n exp(2 pi i n.j / N) with
     E|f_n|^2 = eps^2 / (2 omega_n L^3), omega_n^2 = k_eff^2/dx^2 + m_eff^2,
-    k_eff^2 = sum_d 4 sin^2(pi n_d / N); f_0 = 0; f_{-n} = conj(f_n);
+    k_eff^2 of the stencil (keff2_modes); f_0 = 0; f_{-n} = conj(f_n);
     self-conjugate modes real.  Each +-n pair draws its normals at the
     canonical (smaller linear index) member."""
     dx = L / n
     nz, ny, nx, idx = _mode_indices(n)
     neg = ((-nz) % n * n + (-ny) % n) * n + (-nx) % n
     canon = np.minimum(idx, neg)
-    keff2 = sum(4.0 * np.sin(np.pi * c / n) ** 2 for c in (nz, ny, nx))
+    keff2 = keff2_modes(n, c)
     w2 = keff2 / dx ** 2 + m2eff
     w = np.sqrt(np.where(w2 > 0, w2, 1.0))
     P = np.where(w2 > 0, eps ** 2 / (2.0 * w * L ** 3), 0.0)

@@ -282,3 +282,36 @@ def test_full_lattice_4cubed_vs_ode(order):
         errs.append(np.abs(pack(lat) - ref).max())
     slope = np.log2(errs[0] / errs[1])
     assert order - 0.5 < slope < order + 1.0, (errs, slope)
+
+
+@pytest.mark.parametrize("order", [4, 6])
+def test_exact_linear_map_27_point(order):
+    """Same pin for the isotropic 27-point member of eq. (2.7): the mode
+    frequency is set by its symbol, written here as the brute-force sum of
+    weighted neighbour phases."""
+    import itertools
+    c = oracle.STENCIL_27
+    n, L, m2, h, steps = 6, 4.0, 0.7, 0.05, 60
+    lat = oracle.Lattice(n, L, oracle.Potential("free", (m2,)), expand=False, stencil=c)
+    phi, pi = synth.gaussian_state(n, 1, 12, phi_amp=1.0, pi_amp=1.0)
+    lat.phi[...] = phi
+    lat.pi[...] = pi
+    lat.evolve(steps, h, order)
+    f = np.fft.fftfreq(n) * n
+    lam = np.zeros((n, n, n))
+    for iz, iy, ix in itertools.product(range(n), repeat=3):
+        k = 2 * np.pi * np.array([f[iz], f[iy], f[ix]]) / n
+        tot = 0.0
+        for off in itertools.product((-1, 0, 1), repeat=3):
+            tot += c[sum(1 for o in off if o)] * np.cos(np.dot(k, off))
+        lam[iz, iy, ix] = tot
+    omega2 = -lam / lat.dx ** 2 + m2
+    M1 = _mode_map(h, order, omega2, 1.0)
+    M = np.broadcast_to(np.eye(2), omega2.shape + (2, 2)).copy()
+    for _ in range(steps):
+        M = M1 @ M
+    P, Q = np.fft.fftn(phi[0]), np.fft.fftn(pi[0])
+    np.testing.assert_allclose(lat.phi[0], np.fft.ifftn(M[..., 0, 0] * P + M[..., 0, 1] * Q).real,
+                               atol=1e-12 * np.abs(phi).max())
+    np.testing.assert_allclose(lat.pi[0], np.fft.ifftn(M[..., 1, 0] * P + M[..., 1, 1] * Q).real,
+                               atol=1e-12 * np.abs(pi).max())

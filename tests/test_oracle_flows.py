@@ -10,10 +10,11 @@ import synth
 H_CS = 1e-30
 
 
-def _lattice(pot=None, expand=True, rho_rad0=0.3, rho_mat0=0.2, n=4, seed=5):
+def _lattice(pot=None, expand=True, rho_rad0=0.3, rho_mat0=0.2, n=4, seed=5,
+             stencil=oracle.STENCIL_7):
     pot = pot or oracle.Potential("chaotic2", (1.0, 3.0))
     lat = oracle.Lattice(n, 2.0, pot, mpl=0.9, a0=1.3, rho_rad0=rho_rad0,
-                         rho_mat0=rho_mat0, expand=expand)
+                         rho_mat0=rho_mat0, expand=expand, stencil=stencil)
     phi, pi = synth.gaussian_state(n, pot.nfields, seed, phi_base=[0.8] + [0.3] * (pot.nfields - 1),
                                    phi_amp=0.2, pi_amp=0.3)
     lat.phi[...] = phi
@@ -50,12 +51,14 @@ POTS = [oracle.Potential("chaotic2", (1.0, 3.0)),
         oracle.Potential("free", (1.0, 2.0, 0.5))]
 
 
-@pytest.mark.parametrize("pot", POTS, ids=lambda p: p.kind)
-def test_flows_are_hamiltonian_vector_fields(pot):
+@pytest.mark.parametrize("pot,stencil", [(p, oracle.STENCIL_7) for p in POTS]
+                         + [(POTS[0], oracle.STENCIL_27), (POTS[2], oracle.STENCIL_19)],
+                         ids=lambda v: getattr(v, "kind", None) or "c3=%g" % v[3])
+def test_flows_are_hamiltonian_vector_fields(pot, stencil):
     """Each flow's increment / tau equals the Hamiltonian vector field of its
     part of eq. (2.46): H1 drives a, H2 drives phi and p_a, H3 drives pi and
     p_a (brute-force complex step over every lattice entry)."""
-    lat = _lattice(pot)
+    lat = _lattice(pot, stencil=stencil)
     tau = 0.37
 
     # H1: a' = dH1/dp_a, nothing else moves

@@ -152,3 +152,29 @@ def test_spectrum_parseval_random(n):
     nb = int(np.ceil(np.sqrt(3) * n / 2)) + 2
     _, P, c = oracle.spectrum(f, 1.0, nb)
     assert np.sum(c * P) == pytest.approx(np.var(f), rel=1e-12)
+
+
+def test_vacuum_field_27_point_uses_its_own_dispersion():
+    """With the 27-point member the mode power follows that stencil's
+    frequencies: the normalised |f_n|^2 / P_n averages to one with P_n from
+    the stencil's symbol (computed here by brute force over the offsets),
+    and not with the 7-point frequencies at the high modes."""
+    import itertools
+    c = oracle.STENCIL_27
+    n, L, m2, eps, seed = 16, 4.0, 1.0, 1e-3, 77
+    d = oracle.lattice.vacuum_field(n, L, m2, eps, seed, 0, 1, c)
+    F = np.fft.fftn(d) / n ** 3
+    f = np.fft.fftfreq(n) * n
+    keff2 = np.zeros((n, n, n))
+    for iz, iy, ix in itertools.product(range(n), repeat=3):
+        k = 2 * np.pi * np.array([f[iz], f[iy], f[ix]]) / n
+        keff2[iz, iy, ix] = -sum(c[sum(1 for o in off if o)] * np.cos(np.dot(k, off))
+                                 for off in itertools.product((-1, 0, 1), repeat=3))
+    w = np.sqrt(keff2 / (L / n) ** 2 + m2)
+    P = eps ** 2 / (2 * w * L ** 3)
+    P[0, 0, 0] = 0
+    ratio = (np.abs(F) ** 2 / np.where(P > 0, P, 1))[P > 0]
+    assert abs(ratio.mean() - 1) < 0.05
+    P7, k7 = _mode_power(n, L, m2, eps)
+    hi = (k7 > 8) & (P7 > 0)
+    assert abs((np.abs(F) ** 2 / np.where(P7 > 0, P7, 1))[hi].mean() - 1) > 0.1
