@@ -14,6 +14,8 @@ composition prescribes, with no merging, fusion or lazy bookkeeping:
 * ``lattice``   stencils, potentials, the Hamiltonian and its three-way
                 split, the exact flows, the second-order map, the Yoshida /
                 Table 1 compositions, observables, spectrum, initial state.
+* ``linear``    the linearized integrator: homogeneous background plus
+                Fourier-space perturbations, every mode evolved on its own.
 * ``rng``       the counter-based SplitMix64 generator and Box-Muller normals,
                 written from their published definitions.
 
@@ -27,4 +29,5 @@ from .lattice import (  # noqa: F401
     STENCIL_7, STENCIL_19, STENCIL_27, isotropic_stencil, stencil_symbol,
     stencil_ok, stencil_max_keff2, keff2_modes,
 )
+from .linear import LinearLattice  # noqa: F401
 from . import rng  # noqa: F401

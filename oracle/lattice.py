@@ -262,6 +262,37 @@ class Potential:
         base = m2 * (1.0 + K + K * math.log(u / M2))
         return [base + m2 * K * phi0[0] ** 2 / u, base + m2 * K * phi0[1] ** 2 / u]
 
+    def hessian(self, phi0):
+        """Matrix d^2V/dphi_i dphi_j at a homogeneous point phi0: the
+        quadratic form of V^(2), eq. (2.26), is delta^T H delta / 2."""
+        k, p = self.kind, self.params
+        phi0 = [float(v) for v in phi0]
+        nf = self.nfields
+        H = np.zeros((nf, nf))
+        if k == "free":
+            for i in range(nf):
+                H[i, i] = p[i]
+        elif k == "chaotic2":
+            m2, G = p
+            f, c = phi0
+            H[0, 0] = m2 + G * c * c
+            H[0, 1] = H[1, 0] = 2.0 * G * f * c
+            H[1, 1] = G * f * f
+        elif k == "oscillon":
+            m2, lam, g = p
+            f = phi0[0]
+            H[0, 0] = m2 - 3.0 * lam * f * f + 5.0 * g * f ** 4
+        else:
+            m2, K, M2 = p
+            u = 0.5 * (phi0[0] ** 2 + phi0[1] ** 2)
+            if u <= 0.0:
+                raise ValueError("Q-ball Hessian undefined at |Phi| = 0")
+            base = m2 * (1.0 + K + K * math.log(u / M2))
+            for i in range(2):
+                for j in range(2):
+                    H[i, j] = (base if i == j else 0.0) + m2 * K * phi0[i] * phi0[j] / u
+        return H
+
 
 # ---------------------------------------------------------------------------
 # The lattice and its exact flows
