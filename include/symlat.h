@@ -138,6 +138,25 @@ sl_status sl_lattice_destroy(sl_lattice* lat);
  * nparams is wrong.  Must precede sl_init_fluctuations / sl_evolve. */
 sl_status sl_set_potential(sl_lattice* lat, int32_t kind, const double* params, int32_t nparams);
 
+/* Discrete Laplacian of eq. (2.7), from the cubic family the paper draws
+ * its second-order stencils from: c[0] weights the site, c[1] its 6 face,
+ * c[2] its 12 edge and c[3] its 8 corner neighbours; G of eq. (2.8) uses
+ * the same weights, G = 1/2 sum_nbr c_class (f(nbr) - f(x))^2.  The default
+ * is the 7-point member (-6, 1, 0, 0).  A member must annihilate constants
+ * (c0 + 6 c1 + 12 c2 + 8 c3 = 0) and tend to the Laplacian (c1 + 4 c2 +
+ * 4 c3 = 1); its leading error is isotropic when c1 = 2 c2 + 8 c3, e.g.
+ * the 19-point (-4, 1/3, 1/6, 0) and 27-point (-128/30, 14/30, 3/30, 1/30)
+ * members.  Any member other than the 7-point one runs the 27-point pass
+ * (one site per lane, vx = 1, pf = 1).  The stencil enters the kick, the
+ * p_a sums, the observables, the stability bound (largest k_eff^2 over the
+ * zone) and the vacuum mode frequencies, so set it before
+ * sl_init_fluctuations.  c is a host array of 4 doubles.  SL_E_INVALID for
+ * non-finite values or a member outside the family (tolerance 1e-12 of the
+ * weighted coefficient sum); SL_E_STATE for a change of stencil kind while
+ * the lattice belongs to a batch.  sl_get_stencil copies the weights out. */
+sl_status sl_set_stencil(sl_lattice* lat, const double* c);
+sl_status sl_get_stencil(sl_lattice* lat, double* c_out);
+
 /* Initial state: phi_i = phi0[i] + fluctuation, pi_i = pi0[i] (canonical
  * momenta), a = a0, eta = 0, then p_a from the constraint H = 0 on the
  * expanding branch (p_a < 0), eq. (2.20).  phi0 and pi0 hold nfields
@@ -156,7 +175,8 @@ sl_status sl_init_fluctuations(sl_lattice* lat, const double* phi0, const double
  * pending, so evolve(a) then evolve(b) equals evolve(a + b) bit for bit.
  * SL_E_INVALID for steps < 0, dt not finite, or an unknown order;
  * SL_E_UNSTABLE if omega_max |dt| exceeds the order's linear stability
- * limit (omega_max^2 = 12/dx^2 + a^2 max(m_eff^2, 0)). */
+ * limit (omega_max^2 = k_eff,max^2/dx^2 + a^2 max(m_eff^2, 0), with
+ * k_eff,max^2 = 12 for the 7-point stencil). */
 sl_status sl_evolve(sl_lattice* lat, int64_t steps, double dt, int32_t order);
 
 /* Compute the observables (one extra read pass over the lattice) and
@@ -213,7 +233,9 @@ sl_status sl_kernel_timing(sl_lattice* lat, int64_t* passes, double* total_ms);
  * ty = 256/tx rows, tz z-planes per workgroup, and the prefetch depth pf of
  * the z-march (1: next plane loaded each iteration; 2: own column two
  * planes and halo one plane ahead).  Lattices with more than two fields run
- * with vx = 1, pf = 1.  sl_get_tile reports the shape in use; sl_set_tile
+ * with vx = 1, pf = 1, and so does any stencil other than the 7-point one
+ * (then 2 tx + 2 ty + 4 <= 256 halo lanes, true for every tx).  A batch
+ * member keeps its vx and pf.  sl_get_tile reports the shape in use; sl_set_tile
  * overrides it (tz = 0: z-chunk chosen from the kernel's occupancy so the
  * grid fills whole rounds of resident workgroups).  SL_E_INVALID for
  * unsupported shapes or more than 65536 workgroups. */
@@ -267,6 +289,65 @@ sl_status sl_device_memory(size_t* free_bytes, size_t* total_bytes);
  * achieved read+write bandwidth in GB/s.  Used to calibrate memory counters
  * and to state the achievable HBM bandwidth beside the lattice kernels. */
 sl_status sl_hbm_copy_bench(size_t bytes, int32_t iters, double* gbs);
+
+/* ---------------------------------------------------------------------------
+ * Linearized integrator (Sec. 2.2 and Sec. 2.4).  The fields are a
+ * homogeneous background phi0_i (momentum pi0_i = a^2 phi0_i' per site) plus
+ * perturbations with zero lattice sum, eq. (2.21)-(2.22); the Hamiltonian is
+ * kept to second order in the perturbations, eq. (2.34), which do not act
+ * back on a, p_a or the background.  A step composes the second-order map
+ * of eq. (2.50) over the five parts of eq. (2.49) with the weights of
+ * sl_evolve's orders.  The perturbations are evolved in Fourier space, eq.
+ * (2.38): every mode class with the same k_eff^2 (modes whose folded wave
+ * numbers min(n_d, N - n_d) form the same multiset) is integrated once as
+ * growth functions, the 2N x 2N matrix M of eq. (2.51), which then advances
+ * every Fourier mode of the class.  FP64 throughout; at most 4 fields.
+ * ------------------------------------------------------------------------- */
+typedef struct sl_linear sl_linear;
+
+/* Create a handle for cfg (precision must be SL_FP64, nfields <= 4); the
+ * stream is as for sl_lattice_create.  Device memory: 4 nfields n^3
+ * complex modes plus transform scratch, and (2 nfields)^2 doubles per
+ * mode class (C(n/2 + 3, 3) classes).  SL_E_INVALID for a bad config. */
+sl_status sl_linear_create(const sl_config* cfg, void* hip_stream, sl_linear** out);
+sl_status sl_linear_destroy(sl_linear* lin);
+/* Potential family and parameters, as sl_set_potential. */
+sl_status sl_linear_set_potential(sl_linear* lin, int32_t kind, const double* params,
+                                  int32_t nparams);
+/* Laplacian weights (centre, face, edge, corner), as sl_set_stencil; the
+ * stencil sets k_eff^2 of every mode. */
+sl_status sl_linear_set_stencil(sl_linear* lin, const double* c);
+/* State from host FP64 lattice fields phi, pi (nfields n^3 each, [field][z]
+ * [y][x]): phi0_i, pi0_i are their lattice means, the perturbations the
+ * remainders, transformed to Fourier space on the device (the k = 0 mode
+ * set to zero).  a = a0, eta = 0; p_a = NaN solves the background
+ * constraint H1 + H2 + H3 = 0 of eq. (2.49) on the expanding branch.
+ * Synchronises. */
+sl_status sl_linear_set_fields(sl_linear* lin, const double* phi, const double* pi, double p_a);
+/* Advance `steps` composed steps of size dt: background coefficients per
+ * stage, growth functions of every class, then every mode times its M.
+ * Asynchronous.  SL_E_INVALID / SL_E_UNSTABLE as sl_evolve (stability from
+ * the largest k_eff^2 and the Hessian diagonal at phi0). */
+sl_status sl_linear_evolve(sl_linear* lin, int64_t steps, double dt, int32_t order);
+/* Lattice fields phi0 + delta phi and pi0 + delta pi as host FP64 arrays
+ * (inverse transform on the device); either pointer may be NULL.
+ * Synchronises. */
+sl_status sl_linear_get_fields(sl_linear* lin, double* phi_out, double* pi_out);
+/* Background: conformal time, a, p_a and phi0, pi0 (nfields each; any
+ * pointer may be NULL).  Synchronises. */
+sl_status sl_linear_get_background(sl_linear* lin, double* eta, double* a, double* p_a,
+                                   double* phi0, double* pi0);
+/* Number of mode classes (distinct folded wave-number multisets). */
+sl_status sl_linear_classes(sl_linear* lin, int64_t* nclasses);
+sl_status sl_linear_synchronize(sl_linear* lin);
+/* Measurement: while enabled, each evolve call brackets its background and
+ * growth launches and its apply launch with HIP events on the handle's
+ * stream; sl_linear_kernel_timing synchronises, returns the number of
+ * growth launches and the summed growth, background and apply times (ms)
+ * since the last call, and clears the record. */
+sl_status sl_linear_set_kernel_timing(sl_linear* lin, int32_t enable);
+sl_status sl_linear_kernel_timing(sl_linear* lin, int64_t* growth_launches, double* growth_ms,
+                                  double* table_ms, double* apply_ms);
 
 #ifdef __cplusplus
 }

@@ -6,10 +6,35 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
+#include <vector>
 
 #include "symlat.h"
 
 namespace symlat {
+
+// ---- host helpers shared by the runtime sources (runtime.hip) -------------
+// Record the thread-local message of sl_last_error and return st.
+sl_status fail(sl_status st, const char* fmt, ...);
+// Stage weights of the order-2/4/6/8 composition (empty if unknown).
+std::vector<double> weights_for(int order);
+// Largest stable omega*h of the composition on a harmonic mode (-1 if unknown).
+double stability_limit_for(int order);
+// d^2 V / d phi_i^2 at a homogeneous point; false where undefined.
+bool hessian_diag(int kind, int nf, const double* p, const double* f, double* out);
+// Parameter count of a potential family (-1 if unknown) and the field count
+// it requires (0: any).
+int nparams_for(int kind, int nf);
+int nfields_for(int kind);
+bool config_ok(const sl_config* c, std::string* why);
+
+#define HIP_TRY(expr)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      return ::symlat::fail(SL_E_DEVICE, "%s failed: %s", #expr,               \
+                            hipGetErrorString(e_));                            \
+  } while (0)
 
 constexpr int kBlock = 256;     // threads per workgroup of every lattice kernel
 constexpr int kMaxFields = 8;
@@ -57,6 +82,16 @@ struct PotArgs {
   double p[kMaxFields];
 };
 
+// Discrete Laplacian of eq. (2.7): weights of the centre and of the 6 face,
+// 12 edge and 8 corner neighbours.  kind 0 is the 7-point member
+// (-6, 1, 0, 0) with its own pass kernel; kind 1 is any member of the cubic
+// family (27-point pass).
+struct Stencil {
+  double c[4];
+  int32_t kind;
+  int32_t pad;
+};
+
 // Launch shape of the tiled passes: TX lanes in x (power of two) each
 // holding VX consecutive sites (tile width TX*VX), TY = 256/TX rows in y,
 // TZ planes per z-chunk.
@@ -77,6 +112,7 @@ struct PassParams {
   double* partials;
   void* sink;  // per-thread slots that absorb the stores of idle lanes
   PotArgs prm;
+  double stc[4];  // stencil weights (27-point pass only)
   int n;
   int tx, logtx, ty, tz;  // lanes in x, log2(lanes), rows, planes per chunk
   int ntx, nty, ntz;
@@ -102,20 +138,23 @@ struct LatView {
   PotArgs prm;
   BgConsts bg;
   Tile tile;
+  Stencil st;
 };
 
 // ---- step kernels (kernels_step.hip) --------------------------------------
 hipError_t launch_pass(const LatView& v, hipStream_t s);
-// Resident workgroups per CU of the pass kernel for this shape.
-int pass_blocks_per_cu(int prec, int pot, int nf, const Tile& t);
+// Resident workgroups per CU of the pass kernel for this shape and stencil
+// kind (the 27-point pass takes vx = 1, pf = 1 only).
+int pass_blocks_per_cu(int prec, int pot, int nf, const Tile& t, int stencil_kind);
 PassParams pass_params(const LatView& v);
 size_t pass_lds_bytes(int prec, int nf, const Tile& t);
 // Batched form: one fused pass over the tiles of nruns lattices (run table
 // and tile starts in device memory), then one finalize workgroup per run.
-hipError_t launch_batched_pass(int prec, int pot, int nf, const Tile& shape, size_t lds,
-                               const PassParams* runs_dev, const int* start_dev, int nruns,
-                               int grid, hipStream_t s);
-int batched_blocks_per_cu(int prec, int pot, int nf, const Tile& shape, size_t lds);
+hipError_t launch_batched_pass(int prec, int pot, int nf, const Tile& shape, int stencil_kind,
+                               size_t lds, const PassParams* runs_dev, const int* start_dev,
+                               int nruns, int grid, hipStream_t s);
+int batched_blocks_per_cu(int prec, int pot, int nf, const Tile& shape, int stencil_kind,
+                          size_t lds);
 hipError_t launch_batched_finalize(const BatchRun* runs_dev, int nruns, double w, double w_next,
                                    double h, int has_next, int end_of_step, hipStream_t s);
 hipError_t launch_batched_begin(const BatchRun* runs_dev, int nruns, double w, double h,

@@ -28,9 +28,38 @@ Bufs bufs_of(const LatView& v) {
 template <int NF>
 constexpr int nsums() { return 5 * NF + 1; }
 
+// G[f] and D[f] of eq. (2.7)-(2.8) at one site with the general cubic
+// stencil: the 26 neighbours weighted by class (face, edge, corner).
+template <typename T>
+__device__ void stencil27_at(const T* __restrict__ phi, const T* __restrict__ pi, double c,
+                             size_t o, int n, int x, int y, int z, double f, const Stencil& st,
+                             double& D, double& G) {
+  const size_t n2 = size_t(n) * n;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0}, g[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int zz = z + dz < 0 ? n - 1 : (z + dz >= n ? 0 : z + dz);
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int yy = y + dy < 0 ? n - 1 : (y + dy >= n ? 0 : y + dy);
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int cls = (dz != 0) + (dy != 0) + (dx != 0);
+        if (cls == 0) continue;
+        const int xx = x + dx < 0 ? n - 1 : (x + dx >= n ? 0 : x + dx);
+        const size_t e = o + size_t(zz) * n2 + size_t(yy) * n + xx;
+        const double v = fma(c, double(pi[e]), double(phi[e]));
+        acc[cls] += v;
+        const double d = v - f;
+        g[cls] += d * d;
+      }
+    }
+  }
+  D = st.c[0] * f + st.c[1] * acc[1] + st.c[2] * acc[2] + st.c[3] * acc[3];
+  G = 0.5 * (st.c[1] * g[1] + st.c[2] * g[2] + st.c[3] * g[3]);
+}
+
 template <typename T, int NF, int KIND>
 __global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScalars* sc,
-                                                         PotArgs prm, int n, double* partials) {
+                                                         PotArgs prm, int n, Stencil st,
+                                                         double* partials) {
   constexpr int NV = nsums<NF>();
   __shared__ KSum scratch[4 * NV];
   const int par = sc->parity;
@@ -67,19 +96,26 @@ __global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScala
       const double pc = double(pi[o + e]);
       const double fcv = fma(c, pc, double(phi[o + e]));
       f[i] = fcv;
-      double nb[6];
-      const size_t idx[6] = {xm, xp, ym, yp, zm, zp};
+      double D, G;
+      if (st.kind == 0) {
+        double nb[6];
+        const size_t idx[6] = {xm, xp, ym, yp, zm, zp};
 #pragma unroll
-      for (int q = 0; q < 6; ++q) nb[q] = fma(c, double(pi[o + idx[q]]), double(phi[o + idx[q]]));
-      double D = -6.0 * fcv, G = 0.0;
+        for (int q = 0; q < 6; ++q) nb[q] = fma(c, double(pi[o + idx[q]]), double(phi[o + idx[q]]));
+        D = -6.0 * fcv;
+        G = 0.0;
 #pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        D += nb[q];
-        const double d = nb[q] - fcv;
-        G += d * d;
+        for (int q = 0; q < 6; ++q) {
+          D += nb[q];
+          const double d = nb[q] - fcv;
+          G += d * d;
+        }
+        G = 0.5 * G;
+      } else {
+        stencil27_at<T>(phi, pi, c, o, n, x, y, z, fcv, st, D, G);
       }
       kadd(acc[5 * i + 0], pc * pc);
-      kadd(acc[5 * i + 1], 0.5 * G);
+      kadd(acc[5 * i + 1], G);
       const double ds = fcv - shift[i];
       kadd(acc[5 * i + 2], ds);
       kadd(acc[5 * i + 3], ds * ds);
@@ -201,7 +237,7 @@ hipError_t energies_t(const LatView& v, double* sums, sl_energies_t* out, int mo
   int nb = int((n3 + kBlock - 1) / kBlock);
   if (nb > kDiagBlocksMax) nb = kDiagBlocksMax;
   hipLaunchKernelGGL((energies_kernel<T, NF, KIND>), dim3(nb), dim3(kBlock), 0, s, B, v.sc,
-                     v.prm, v.n, v.partials);
+                     v.prm, v.n, v.st, v.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((energies_finalize<NF>), dim3(1), dim3(kBlock), 0, s, v.partials, nb, v.sc,

@@ -52,8 +52,11 @@ __global__ void fill_homogeneous_kernel(void* phi0, void* pi0, int nf, size_t n3
 // f_n for every mode n of one field: E|f_n|^2 = A^2/(2 omega_n L^3),
 // omega_n^2 = k_eff^2/dx^2 + m_eff^2, f_0 = 0, f_{-n} = conj(f_n), real on
 // self-conjugate modes; each +-n pair draws at its smaller linear index.
+// k_eff^2 is minus the eigenvalue of the lattice Laplacian on the mode: for
+// the 7-point stencil sum_d 4 sin^2(pi n_d/N), for a general member of the
+// cubic family -(c0 + 2 c1 sum cos + 4 c2 sum cos cos + 8 c3 prod cos).
 __global__ void vacuum_modes_kernel(double2* F, int n, double L, int field, double m2eff,
-                                    double amp, uint64_t seed) {
+                                    double amp, uint64_t seed, Stencil st) {
   const size_t n2 = size_t(n) * n, n3 = n2 * n;
   const double dx = L / n;
   const size_t stride = size_t(gridDim.x) * blockDim.x;
@@ -62,8 +65,15 @@ __global__ void vacuum_modes_kernel(double2* F, int n, double L, int field, doub
     const int mx = (n - nx) % n, my = (n - ny) % n, mz = (n - nz) % n;
     const size_t neg = (size_t(mz) * n + my) * n + mx;
     const size_t canon = e < neg ? e : neg;
-    const double sx = sinpi(double(nx) / n), sy = sinpi(double(ny) / n), sz = sinpi(double(nz) / n);
-    const double keff2 = 4.0 * sz * sz + 4.0 * sy * sy + 4.0 * sx * sx;
+    double keff2;
+    if (st.kind == 0) {
+      const double sx = sinpi(double(nx) / n), sy = sinpi(double(ny) / n), sz = sinpi(double(nz) / n);
+      keff2 = 4.0 * sz * sz + 4.0 * sy * sy + 4.0 * sx * sx;
+    } else {
+      const double cx = cospi(2.0 * nx / n), cy = cospi(2.0 * ny / n), cz = cospi(2.0 * nz / n);
+      keff2 = -(st.c[0] + 2.0 * st.c[1] * (cz + cy + cx) +
+                4.0 * st.c[2] * (cz * cy + cz * cx + cy * cx) + 8.0 * st.c[3] * cz * cy * cx);
+    }
     const double w2 = keff2 / (dx * dx) + m2eff;
     double P = 0.0;
     if (w2 > 0.0 && e != 0) P = amp * amp / (2.0 * sqrt(w2) * L * L * L);
@@ -261,7 +271,7 @@ hipError_t launch_vacuum_modes(const LatView& v, double2* cbuf, int field, doubl
                                double amp, uint64_t seed, hipStream_t s) {
   const size_t n3 = size_t(v.n) * v.n * v.n;
   hipLaunchKernelGGL(vacuum_modes_kernel, dim3(grid_for(n3)), dim3(kBlock), 0, s, cbuf, v.n,
-                     v.bg.L, field, m2eff, amp, seed);
+                     v.bg.L, field, m2eff, amp, seed, v.st);
   return hipGetLastError();
 }
 

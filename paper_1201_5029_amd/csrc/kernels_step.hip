@@ -330,12 +330,210 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
   }
 }
 
-template <typename T, int NF, int KIND, int VX, int PF>
+// The same stage pass with any member of the cubic stencil family of
+// eq. (2.7): D = c0 f + c1 (6 faces) + c2 (12 edges) + c3 (8 corners).  Per
+// plane p of the own column the lane forms, from the drifted plane in LDS
+// (halo ring including the four corner cells), the centre value f(p), the
+// in-plane face sum F(p) = f(x+-1) + f(y+-1) and the in-plane corner sum
+// C(p) = f(x+-1, y+-1).  Then, for the site at plane z,
+//   faces = F(z) + f(z-1) + f(z+1),  edges = C(z) + F(z-1) + F(z+1),
+//   corners = C(z-1) + C(z+1),
+// so a ring of three (f, F, C) triples in registers replaces a second LDS
+// plane.  The ring lags the loads by one plane: the chunk walks planes
+// z0 - 1 .. zend and writes plane p - 1 while plane p is in LDS.  One site
+// per lane; the memory instructions are uniform across lanes (idle lanes
+// load the tile's first column and store into the sink), and the loads of
+// plane p + 1 go out after the barrier, before the stores of plane p - 1.
+template <typename T, int NF, int KIND>
+__device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T* lds,
+                                            KSum* red_scratch) {
+  const int par = P.sc->parity;
+  const T* __restrict__ phi_in = static_cast<const T*>(P.phi[par]);
+  const T* __restrict__ pi_in = static_cast<const T*>(P.pi[par]);
+  T* __restrict__ phi_out = static_cast<T*>(P.phi_w[par ^ 1]);
+  T* __restrict__ pi_out = static_cast<T*>(P.pi_w[par ^ 1]);
+  const T c = static_cast<T>(P.sc->c_next);
+  const T alpha = static_cast<T>(P.sc->alpha);
+  const T beta = static_cast<T>(P.sc->beta);
+  const T w0 = static_cast<T>(P.stc[0]), w1 = static_cast<T>(P.stc[1]);
+  const T w2 = static_cast<T>(P.stc[2]), w3 = static_cast<T>(P.stc[3]);
+  PotT<T> pot;
+#pragma unroll
+  for (int i = 0; i < kMaxFields; ++i) pot.p[i] = static_cast<T>(P.prm.p[i]);
+
+  const int n = P.n;
+  const size_t n2 = size_t(n) * n;
+  const size_t n3 = n2 * n;
+
+  int b = tile_id;
+  const int xt = b % P.ntx;
+  b /= P.ntx;
+  const int yt = b % P.nty;
+  const int zt = b / P.nty;
+  const int TW = P.tx;
+  const int x0 = xt * TW, y0 = yt * P.ty, z0 = zt * P.tz;
+  const int wx = min(TW, n - x0), wy = min(P.ty, n - y0), zc = min(P.tz, n - z0);
+  const int zend = z0 + zc;
+
+  const int tid = threadIdx.x;
+  const int tx = tid & (P.tx - 1);
+  const int ty = tid >> P.logtx;
+  const bool active = (tx < wx) && (ty < wy);
+  const int LX = TW + 2;
+  const int plane = LX * (P.ty + 2);
+  const int own = (ty + 1) * LX + 1 + tx;
+  const size_t col = active ? size_t(y0 + ty) * n + (x0 + tx) : size_t(y0) * n + x0;
+
+  // halo cell of this lane (one site): rows above/below, columns left/right,
+  // then the four corners; lanes without one re-load their own column
+  bool hjob = false;
+  int hl = 0;
+  size_t hcol = col;
+  {
+    const int TX = P.tx, TY = P.ty;
+    int hx = -1, hy = 0;
+    const int xl = (x0 - 1 + n) % n, xr = (x0 + wx) % n;
+    const int yb = (y0 - 1 + n) % n, yt2 = (y0 + wy) % n;
+    if (tid < TX) {
+      if (tid < wx) { hx = x0 + tid; hy = yb; hl = 1 + tid; }
+    } else if (tid < 2 * TX) {
+      const int t = tid - TX;
+      if (t < wx) { hx = x0 + t; hy = yt2; hl = (wy + 1) * LX + 1 + t; }
+    } else if (tid < 2 * TX + TY) {
+      const int r = tid - 2 * TX;
+      if (r < wy) { hx = xl; hy = y0 + r; hl = (r + 1) * LX; }
+    } else if (tid < 2 * TX + 2 * TY) {
+      const int r = tid - 2 * TX - TY;
+      if (r < wy) { hx = xr; hy = y0 + r; hl = (r + 1) * LX + wx + 1; }
+    } else if (tid < 2 * TX + 2 * TY + 4) {
+      const int k = tid - 2 * TX - 2 * TY;
+      hx = (k & 1) ? xr : xl;
+      hy = (k & 2) ? yt2 : yb;
+      hl = ((k & 2) ? (wy + 1) * LX : 0) + ((k & 1) ? wx + 1 : 0);
+    }
+    if (hx >= 0) {
+      hjob = true;
+      hcol = size_t(hy) * n + hx;
+    }
+  }
+  auto wrapz = [n](int z) { return z < 0 ? z + n : (z >= n ? z - n : z); };
+
+  KSum acc_dd{0.0, 0.0}, acc_v{0.0, 0.0}, acc_p{0.0, 0.0};
+  // ring: (f, F, C) of planes p-2 (A) and p-1 (B); momenta of plane p-1
+  T fA[NF], FA[NF], CA[NF], fB[NF], FB[NF], CB[NF], qB[NF];
+  // raw loads in flight (plane p): own column and halo cell
+  T nph[NF], npi[NF], hph[NF], hpi[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) fA[i] = FA[i] = CA[i] = fB[i] = FB[i] = CB[i] = qB[i] = T(0);
+
+  auto load_plane = [&](int zz) {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const size_t o = i * n3 + size_t(zz) * n2;
+      nph[i] = phi_in[o + col];
+      npi[i] = pi_in[o + col];
+      hph[i] = phi_in[o + hcol];
+      hpi[i] = pi_in[o + hcol];
+    }
+  };
+
+  T* sink = static_cast<T*>(P.sink) + size_t(tid) * (2 * NF);
+  load_plane(wrapz(z0 - 1));
+  // same trailing sequence as an iteration (loads, then 2 NF stores) so the
+  // wait at the loop head covers the loads only
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    sink[2 * i] = fB[i];
+    sink[2 * i + 1] = qB[i];
+  }
+
+  int buf = 0;
+  for (int p = z0 - 1; p <= zend; ++p) {
+    T* L = lds + size_t(buf) * NF * plane;
+    T qN[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      qN[i] = npi[i];
+      const T f = drift(nph[i], npi[i], c);
+      if (active) L[i * plane + own] = f;
+      if (hjob) L[i * plane + hl] = drift(hph[i], hpi[i], c);
+    }
+    __syncthreads();
+    load_plane(wrapz(min(p + 1, zend)));  // past the end: the last plane again
+    T fN[NF], FN[NF], CN[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const T* Li = L + i * plane + own;
+      fN[i] = Li[0];
+      FN[i] = (Li[-1] + Li[1]) + (Li[-LX] + Li[LX]);
+      CN[i] = (Li[-LX - 1] + Li[-LX + 1]) + (Li[LX - 1] + Li[LX + 1]);
+    }
+    // site at plane z = p - 1: ring (A, B, N) = planes (z - 1, z, z + 1)
+    const bool out = active && p >= z0 + 1;
+    {
+      T D[NF], dV[NF], V, pn[NF];
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        const T faces = FB[i] + (fA[i] + fN[i]);
+        const T edges = CB[i] + (FA[i] + FN[i]);
+        const T corners = CA[i] + CN[i];
+        D[i] = ((w0 * fB[i] + w1 * faces) + w2 * edges) + w3 * corners;
+      }
+      potential<KIND, NF, T>(fB, pot, V, dV);
+      double dd = 0.0, p2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        pn[i] = qB[i] + alpha * D[i] - beta * dV[i];
+        dd += double(fB[i]) * double(D[i]);
+        p2 += double(pn[i]) * double(pn[i]);
+      }
+      const size_t oc = size_t(wrapz(p - 1)) * n2 + col;
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        T* po = out ? phi_out + i * n3 + oc : sink + 2 * i;
+        T* qo = out ? pi_out + i * n3 + oc : sink + 2 * i + 1;
+        *po = fB[i];
+        *qo = pn[i];
+      }
+      if (out) {
+        kadd(acc_dd, dd);
+        kadd(acc_v, double(V));
+        kadd(acc_p, p2);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      fA[i] = fB[i]; FA[i] = FB[i]; CA[i] = CB[i];
+      fB[i] = fN[i]; FB[i] = FN[i]; CB[i] = CN[i];
+      qB[i] = qN[i];
+    }
+    buf ^= 1;
+  }
+
+  KSum v3[3] = {acc_dd, acc_v, acc_p};
+  block_reduce<3>(v3, red_scratch);
+  if (threadIdx.x == 0) {
+    double* o = P.partials + size_t(tile_id) * 6;
+    o[0] = v3[0].s; o[1] = v3[0].c;
+    o[2] = v3[1].s; o[3] = v3[1].c;
+    o[4] = v3[2].s; o[5] = v3[2].c;
+  }
+}
+
+template <typename T, int NF, int KIND, int VX, int PF, int ST>
+__device__ __forceinline__ void pass_any(const PassParams& P, int tile_id, T* lds, KSum* red) {
+  if constexpr (ST == 0)
+    pass_tile<T, NF, KIND, VX, PF>(P, tile_id, lds, red);
+  else
+    pass_tile27<T, NF, KIND>(P, tile_id, lds, red);
+}
+
+template <typename T, int NF, int KIND, int VX, int PF, int ST>
 __global__ __launch_bounds__(kBlock) void pass_kernel(PassParams P) {
   extern __shared__ unsigned char smem_raw[];
   __shared__ KSum red_scratch[4 * 3];
-  pass_tile<T, NF, KIND, VX, PF>(P, xcd_tile(blockIdx.x, gridDim.x), reinterpret_cast<T*>(smem_raw),
-                                 red_scratch);
+  pass_any<T, NF, KIND, VX, PF, ST>(P, xcd_tile(blockIdx.x, gridDim.x),
+                                    reinterpret_cast<T*>(smem_raw), red_scratch);
 }
 
 // Batched form: the tiles of many lattices (same precision, potential family
@@ -344,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(PassParams P) {
 // global tiles and its workgroups stride through it, so one launch of about
 // the resident capacity covers any mix of lattice sizes.  A run's tiles and
 // partial sums are exactly those of the same lattice advanced alone.
-template <typename T, int NF, int KIND, int VX, int PF>
+template <typename T, int NF, int KIND, int VX, int PF, int ST>
 __global__ __launch_bounds__(kBlock) void batched_pass_kernel(const PassParams* __restrict__ runs,
                                                              const int* __restrict__ start,
                                                              int nruns) {
@@ -363,8 +561,8 @@ __global__ __launch_bounds__(kBlock) void batched_pass_kernel(const PassParams* 
       const int mid = (lo + hi + 1) >> 1;
       if (start[mid] <= g) lo = mid; else hi = mid - 1;
     }
-    pass_tile<T, NF, KIND, VX, PF>(runs[lo], g - start[lo], reinterpret_cast<T*>(smem_raw),
-                                   red_scratch);
+    pass_any<T, NF, KIND, VX, PF, ST>(runs[lo], g - start[lo], reinterpret_cast<T*>(smem_raw),
+                                      red_scratch);
   }
 }
 
@@ -488,6 +686,7 @@ PassParams make_params(const LatView& v) {
   P.partials = v.partials;
   P.sink = v.sink;
   P.prm = v.prm;
+  for (int k = 0; k < 4; ++k) P.stc[k] = v.st.c[k];
   P.n = v.n;
   P.tx = v.tile.tx;
   P.logtx = v.tile.logtx;
@@ -509,77 +708,89 @@ struct PassKernel {
 };
 
 template <typename T, int NF, int KIND>
-PassKernel pick_t(const Tile& t) {
+PassKernel pick_t(const Tile& t, int st) {
   PassKernel k;
   k.lds = size_t(2) * NF * (t.tx * t.vx + 2) * (t.ty + 2) * sizeof(T);
+  if (st != 0) {
+    // any cubic-family stencil: one site per lane, lagged ring (see pass_tile27)
+    k.fn = pass_kernel<T, NF, KIND, 1, 1, 1>;
+    k.bfn = batched_pass_kernel<T, NF, KIND, 1, 1, 1>;
+    return k;
+  }
   if constexpr (NF <= 2) {
     if (t.pf == 2) {
-      k.fn = t.vx == 4 ? pass_kernel<T, NF, KIND, 4, 2>
-                       : (t.vx == 2 ? pass_kernel<T, NF, KIND, 2, 2> : pass_kernel<T, NF, KIND, 1, 2>);
-      k.bfn = t.vx == 4 ? batched_pass_kernel<T, NF, KIND, 4, 2>
-                        : (t.vx == 2 ? batched_pass_kernel<T, NF, KIND, 2, 2>
-                                     : batched_pass_kernel<T, NF, KIND, 1, 2>);
+      k.fn = t.vx == 4 ? pass_kernel<T, NF, KIND, 4, 2, 0>
+                       : (t.vx == 2 ? pass_kernel<T, NF, KIND, 2, 2, 0>
+                                    : pass_kernel<T, NF, KIND, 1, 2, 0>);
+      k.bfn = t.vx == 4 ? batched_pass_kernel<T, NF, KIND, 4, 2, 0>
+                        : (t.vx == 2 ? batched_pass_kernel<T, NF, KIND, 2, 2, 0>
+                                     : batched_pass_kernel<T, NF, KIND, 1, 2, 0>);
     } else {
-      k.fn = t.vx == 4 ? pass_kernel<T, NF, KIND, 4, 1>
-                       : (t.vx == 2 ? pass_kernel<T, NF, KIND, 2, 1> : pass_kernel<T, NF, KIND, 1, 1>);
-      k.bfn = t.vx == 4 ? batched_pass_kernel<T, NF, KIND, 4, 1>
-                        : (t.vx == 2 ? batched_pass_kernel<T, NF, KIND, 2, 1>
-                                     : batched_pass_kernel<T, NF, KIND, 1, 1>);
+      k.fn = t.vx == 4 ? pass_kernel<T, NF, KIND, 4, 1, 0>
+                       : (t.vx == 2 ? pass_kernel<T, NF, KIND, 2, 1, 0>
+                                    : pass_kernel<T, NF, KIND, 1, 1, 0>);
+      k.bfn = t.vx == 4 ? batched_pass_kernel<T, NF, KIND, 4, 1, 0>
+                        : (t.vx == 2 ? batched_pass_kernel<T, NF, KIND, 2, 1, 0>
+                                     : batched_pass_kernel<T, NF, KIND, 1, 1, 0>);
     }
   } else {
     // more than two fields: one site per lane, no deep prefetch (register budget)
-    k.fn = pass_kernel<T, NF, KIND, 1, 1>;
-    k.bfn = batched_pass_kernel<T, NF, KIND, 1, 1>;
+    k.fn = pass_kernel<T, NF, KIND, 1, 1, 0>;
+    k.bfn = batched_pass_kernel<T, NF, KIND, 1, 1, 0>;
   }
   return k;
 }
 
 template <typename T>
-PassKernel pick_prec(int pot, int nf, const Tile& t) {
+PassKernel pick_prec(int pot, int nf, const Tile& t, int st) {
   switch (pot) {
-    case SL_POT_CHAOTIC2: return pick_t<T, 2, SL_POT_CHAOTIC2>(t);
-    case SL_POT_OSCILLON: return pick_t<T, 1, SL_POT_OSCILLON>(t);
-    case SL_POT_QBALL_LOG: return pick_t<T, 2, SL_POT_QBALL_LOG>(t);
+    case SL_POT_CHAOTIC2: return pick_t<T, 2, SL_POT_CHAOTIC2>(t, st);
+    case SL_POT_OSCILLON: return pick_t<T, 1, SL_POT_OSCILLON>(t, st);
+    case SL_POT_QBALL_LOG: return pick_t<T, 2, SL_POT_QBALL_LOG>(t, st);
     default: break;
   }
   switch (nf) {
-    case 1: return pick_t<T, 1, SL_POT_FREE>(t);
-    case 2: return pick_t<T, 2, SL_POT_FREE>(t);
-    case 3: return pick_t<T, 3, SL_POT_FREE>(t);
-    case 4: return pick_t<T, 4, SL_POT_FREE>(t);
-    case 5: return pick_t<T, 5, SL_POT_FREE>(t);
-    case 6: return pick_t<T, 6, SL_POT_FREE>(t);
-    case 7: return pick_t<T, 7, SL_POT_FREE>(t);
-    default: return pick_t<T, 8, SL_POT_FREE>(t);
+    case 1: return pick_t<T, 1, SL_POT_FREE>(t, st);
+    case 2: return pick_t<T, 2, SL_POT_FREE>(t, st);
+    case 3: return pick_t<T, 3, SL_POT_FREE>(t, st);
+    case 4: return pick_t<T, 4, SL_POT_FREE>(t, st);
+    case 5: return pick_t<T, 5, SL_POT_FREE>(t, st);
+    case 6: return pick_t<T, 6, SL_POT_FREE>(t, st);
+    case 7: return pick_t<T, 7, SL_POT_FREE>(t, st);
+    default: return pick_t<T, 8, SL_POT_FREE>(t, st);
   }
 }
 
-PassKernel pick(int prec, int pot, int nf, const Tile& t) {
-  return prec == SL_FP32 ? pick_prec<float>(pot, nf, t) : pick_prec<double>(pot, nf, t);
+PassKernel pick(int prec, int pot, int nf, const Tile& t, int st) {
+  return prec == SL_FP32 ? pick_prec<float>(pot, nf, t, st) : pick_prec<double>(pot, nf, t, st);
 }
 
 }  // namespace
 
 hipError_t launch_pass(const LatView& v, hipStream_t s) {
   if (v.nf < 1 || v.nf > kMaxFields) return hipErrorInvalidValue;
-  if (v.nf > 2 && (v.tile.vx != 1 || v.tile.pf != 1)) return hipErrorInvalidValue;
-  const PassKernel k = pick(v.prec, v.pot, v.nf, v.tile);
+  if ((v.nf > 2 || v.st.kind != 0) && (v.tile.vx != 1 || v.tile.pf != 1))
+    return hipErrorInvalidValue;
+  // the 27-point pass needs lanes for 2 rows + 2 columns + 4 corners of halo
+  if (v.st.kind != 0 && 2 * v.tile.tx + 2 * v.tile.ty + 4 > kBlock) return hipErrorInvalidValue;
+  const PassKernel k = pick(v.prec, v.pot, v.nf, v.tile, v.st.kind);
   hipLaunchKernelGGL(k.fn, dim3(v.tile.nblocks()), dim3(kBlock), k.lds, s, make_params(v));
   return hipGetLastError();
 }
 
 PassParams pass_params(const LatView& v) { return make_params(v); }
 
-hipError_t launch_batched_pass(int prec, int pot, int nf, const Tile& shape, size_t lds,
-                               const PassParams* runs_dev, const int* start_dev, int nruns,
-                               int grid, hipStream_t s) {
-  const PassKernel k = pick(prec, pot, nf, shape);
+hipError_t launch_batched_pass(int prec, int pot, int nf, const Tile& shape, int stencil_kind,
+                               size_t lds, const PassParams* runs_dev, const int* start_dev,
+                               int nruns, int grid, hipStream_t s) {
+  const PassKernel k = pick(prec, pot, nf, shape, stencil_kind);
   hipLaunchKernelGGL(k.bfn, dim3(grid), dim3(kBlock), lds, s, runs_dev, start_dev, nruns);
   return hipGetLastError();
 }
 
-int batched_blocks_per_cu(int prec, int pot, int nf, const Tile& shape, size_t lds) {
-  const PassKernel k = pick(prec, pot, nf, shape);
+int batched_blocks_per_cu(int prec, int pot, int nf, const Tile& shape, int stencil_kind,
+                          size_t lds) {
+  const PassKernel k = pick(prec, pot, nf, shape, stencil_kind);
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k.bfn, kBlock, lds) != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
@@ -603,8 +814,8 @@ hipError_t launch_batched_begin(const BatchRun* runs_dev, int nruns, double w, d
   return hipGetLastError();
 }
 
-int pass_blocks_per_cu(int prec, int pot, int nf, const Tile& t) {
-  const PassKernel k = pick(prec, pot, nf, t);
+int pass_blocks_per_cu(int prec, int pot, int nf, const Tile& t, int stencil_kind) {
+  const PassKernel k = pick(prec, pot, nf, t, stencil_kind);
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k.fn, kBlock, k.lds) != hipSuccess) return 1;
   return nb > 0 ? nb : 1;

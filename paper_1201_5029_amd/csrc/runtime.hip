@@ -16,7 +16,7 @@
 
 using namespace symlat;
 
-namespace {
+namespace symlat {
 
 thread_local std::string g_last_error;
 
@@ -29,13 +29,6 @@ sl_status fail(sl_status st, const char* fmt, ...) {
   g_last_error = buf;
   return st;
 }
-
-#define HIP_TRY(expr)                                                                       \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
-      return fail(SL_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));              \
-  } while (0)
 
 // ---------------------------------------------------------------------------
 // Composition weights (Sec. 2.3): second-order map (order 2), triple jump
@@ -143,6 +136,10 @@ bool config_ok(const sl_config* c, std::string* why) {
   return true;
 }
 
+}  // namespace symlat
+
+namespace {
+
 constexpr long kMaxPassBlocks = 65536;  // bound of the per-block partial-sum buffer
 
 // Tile geometry for lanes tx (16/32/64), vx sites per lane, tz planes and
@@ -209,9 +206,9 @@ size_t partial_doubles() {
 // Process-wide cache of autotuned pass shapes keyed by (device, n, fields,
 // precision, potential family).
 struct TuneKey {
-  int dev, n, nf, prec, pot;
+  int dev, n, nf, prec, pot, st;
   bool operator==(const TuneKey& o) const {
-    return dev == o.dev && n == o.n && nf == o.nf && prec == o.prec && pot == o.pot;
+    return dev == o.dev && n == o.n && nf == o.nf && prec == o.prec && pot == o.pot && st == o.st;
   }
 };
 struct TuneVal {
@@ -239,6 +236,7 @@ struct sl_lattice {
   double pot_raw[kMaxFields] = {0};
   double hom[kMaxFields] = {0};
   double m2max = 0.0;
+  double keff2_max = 12.0;  // largest k_eff^2 of the stencil over the zone
   double a_host = 1.0;
   double* sums_dev = nullptr;
   sl_energies_t* energies_dev = nullptr;
@@ -248,6 +246,8 @@ struct sl_lattice {
   int tz_user = 0;  // 0: z-chunk chosen from the occupancy of the pass kernel
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
 };
+
+void batch_member_changed(sl_batch* B);
 
 namespace {
 
@@ -272,7 +272,9 @@ void retile(sl_lattice* L, int tx, int vx, int tz, int pf) {
   const int n = L->cfg.n;
   Tile t = tile_geometry(n, tx, vx, n, pf);
   if (tz <= 0) {
-    const int bpc = L->pot_set ? pass_blocks_per_cu(L->cfg.precision, L->v.pot, L->cfg.nfields, t) : 1;
+    const int bpc = L->pot_set ? pass_blocks_per_cu(L->cfg.precision, L->v.pot, L->cfg.nfields, t,
+                                                    L->v.st.kind)
+                               : 1;
     tz = pick_tz(n, t.ntx * t.nty, long(bpc) * device_cus());
   }
   L->v.tile = tile_geometry(n, tx, vx, tz, pf);
@@ -399,6 +401,7 @@ sl_status sl_lattice_create(const sl_config* cfg, void* hip_stream, sl_lattice**
   v.bg.mpl2 = cfg->mpl * cfg->mpl;
   v.bg.L = cfg->L;
   v.bg.expand = cfg->expansion == SL_EXPAND_SELF ? 1 : 0;
+  v.st = Stencil{{-6.0, 1.0, 0.0, 0.0}, 0, 0};
   {
     int tx, vx, pf;
     default_shape(cfg->n, cfg->precision, cfg->nfields, &tx, &vx, &pf);
@@ -471,7 +474,7 @@ sl_status sl_set_potential(sl_lattice* L, int32_t kind, const double* params, in
   L->pot_kind = kind;
   L->pot_set = true;
   refresh_m2max(L);
-  const TuneKey key{L->device, L->cfg.n, L->cfg.nfields, L->cfg.precision, kind};
+  const TuneKey key{L->device, L->cfg.n, L->cfg.nfields, L->cfg.precision, kind, L->v.st.kind};
   for (const auto& kv : tune_cache()) {
     if (kv.first == key) {
       L->tz_user = kv.second.tz;
@@ -576,7 +579,7 @@ sl_status sl_set_fields(sl_lattice* L, const double* phi, const double* pi, doub
 namespace {
 sl_status check_stable(sl_lattice* L, double dt, int order) {
   const double dx = L->cfg.L / L->cfg.n;
-  const double omax = std::sqrt(12.0 / (dx * dx) + L->a_host * L->a_host * L->m2max);
+  const double omax = std::sqrt(L->keff2_max / (dx * dx) + L->a_host * L->a_host * L->m2max);
   const double lim = stability_limit_for(order);
   if (omax * std::fabs(dt) > lim)
     return fail(SL_E_UNSTABLE, "omega_max*|dt| = %.4f exceeds the order-%d stability limit %.4f",
@@ -738,7 +741,8 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
     return fail(SL_E_INVALID, "vx_only must be 0, 1, 2 or 4");
   if (pf_only != 0 && pf_only != 1 && pf_only != 2) return fail(SL_E_INVALID, "pf_only must be 0, 1 or 2");
   const int n = L->cfg.n;
-  const bool many = L->cfg.nfields > 2;
+  // more than two fields, or the 27-point pass: one site per lane, pf = 1
+  const bool many = L->cfg.nfields > 2 || L->v.st.kind != 0;
   struct Cand {
     int tx, vx, tz, pf;
   };
@@ -804,7 +808,7 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
   }
   L->tz_user = win.tz;
   retile(L, win.tx, win.vx, win.tz, win.pf);
-  const TuneKey key{L->device, n, L->cfg.nfields, L->cfg.precision, L->v.pot};
+  const TuneKey key{L->device, n, L->cfg.nfields, L->cfg.precision, L->v.pot, L->v.st.kind};
   bool found = false;
   for (auto& kv : tune_cache()) {
     if (kv.first == key) {
@@ -845,6 +849,10 @@ sl_status sl_set_tile(sl_lattice* L, int32_t tx, int32_t vx, int32_t tz, int32_t
   if (pf != 1 && pf != 2) return fail(SL_E_INVALID, "pf must be 1 or 2");
   if (L->cfg.nfields > 2 && (vx != 1 || pf != 1))
     return fail(SL_E_INVALID, "more than two fields run with vx = 1 and pf = 1 only");
+  if (L->v.st.kind != 0 && (vx != 1 || pf != 1))
+    return fail(SL_E_INVALID, "the 27-point stencil runs with vx = 1 and pf = 1 only");
+  if (L->batch && (vx != L->v.tile.vx || pf != L->v.tile.pf))
+    return fail(SL_E_STATE, "a batch member keeps its vx and pf (remove it from the batch first)");
   if (tz < 0 || tz > L->cfg.n) return fail(SL_E_INVALID, "tz must be in [0, n]");
   const Tile t = tile_geometry(L->cfg.n, tx, vx, tz > 0 ? tz : L->cfg.n, pf);
   if (long(t.nblocks()) > kMaxPassBlocks)
@@ -852,6 +860,67 @@ sl_status sl_set_tile(sl_lattice* L, int32_t tx, int32_t vx, int32_t tz, int32_t
   HIP_TRY(hipStreamSynchronize(L->stream));
   L->tz_user = tz;
   retile(L, tx, vx, tz, pf);
+  if (L->batch) batch_member_changed(L->batch);
+  return SL_OK;
+}
+
+sl_status sl_set_stencil(sl_lattice* L, const double* c) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  if (!c) return fail(SL_E_INVALID, "coefficients are NULL");
+  double scale = 1.0;
+  for (int k = 0; k < 4; ++k) {
+    if (!std::isfinite(c[k])) return fail(SL_E_INVALID, "coefficient %d is not finite", k);
+    scale += std::fabs(c[k]) * (k == 0 ? 1 : (k == 1 ? 6 : (k == 2 ? 12 : 8)));
+  }
+  if (std::fabs(c[0] + 6.0 * c[1] + 12.0 * c[2] + 8.0 * c[3]) > 1e-12 * scale)
+    return fail(SL_E_INVALID, "stencil must annihilate constants: c0 + 6 c1 + 12 c2 + 8 c3 = 0");
+  if (std::fabs(c[1] + 4.0 * c[2] + 4.0 * c[3] - 1.0) > 1e-12 * scale)
+    return fail(SL_E_INVALID, "stencil must tend to the Laplacian: c1 + 4 c2 + 4 c3 = 1");
+  const int kind = (c[0] == -6.0 && c[1] == 1.0 && c[2] == 0.0 && c[3] == 0.0) ? 0 : 1;
+  if (L->batch && kind != L->v.st.kind)
+    return fail(SL_E_STATE, "a batch member keeps its stencil kind (remove it from the batch first)");
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  Stencil st{{c[0], c[1], c[2], c[3]}, kind, 0};
+  // the symbol is multilinear in the three cosines: its extremes over the
+  // zone sit at the vertices k_d in {0, pi}
+  double kmax = 0.0;
+  for (int v = 0; v < 8; ++v) {
+    const double cz = (v & 4) ? -1.0 : 1.0, cy = (v & 2) ? -1.0 : 1.0, cx = (v & 1) ? -1.0 : 1.0;
+    const double sym = c[0] + 2.0 * c[1] * (cz + cy + cx) + 4.0 * c[2] * (cz * cy + cz * cx + cy * cx) +
+                       8.0 * c[3] * cz * cy * cx;
+    if (-sym > kmax) kmax = -sym;
+  }
+  const int old_kind = L->v.st.kind;
+  L->v.st = st;
+  L->keff2_max = kmax;
+  if (kind != old_kind) {
+    int tx = L->v.tile.tx, vx = L->v.tile.vx, pf = L->v.tile.pf;
+    if (kind != 0) {
+      vx = 1;
+      pf = 1;
+    } else {
+      default_shape(L->cfg.n, L->cfg.precision, L->cfg.nfields, &tx, &vx, &pf);
+    }
+    if (L->pot_set) {
+      const TuneKey key{L->device, L->cfg.n, L->cfg.nfields, L->cfg.precision, L->v.pot, kind};
+      for (const auto& kv : tune_cache()) {
+        if (kv.first == key) {
+          tx = kv.second.tx;
+          vx = kv.second.vx;
+          pf = kv.second.pf;
+          L->tz_user = kv.second.tz;
+        }
+      }
+    }
+    retile(L, tx, vx, L->tz_user, pf);
+  }
+  if (L->batch) batch_member_changed(L->batch);
+  return SL_OK;
+}
+
+sl_status sl_get_stencil(sl_lattice* L, double* c_out) {
+  if (!L || !c_out) return fail(SL_E_INVALID, "lattice handle or output is NULL");
+  for (int k = 0; k < 4; ++k) c_out[k] = L->v.st.c[k];
   return SL_OK;
 }
 
@@ -868,6 +937,7 @@ struct sl_batch {
   std::vector<sl_lattice*> runs;
   int prec = -1, pot = -1, nf = -1;
   Tile shape{};  // carries vx and pf of every member
+  int st_kind = 0;  // stencil kind of every member
   PassParams* pass_dev = nullptr;
   BatchRun* run_dev = nullptr;
   int* start_dev = nullptr;
@@ -885,6 +955,17 @@ struct sl_batch {
   int g_order = 0;
   uint64_t g_version = ~0ull;
 };
+
+namespace {
+
+}  // namespace
+
+// A member's tile or stencil changed: re-upload the run table and capture
+// a new graph at the next step.
+void batch_member_changed(sl_batch* B) {
+  B->dirty = true;
+  ++B->version;
+}
 
 namespace {
 
@@ -938,7 +1019,8 @@ sl_status batch_upload(sl_batch* B) {
   HIP_TRY(hipStreamSynchronize(B->stream));
   B->total_tiles = start[R];
   B->lds = lds;
-  const long resident = long(batched_blocks_per_cu(B->prec, B->pot, B->nf, B->shape, lds)) * device_cus();
+  const long resident =
+      long(batched_blocks_per_cu(B->prec, B->pot, B->nf, B->shape, B->st_kind, lds)) * device_cus();
   B->grid = int(B->total_tiles < resident ? B->total_tiles : resident);
   if (B->grid < 1) B->grid = 1;
   B->dirty = false;
@@ -955,7 +1037,7 @@ sl_status batch_enqueue(sl_batch* B, int64_t steps, double dt, const std::vector
       const bool last_stage = j == s - 1;
       const int has_next = !(last_stage && step == steps - 1);
       const double wn = last_stage ? w[0] : w[j + 1];
-      HIP_TRY(launch_batched_pass(B->prec, B->pot, B->nf, B->shape, B->lds, B->pass_dev,
+      HIP_TRY(launch_batched_pass(B->prec, B->pot, B->nf, B->shape, B->st_kind, B->lds, B->pass_dev,
                                   B->start_dev, R, B->grid, B->stream));
       HIP_TRY(launch_batched_finalize(B->run_dev, R, w[j], wn, dt, has_next, last_stage ? 1 : 0,
                                       B->stream));
@@ -1015,10 +1097,13 @@ sl_status sl_batch_add(sl_batch* B, sl_lattice* L) {
     B->pot = L->v.pot;
     B->nf = L->cfg.nfields;
     B->shape = L->v.tile;
+    B->st_kind = L->v.st.kind;
   } else if (L->cfg.precision != B->prec || L->v.pot != B->pot || L->cfg.nfields != B->nf ||
-             L->v.tile.vx != B->shape.vx || L->v.tile.pf != B->shape.pf) {
+             L->v.tile.vx != B->shape.vx || L->v.tile.pf != B->shape.pf ||
+             L->v.st.kind != B->st_kind) {
     return fail(SL_E_INVALID,
-                "batch members share precision, potential family, field count, vx and pf");
+                "batch members share precision, potential family, field count, stencil kind, vx "
+                "and pf");
   }
   HIP_TRY(hipStreamSynchronize(B->stream));
   B->runs.push_back(L);

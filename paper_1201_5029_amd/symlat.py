@@ -30,8 +30,21 @@ EXPORTS = (
     "sl_get_tile", "sl_set_tile", "sl_hbm_copy_bench",
     "sl_batch_create", "sl_batch_destroy", "sl_batch_add", "sl_batch_remove",
     "sl_batch_count", "sl_batch_step", "sl_batch_synchronize", "sl_device_memory",
-    "sl_autotune", "sl_autotune_forget",
+    "sl_autotune", "sl_autotune_forget", "sl_set_stencil", "sl_get_stencil",
+    "sl_linear_create", "sl_linear_destroy", "sl_linear_set_potential",
+    "sl_linear_set_stencil", "sl_linear_set_fields", "sl_linear_evolve",
+    "sl_linear_get_fields", "sl_linear_get_background", "sl_linear_classes",
+    "sl_linear_synchronize", "sl_linear_set_kernel_timing", "sl_linear_kernel_timing",
 )
+
+#: Members of the cubic stencil family of eq. (2.7): (centre, face, edge,
+#: corner) weights.  "19" and "27" are the members with isotropic leading
+#: error (c1 = 2 c2 + 8 c3) without and with corner weights.
+STENCILS = {
+    "7": (-6.0, 1.0, 0.0, 0.0),
+    "19": (-4.0, 1.0 / 3.0, 1.0 / 6.0, 0.0),
+    "27": (-128.0 / 30.0, 14.0 / 30.0, 3.0 / 30.0, 1.0 / 30.0),
+}
 
 
 class SymlatError(RuntimeError):
@@ -99,6 +112,20 @@ def load():
         "sl_device_memory": (I32, [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
         "sl_autotune": (I32, [P, I32, I32, I32] + [ctypes.POINTER(I32)] * 4 + [dp]),
         "sl_autotune_forget": (I32, []),
+        "sl_set_stencil": (I32, [P, dp]),
+        "sl_get_stencil": (I32, [P, dp]),
+        "sl_linear_create": (I32, [ctypes.POINTER(Config), P, ctypes.POINTER(P)]),
+        "sl_linear_destroy": (I32, [P]),
+        "sl_linear_set_potential": (I32, [P, I32, dp, I32]),
+        "sl_linear_set_stencil": (I32, [P, dp]),
+        "sl_linear_set_fields": (I32, [P, P, P, D]),
+        "sl_linear_evolve": (I32, [P, I64, D, I32]),
+        "sl_linear_get_fields": (I32, [P, P, P]),
+        "sl_linear_get_background": (I32, [P, dp, dp, dp, dp, dp]),
+        "sl_linear_classes": (I32, [P, ctypes.POINTER(I64)]),
+        "sl_linear_synchronize": (I32, [P]),
+        "sl_linear_set_kernel_timing": (I32, [P, I32]),
+        "sl_linear_kernel_timing": (I32, [P, ctypes.POINTER(I64), dp, dp, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -200,6 +227,19 @@ class Lattice:
         params = list(params)
         _check(self._lib.sl_set_potential(self._h, POTENTIAL[kind], _dvec(params, len(params)),
                                           len(params)))
+
+    def set_stencil(self, c):
+        """Laplacian weights (centre, face, edge, corner): a name of
+        STENCILS or a 4-sequence."""
+        c = STENCILS[c] if isinstance(c, str) else tuple(float(v) for v in c)
+        if len(c) != 4:
+            raise ValueError("a stencil has 4 weights")
+        _check(self._lib.sl_set_stencil(self._h, _dvec(c, 4)))
+
+    def stencil(self):
+        buf = (ctypes.c_double * 4)()
+        _check(self._lib.sl_get_stencil(self._h, buf))
+        return tuple(buf[i] for i in range(4))
 
     def init_fluctuations(self, phi0, pi0, kind="vacuum", amplitude=0.0, seed=0):
         _check(self._lib.sl_init_fluctuations(
@@ -323,6 +363,85 @@ class Batch:
             pass
 
 
+class Linear:
+    """Linearized integrator: homogeneous background plus Fourier-space
+    perturbations advanced through growth functions per k_eff^2 class."""
+
+    def __init__(self, n, nfields, L, expand=True, mpl=1.0, a0=1.0, rho_rad0=0.0,
+                 rho_mat0=0.0, stream=None):
+        self._lib = load()
+        self.n, self.nfields = int(n), int(nfields)
+        cfg = make_config(n, nfields, L, "f64", expand, mpl, a0, rho_rad0, rho_mat0)
+        h = ctypes.c_void_p()
+        _check(self._lib.sl_linear_create(ctypes.byref(cfg), ctypes.c_void_p(stream or 0),
+                                          ctypes.byref(h)))
+        self._h = h
+
+    def set_potential(self, kind, params):
+        params = list(params)
+        _check(self._lib.sl_linear_set_potential(self._h, POTENTIAL[kind],
+                                                 _dvec(params, len(params)), len(params)))
+
+    def set_stencil(self, c):
+        c = STENCILS[c] if isinstance(c, str) else tuple(float(v) for v in c)
+        _check(self._lib.sl_linear_set_stencil(self._h, _dvec(c, 4)))
+
+    def set_fields(self, phi, pi, p_a=math.nan):
+        shape = (self.nfields, self.n, self.n, self.n)
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(shape)
+        pi = np.ascontiguousarray(pi, dtype=np.float64).reshape(shape)
+        _check(self._lib.sl_linear_set_fields(self._h, phi.ctypes.data, pi.ctypes.data,
+                                              float(p_a)))
+
+    def evolve(self, steps, dt, order=4):
+        _check(self._lib.sl_linear_evolve(self._h, int(steps), float(dt), int(order)))
+
+    def get_fields(self):
+        shape = (self.nfields, self.n, self.n, self.n)
+        phi = np.empty(shape)
+        pi = np.empty(shape)
+        _check(self._lib.sl_linear_get_fields(self._h, phi.ctypes.data, pi.ctypes.data))
+        return phi, pi
+
+    def background(self):
+        """(eta, a, p_a, phi0, pi0)."""
+        v = [ctypes.c_double() for _ in range(3)]
+        f0 = (ctypes.c_double * self.nfields)()
+        p0 = (ctypes.c_double * self.nfields)()
+        _check(self._lib.sl_linear_get_background(self._h, *[ctypes.byref(x) for x in v], f0, p0))
+        return v[0].value, v[1].value, v[2].value, list(f0), list(p0)
+
+    def classes(self):
+        c = ctypes.c_int64()
+        _check(self._lib.sl_linear_classes(self._h, ctypes.byref(c)))
+        return c.value
+
+    def synchronize(self):
+        _check(self._lib.sl_linear_synchronize(self._h))
+
+    def set_kernel_timing(self, enable):
+        _check(self._lib.sl_linear_set_kernel_timing(self._h, 1 if enable else 0))
+
+    def kernel_timing(self):
+        """(growth launches, growth ms, background-table ms, apply ms)."""
+        n = ctypes.c_int64()
+        g, t, a = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.sl_linear_kernel_timing(self._h, ctypes.byref(n), ctypes.byref(g),
+                                                 ctypes.byref(t), ctypes.byref(a)))
+        return n.value, g.value, t.value, a.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.sl_linear_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def from_recipe(r, stream=None):
     """Lattice with potential set and initial state drawn from a workload
     recipe dict (see the synth module)."""
@@ -330,5 +449,7 @@ def from_recipe(r, stream=None):
                   expand=r.get("expand", True), mpl=r["mpl"], a0=r.get("a0", 1.0),
                   stream=stream)
     lat.set_potential(r["potential"], r["params"])
+    if r.get("stencil") is not None:
+        lat.set_stencil(r["stencil"])
     lat.init_fluctuations(r["phi0"], r["pi0"], r["fluct"], r["amplitude"], r["seed"])
     return lat

@@ -16,10 +16,11 @@ def say(*a):
 
 
 def oracle_lattice(n, L, kind, params, phi, pi, mpl=1.0, a0=1.0, rho_rad0=0.0,
-                   rho_mat0=0.0, expand=True, p_a=None):
+                   rho_mat0=0.0, expand=True, p_a=None, stencil=None):
     pot = oracle.Potential(kind, params)
     lat = oracle.Lattice(n, L, pot, mpl=mpl, a0=a0, rho_rad0=rho_rad0,
-                         rho_mat0=rho_mat0, expand=expand)
+                         rho_mat0=rho_mat0, expand=expand,
+                         stencil=oracle.STENCIL_7 if stencil is None else stencil)
     lat.phi[...] = phi
     lat.pi[...] = pi
     if p_a is None:
@@ -30,10 +31,13 @@ def oracle_lattice(n, L, kind, params, phi, pi, mpl=1.0, a0=1.0, rho_rad0=0.0,
 
 
 def gpu_lattice(n, L, kind, params, phi, pi, precision="f64", mpl=1.0, a0=1.0,
-                rho_rad0=0.0, rho_mat0=0.0, expand=True, p_a=math.nan, tile=None):
+                rho_rad0=0.0, rho_mat0=0.0, expand=True, p_a=math.nan, tile=None,
+                stencil=None):
     g = sl.Lattice(n, phi.shape[0], L, precision=precision, expand=expand, mpl=mpl,
                    a0=a0, rho_rad0=rho_rad0, rho_mat0=rho_mat0)
     g.set_potential(kind, params)
+    if stencil is not None:
+        g.set_stencil(stencil)
     if tile is not None:
         g.set_tile(*tile)
     g.set_fields(phi, pi, a0, p_a)

@@ -1,0 +1,157 @@
+"""GPU parity of the linearized integrator (growth functions per k_eff^2
+class, Sec. 2.2 and 2.4) against the FP64 oracle that evolves every Fourier
+mode on its own; FP64 gate 1e-10 on the fields (per array, normalised by
+the array's max |value|) and on the background."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1201_5029_amd as sl
+import synth
+from gpu_util import max_rel, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _state(n, nf, seed, base, pibase, amp):
+    return synth.gaussian_state(n, nf, seed, phi_base=base, phi_amp=amp, pi_base=pibase,
+                                pi_amp=amp)
+
+
+def _pair(n, L, kind, params, phi, pi, mpl=1.0, stencil=None, expand=True, a0=1.0):
+    pot = oracle.Potential(kind, params)
+    o = oracle.LinearLattice(n, L, pot, mpl=mpl, a0=a0, expand=expand,
+                             stencil=oracle.STENCIL_7 if stencil is None else stencil)
+    o.set_fields(phi, pi)
+    g = sl.Linear(n, pot.nfields, L, expand=expand, mpl=mpl, a0=a0)
+    g.set_potential(kind, params)
+    if stencil is not None:
+        g.set_stencil(stencil)
+    g.set_fields(phi, pi)
+    return o, g
+
+
+def _compare(o, g, tag):
+    phi, pi = g.get_fields()
+    ophi, opi = o.fields()
+    eta, a, pa, f0, p0 = g.background()
+    # perturbations relative to their own size, and the full fields
+    dphi = phi - np.mean(phi, axis=(1, 2, 3), keepdims=True)
+    odphi = ophi - np.mean(ophi, axis=(1, 2, 3), keepdims=True)
+    dpi = pi - np.mean(pi, axis=(1, 2, 3), keepdims=True)
+    odpi = opi - np.mean(opi, axis=(1, 2, 3), keepdims=True)
+    errs = dict(dphi=max_rel(dphi, odphi), dpi=max_rel(dpi, odpi),
+                a=abs(a - o.a) / abs(o.a),
+                p_a=abs(pa - o.p_a) / max(abs(o.p_a), 1e-300) if o.p_a else abs(pa),
+                phi0=max(abs(x - y) / max(abs(y), 1e-300) for x, y in zip(f0, o.phi0)),
+                pi0=max(abs(x - y) / max(abs(y), 1e-30) for x, y in zip(p0, o.pi0)))
+    say(tag, errs)
+    assert eta == pytest.approx(o.eta, rel=1e-14)
+    return errs
+
+
+PREHEAT = synth.preheat(n=16)
+
+
+@pytest.mark.parametrize("order,steps", [(2, 80), (4, 60), (6, 40)])
+def test_linear_preheat_fp64(order, steps):
+    n = 16
+    phi, pi = _state(n, 2, 41, PREHEAT["phi0"], [0.0, 0.0], 1e-4)
+    o, g = _pair(n, PREHEAT["L"], "chaotic2", PREHEAT["params"], phi, pi, mpl=PREHEAT["mpl"])
+    assert g.classes() == math.comb(n // 2 + 3, 3)
+    g.evolve(steps, PREHEAT["dt"], order)
+    o.evolve(steps, PREHEAT["dt"], order)
+    e = _compare(o, g, "linear preheat order %d" % order)
+    assert max(e.values()) <= TOL
+
+
+def test_linear_multichunk_order8_odd_n():
+    """15 stages x 150 steps = 2250 stages: more than one background chunk;
+    odd n folds n_d and n - n_d with no self-paired Nyquist plane."""
+    n = 9
+    phi, pi = _state(n, 2, 42, [0.9, 0.05], [0.01, 0.0], 1e-3)
+    o, g = _pair(n, 4.0, "chaotic2", (1.0, 30.0), phi, pi, mpl=0.8)
+    g.evolve(150, 0.01, 8)
+    o.evolve(150, 0.01, 8)
+    e = _compare(o, g, "linear multichunk")
+    assert max(e.values()) <= TOL
+
+
+@pytest.mark.parametrize("kind,params,nf,base,pibase,mpl", [
+    ("oscillon", (1.0, 1.0, 0.2), 1, [0.8], [0.0], 335.41),
+    ("qball", (1.0, -0.1, 1.0), 2, [math.sqrt(2) * 1e-2, 0.0], [0.0, 0.5 * math.sqrt(2) * 1e-2], 1.0),
+    ("free", (1.0, 2.0, 0.5), 3, [0.3, -0.2, 0.1], [0.01, 0.0, -0.02], 1.5),
+    ("free", (1.0, 2.0, 0.5, 3.0), 4, [0.3, -0.2, 0.1, 0.05], [0.01, 0.0, -0.02, 0.0], 1.5),
+])
+def test_linear_potentials_fp64(kind, params, nf, base, pibase, mpl):
+    n = 12
+    phi, pi = _state(n, nf, 43, base, pibase, 1e-4 * max(abs(b) for b in base))
+    o, g = _pair(n, 6.0, kind, params, phi, pi, mpl=mpl)
+    g.evolve(40, 0.01, 4)
+    o.evolve(40, 0.01, 4)
+    e = _compare(o, g, "linear " + kind)
+    assert max(e.values()) <= TOL
+
+
+def test_linear_27_point_and_static():
+    n = 14
+    phi, pi = _state(n, 2, 44, PREHEAT["phi0"], [0.0, 0.0], 1e-4)
+    o, g = _pair(n, PREHEAT["L"], "chaotic2", PREHEAT["params"], phi, pi, mpl=PREHEAT["mpl"],
+                 stencil=oracle.STENCIL_27)
+    g.evolve(50, PREHEAT["dt"], 4)
+    o.evolve(50, PREHEAT["dt"], 4)
+    e = _compare(o, g, "linear 27-point")
+    assert max(e.values()) <= TOL
+    phi, pi = _state(n, 1, 45, [0.2], [0.1], 0.3)
+    o, g = _pair(n, 5.0, "free", (0.7,), phi, pi, expand=False, a0=1.2)
+    g.evolve(60, 0.03, 6)
+    o.evolve(60, 0.03, 6)
+    e = _compare(o, g, "linear static free")
+    assert max(e.values()) <= TOL
+
+
+def test_linear_free_static_equals_nonlinear_gpu():
+    """A free field in a static background is linear: the growth-function
+    path and the fused lattice pass agree to rounding."""
+    n = 16
+    phi, pi = _state(n, 2, 46, [0.3, -0.1], [0.05, 0.0], 0.2)
+    g = sl.Linear(n, 2, 4.0, expand=False)
+    g.set_potential("free", (0.9, 1.6))
+    g.set_fields(phi, pi)
+    lat = sl.Lattice(n, 2, 4.0, precision="f64", expand=False)
+    lat.set_potential("free", (0.9, 1.6))
+    lat.set_fields(phi, pi, 1.0, 0.0)
+    g.evolve(100, 0.02, 4)
+    lat.evolve(100, 0.02, 4)
+    lphi, lpi = g.get_fields()
+    nphi, npi = lat.get_fields()
+    say("linear vs lattice", max_rel(lphi, nphi), max_rel(lpi, npi))
+    assert max_rel(lphi, nphi) <= TOL and max_rel(lpi, npi) <= TOL
+
+
+def test_linear_split_calls_and_errors():
+    n = 10
+    phi, pi = _state(n, 2, 47, PREHEAT["phi0"], [0.0, 0.0], 1e-4)
+    _, g1 = _pair(n, PREHEAT["L"], "chaotic2", PREHEAT["params"], phi, pi, mpl=PREHEAT["mpl"])
+    _, g2 = _pair(n, PREHEAT["L"], "chaotic2", PREHEAT["params"], phi, pi, mpl=PREHEAT["mpl"])
+    g1.evolve(30, PREHEAT["dt"], 4)
+    g2.evolve(11, PREHEAT["dt"], 4)
+    g2.evolve(19, PREHEAT["dt"], 4)
+    f1, p1 = g1.get_fields()
+    f2, p2 = g2.get_fields()
+    assert max_rel(f1, f2) <= 1e-12 and max_rel(p1, p2) <= 1e-12
+    assert g1.background()[:3] == g2.background()[:3]
+    with pytest.raises(sl.SymlatError):
+        sl.Linear(8, 5, 1.0)
+    with pytest.raises(sl.SymlatError):
+        sl.Linear(8, 2, 1.0).evolve(1, 0.01, 4)          # no potential / state
+    with pytest.raises(sl.SymlatError):
+        g1.evolve(1, 1.0, 4)                             # unstable
+    with pytest.raises(sl.SymlatError):
+        g1.evolve(1, 0.01, 3)
+    with pytest.raises(sl.SymlatError):
+        g1.set_stencil((-6.0, 1.0, 0.1, 0.0))
