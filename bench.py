@@ -38,6 +38,9 @@ def parse():
     p.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage line")
     p.add_argument("--no-serve", action="store_true", help="skip the served ensemble")
     p.add_argument("--no-512", action="store_true", help="skip the 512^3 FP32 line")
+    p.add_argument("--no-batched", action="store_true", help="skip the batched ensemble line")
+    p.add_argument("--no-27", action="store_true", help="skip the 27-point stencil line")
+    p.add_argument("--no-linear", action="store_true", help="skip the linearized-integrator line")
     p.add_argument("--serve-runs", type=int, default=96)
     p.add_argument("--serve-steps", type=int, default=500)
     p.add_argument("--tile", default=None,
@@ -145,6 +148,105 @@ def measure_served(sl, nruns, steps):
         "efolds_rel_err_fp32_vs_fp64_max": float(max(errs)),
         "unit": "field-site-updates/s",
     }
+
+
+def measure_batched(sl, nruns=96, steps=100):
+    """The Delta-N ensemble (96 runs, n in {32, 64, 96}, FP32, 4th order)
+    as one batch: pass shapes from the batch autotuner, then `steps` steps
+    of the captured batch.  The batched pass time is the tuner's HIP-event
+    timing of the pass alone."""
+    import synth
+    recipes = synth.delta_n_scan(nruns=nruns, steps=steps)
+    dt, order = recipes[0]["dt"], recipes[0]["order"]
+    lats = [sl.from_recipe(r) for r in recipes]
+    b = sl.Batch()
+    for lat in lats:
+        b.add(lat)
+    pass_ms = b.autotune(reps=5)
+    shapes = sorted(set((r["n"],) + tuple(lat.tile()) for r, lat in zip(recipes, lats)))
+    b.step(10, dt, order)
+    b.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps, dt, order)
+    b.synchronize()
+    wall = time.perf_counter() - t0
+    sites = sum(r["n"] ** 3 for r in recipes)
+    stages = len(sl.composition_weights(order))
+    bytes_pass = 4 * 4 * 2 * sites
+    b.close()
+    for lat in lats:
+        lat.close()
+    return {"workload": "%d preheat runs, n in {32, 64, 96}, FP32 fields, order 4, one batch"
+                        % nruns,
+            "value": sites * 2 * steps / wall, "unit": "field-site-updates/s",
+            "ms_per_step": wall / steps * 1e3,
+            "effective_GBs": bytes_pass * stages * steps / wall / 1e9,
+            "pass_ms": pass_ms, "pass_achieved_GBs": bytes_pass / (pass_ms * 1e-3) / 1e9,
+            "pass_frac": bytes_pass / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "bytes_per_pass": bytes_pass, "shapes_n_tx_vx_ty_tz_pf": shapes}
+
+
+def measure_stencil27(sl, steps=50, warmup=5):
+    """The 256^3 preheating workload (FP64, 6th order) with the isotropic
+    27-point member of the stencil family: same algorithmic bytes per pass
+    as the 7-point pass."""
+    import synth
+    r = dict(synth.preheat(n=256, order=6, dt=0.0025, precision="f64"), stencil="27")
+    wall, passes, pass_ms, e, tile = measure(sl, r, steps, warmup)
+    n3 = 256 ** 3
+    avg = pass_ms / passes / 1e3
+    return {"workload": "preheat two-field chaotic, 256^3, order 6, FP64, 27-point stencil "
+                        "(-128, 14, 3, 1)/30",
+            "value": n3 * 2 * steps / wall, "ms_per_step": wall / steps * 1e3,
+            "pass_ms": avg * 1e3, "achieved_GBs": 4 * 8 * 2 * n3 / avg / 1e9,
+            "frac": 4 * 8 * 2 * n3 / avg / 1e9 / HBM_PEAK_GBS, "tile": list(tile),
+            "friedmann_residual": e["friedmann_residual"]}
+
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CUs x 128 FP64 flops/clock x 2.4 GHz
+
+
+def measure_linear(sl, n=256, steps=400, order=6, warmup=20):
+    """Linearized integrator on the 256^3 preheating state: growth
+    functions per k_eff^2 class, then every Fourier mode advanced.  The
+    growth kernel is FP64 ALU work: per class column and stage
+    2 (N_f^2 + 3 N_f) flops (two drifts, the k_eff^2 term and the Hessian
+    product as fused multiply-adds)."""
+    import synth
+    r = synth.preheat(n=n, order=order, dt=0.0025, precision="f64")
+    lat = sl.from_recipe(r)
+    phi, pi = lat.get_fields()
+    lat.close()
+    nf = r["nfields"]
+    lin = sl.Linear(n, nf, r["L"], mpl=r["mpl"])
+    lin.set_potential(r["potential"], r["params"])
+    lin.set_fields(phi, pi)
+    del phi, pi
+    lin.evolve(warmup, r["dt"], order)
+    lin.synchronize()
+    t0 = time.perf_counter()
+    lin.evolve(steps, r["dt"], order)
+    lin.synchronize()
+    wall = time.perf_counter() - t0
+    lin.set_kernel_timing(True)
+    lin.evolve(steps, r["dt"], order)
+    launches, g_ms, t_ms, a_ms = lin.kernel_timing()
+    lin.set_kernel_timing(False)
+    ncls = lin.classes()
+    stages = len(sl.composition_weights(order)) * steps
+    flops = ncls * 2 * nf * stages * 2 * (nf * nf + 3 * nf)
+    achieved = flops / (g_ms * 1e-3) / 1e12
+    lin.close()
+    return {"workload": "linearized preheat two-field chaotic, %d^3, order %d, dt 0.0025, FP64"
+                        % (n, order),
+            "value": n ** 3 * nf * steps / wall, "unit": "field-site-updates/s",
+            "ms_per_step": wall / steps * 1e3, "classes": ncls,
+            "growth": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                       "launches": launches, "ms": g_ms, "flops": flops},
+            "background_table_ms": t_ms,
+            "apply_ms": a_ms,
+            "apply_GBs": n ** 3 * 2 * 2 * nf * 16 / (a_ms * 1e-3) / 1e9 if a_ms > 0 else None}
 
 
 def measure_qball512(sl, steps=20, warmup=3):
@@ -260,6 +362,15 @@ def main():
     if not args.no_512 and args.precision == "f64" and args.n == 256:
         log("512^3 FP32 Q-ball ...")
         out["qball512_fp32"] = measure_qball512(sl)
+    if not args.no_batched and args.precision == "f64" and args.n == 256:
+        log("batched ensemble ...")
+        out["batched_c4"] = measure_batched(sl)
+    if not args.no_27 and args.precision == "f64" and args.n == 256:
+        log("27-point stencil ...")
+        out["stencil27_fp64"] = measure_stencil27(sl)
+    if not args.no_linear and args.precision == "f64" and args.n == 256:
+        log("linearized integrator ...")
+        out["linear_fp64"] = measure_linear(sl)
     if not args.no_serve:
         log("served ensemble ...")
         out["served"] = measure_served(sl, args.serve_runs, args.serve_steps)

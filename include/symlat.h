@@ -251,7 +251,8 @@ sl_status sl_set_tile(sl_lattice* lat, int32_t tx, int32_t vx, int32_t tz, int32
  * (0 = free) restrict the search, e.g. to the per-lane shape of a batch.
  * The winner is applied and remembered for this process: lattices created
  * later with the same (device, n, fields, precision, potential family) start
- * with it.  Outputs may be NULL.  sl_autotune_forget clears that memory. */
+ * with it.  Outputs may be NULL.  sl_autotune_forget clears that memory and
+ * the batch tuner's. */
 sl_status sl_autotune(sl_lattice* lat, int32_t reps, int32_t vx_only, int32_t pf_only,
                       int32_t* tx, int32_t* vx, int32_t* tz, int32_t* pf, double* best_ms);
 sl_status sl_autotune_forget(void);
@@ -277,6 +278,17 @@ sl_status sl_batch_remove(sl_batch* batch, sl_lattice* lat);
 sl_status sl_batch_count(const sl_batch* batch, int32_t* count);
 /* Advance every member `steps` steps (same dt and order for all). */
 sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order);
+/* Batch autotuner: per member size (largest share of sites first, two
+ * rounds of coordinate descent) try tx in {16, 32, 64} and z-chunks n/{1, 2,
+ * 4, 8} for all members of that size, timing the batched pass alone (best
+ * of `reps` HIP-event timings of two passes; the members' states are left
+ * unchanged), and keep a shape only if it is at least 0.5 % faster.  vx
+ * and pf stay the batch's.  The chosen shapes are applied to the members
+ * (also for their own sl_evolve calls) and remembered for this process:
+ * lattices of a tuned size that join a batch later are given that shape.
+ * best_ms (may be NULL) receives the final pass time.  SL_E_STATE for an
+ * empty batch. */
+sl_status sl_batch_autotune(sl_batch* batch, int32_t reps, double* best_ms);
 /* Wait for the batch and report members' sticky device errors. */
 sl_status sl_batch_synchronize(sl_batch* batch);
 

@@ -219,6 +219,18 @@ std::vector<std::pair<TuneKey, TuneVal>>& tune_cache() {
   return c;
 }
 
+// Process-wide cache of batch-tuned member shapes: (device, n, fields,
+// precision, potential, stencil kind) plus the batch's vx and pf -> (tx, tz).
+struct BatchTuneKey {
+  TuneKey k;
+  int vx, pf;
+  bool operator==(const BatchTuneKey& o) const { return k == o.k && vx == o.vx && pf == o.pf; }
+};
+std::vector<std::pair<BatchTuneKey, TuneVal>>& batch_tune_cache() {
+  static std::vector<std::pair<BatchTuneKey, TuneVal>> c;
+  return c;
+}
+
 }  // namespace
 
 struct sl_lattice {
@@ -827,6 +839,7 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
 
 sl_status sl_autotune_forget(void) {
   tune_cache().clear();
+  batch_tune_cache().clear();
   return SL_OK;
 }
 
@@ -1106,6 +1119,18 @@ sl_status sl_batch_add(sl_batch* B, sl_lattice* L) {
                 "and pf");
   }
   HIP_TRY(hipStreamSynchronize(B->stream));
+  {
+    // a size the batch tuner has seen before starts with its tuned shape
+    const BatchTuneKey key{{L->device, L->cfg.n, L->cfg.nfields, L->cfg.precision, L->v.pot, L->v.st.kind},
+                           L->v.tile.vx, L->v.tile.pf};
+    for (const auto& kv : batch_tune_cache()) {
+      if (kv.first == key && (kv.second.tx != L->v.tile.tx || kv.second.tz != L->v.tile.tz)) {
+        HIP_TRY(hipStreamSynchronize(L->stream));
+        L->tz_user = kv.second.tz;
+        retile(L, kv.second.tx, L->v.tile.vx, kv.second.tz, L->v.tile.pf);
+      }
+    }
+  }
   B->runs.push_back(L);
   L->batch = B;
   B->dirty = true;
@@ -1127,6 +1152,123 @@ sl_status sl_batch_remove(sl_batch* B, sl_lattice* L) {
     }
   }
   return fail(SL_E_INVALID, "lattice is not in this batch");
+}
+
+sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
+  if (!B) return fail(SL_E_INVALID, "batch handle is NULL");
+  if (reps < 1 || reps > 100) return fail(SL_E_INVALID, "reps must be in [1, 100]");
+  if (B->runs.empty()) return fail(SL_E_STATE, "the batch has no members");
+  for (sl_lattice* L : B->runs) HIP_TRY(hipStreamSynchronize(L->stream));
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  // member sizes, largest share of the sites first
+  std::vector<std::pair<double, int>> sizes;
+  for (sl_lattice* L : B->runs) {
+    bool seen = false;
+    for (auto& s : sizes)
+      if (s.second == L->cfg.n) {
+        s.first += double(L->n3);
+        seen = true;
+      }
+    if (!seen) sizes.push_back({double(L->n3), L->cfg.n});
+  }
+  std::sort(sizes.begin(), sizes.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+    return a.first > b.first;
+  });
+  const int vx = B->shape.vx, pf = B->shape.pf;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  // time the batched pass alone: without its finalize it leaves every
+  // member's state as it was (reads the current buffer, writes the spare
+  // buffer and the partials)
+  auto time_now = [&](double* ms_out) -> sl_status {
+    sl_status st = batch_upload(B);
+    if (st != SL_OK) return st;
+    double best = 1e300;
+    HIP_TRY(launch_batched_pass(B->prec, B->pot, B->nf, B->shape, B->st_kind, B->lds, B->pass_dev,
+                                B->start_dev, int(B->runs.size()), B->grid, B->stream));
+    for (int r = 0; r < reps; ++r) {
+      HIP_TRY(hipEventRecord(e0, B->stream));
+      for (int k = 0; k < 2; ++k)
+        HIP_TRY(launch_batched_pass(B->prec, B->pot, B->nf, B->shape, B->st_kind, B->lds, B->pass_dev,
+                                    B->start_dev, int(B->runs.size()), B->grid, B->stream));
+      HIP_TRY(hipEventRecord(e1, B->stream));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (0.5 * ms < best) best = 0.5 * ms;
+    }
+    *ms_out = best;
+    return SL_OK;
+  };
+  auto apply = [&](int n, int tx, int tz) {
+    for (sl_lattice* L : B->runs)
+      if (L->cfg.n == n) {
+        L->tz_user = tz;
+        retile(L, tx, vx, tz, pf);
+      }
+    B->dirty = true;
+  };
+  batch_drop_graph(B);
+  double cur = 0.0;
+  sl_status st = time_now(&cur);
+  for (int round = 0; round < 2 && st == SL_OK; ++round) {
+    for (const auto& sz : sizes) {
+      const int n = sz.second;
+      int ref_tx = 0, ref_tz = 0;
+      for (sl_lattice* L : B->runs)
+        if (L->cfg.n == n) {
+          ref_tx = L->v.tile.tx;
+          ref_tz = L->v.tile.tz;
+        }
+      int best_tx = ref_tx, best_tz = ref_tz;
+      for (int tx : {16, 32, 64}) {
+        if (tx * vx > 2 * n && tx != 16) continue;
+        if (B->st_kind != 0 && 2 * tx + 2 * (kBlock / tx) + 4 > kBlock) continue;
+        for (int d : {1, 2, 4, 8}) {
+          const int tz = n / d;
+          if (tz < 4 && d != 1) continue;
+          if (tx == ref_tx && tz == ref_tz) continue;
+          const Tile t = tile_geometry(n, tx, vx, tz, pf);
+          if (long(t.nblocks()) > kMaxPassBlocks) continue;
+          apply(n, tx, tz);
+          double ms = 0.0;
+          st = time_now(&ms);
+          if (st != SL_OK) break;
+          if (ms < cur * 0.995) {
+            cur = ms;
+            best_tx = tx;
+            best_tz = tz;
+          }
+        }
+        if (st != SL_OK) break;
+      }
+      apply(n, best_tx, best_tz);
+      if (st != SL_OK) break;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != SL_OK) return st;
+  // remember the shapes for members added later (this batch or another)
+  for (const auto& sz : sizes) {
+    const sl_lattice* R = nullptr;
+    for (sl_lattice* L : B->runs)
+      if (L->cfg.n == sz.second) R = L;
+    const BatchTuneKey key{{R->device, R->cfg.n, R->cfg.nfields, R->cfg.precision, R->v.pot, R->v.st.kind},
+                           vx, pf};
+    bool found = false;
+    for (auto& kv : batch_tune_cache())
+      if (kv.first == key) {
+        kv.second = {R->v.tile.tx, vx, R->v.tile.tz, pf};
+        found = true;
+      }
+    if (!found) batch_tune_cache().push_back({key, {R->v.tile.tx, vx, R->v.tile.tz, pf}});
+  }
+  B->dirty = true;
+  ++B->version;
+  if (best_ms) *best_ms = cur;
+  return SL_OK;
 }
 
 sl_status sl_batch_count(const sl_batch* B, int32_t* count) {

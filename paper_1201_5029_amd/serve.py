@@ -35,14 +35,19 @@ class Request:
 
 
 def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
-          keep_fields=False, clock=time.perf_counter, sleep=time.sleep):
+          keep_fields=False, tune=True, clock=time.perf_counter, sleep=time.sleep):
     """Run the request loop to completion.  Returns (results, stats).
 
+    tune: before the first tick, let the batch autotuner pick the pass
+    shapes of the runs admitted first (a run is never retiled once it has
+    stepped; later runs of a tuned size start with the tuned shape).
+
     results: one dict per request with id, n, arrival, admitted, completed,
-    latency (s, completion - arrival), eta, a, p_a, efolds = ln a, and the
-    final fields when keep_fields.  stats: p50/p99 latency, makespan, field
-    site-updates, aggregate field-site-updates/s, admissions deferred for
-    memory, peak resident runs."""
+    latency (s, completion - arrival), eta, a, p_a, efolds = ln a, the pass
+    shape it ran with (tile) and the final fields when keep_fields.  stats:
+    p50/p99 latency, makespan, field site-updates, aggregate
+    field-site-updates/s, admissions deferred for memory, peak resident
+    runs."""
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     waiting = deque()
     active = {}  # id -> [request, lattice, steps_done, admitted_at]
@@ -54,6 +59,7 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
     deferred = 0
     peak = 0
     batch = Batch()
+    tuned = not tune
     t0 = clock()
     try:
         while pending or waiting or active:
@@ -79,6 +85,9 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
                 if pending:
                     sleep(max(0.0, pending[0].arrival - (clock() - t0)))
                 continue
+            if not tuned:
+                batch.autotune(reps=3)
+                tuned = True
             k = min(tick_steps, min(a[0].steps - a[2] for a in active.values()))
             batch.step(k, dt, order)
             batch.synchronize()
@@ -92,7 +101,7 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
                     res = dict(id=rid, n=req.recipe["n"], arrival=req.arrival,
                                admitted=entry[3], completed=done_at,
                                latency=done_at - req.arrival, eta=eta, a=a, p_a=p_a,
-                               efolds=math.log(a), steps=req.steps)
+                               efolds=math.log(a), steps=req.steps, tile=lat.tile())
                     if keep_fields:
                         res["phi"], res["pi"] = lat.get_fields()
                     results.append(res)

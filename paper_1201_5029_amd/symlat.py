@@ -35,6 +35,7 @@ EXPORTS = (
     "sl_linear_set_stencil", "sl_linear_set_fields", "sl_linear_evolve",
     "sl_linear_get_fields", "sl_linear_get_background", "sl_linear_classes",
     "sl_linear_synchronize", "sl_linear_set_kernel_timing", "sl_linear_kernel_timing",
+    "sl_batch_autotune",
 )
 
 #: Members of the cubic stencil family of eq. (2.7): (centre, face, edge,
@@ -126,6 +127,7 @@ def load():
         "sl_linear_synchronize": (I32, [P]),
         "sl_linear_set_kernel_timing": (I32, [P, I32]),
         "sl_linear_kernel_timing": (I32, [P, ctypes.POINTER(I64), dp, dp, dp]),
+        "sl_batch_autotune": (I32, [P, I32, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -349,6 +351,13 @@ class Batch:
 
     def synchronize(self):
         _check(self._lib.sl_batch_synchronize(self._h))
+
+    def autotune(self, reps=3):
+        """Tune the members' pass shapes for the batched pass; returns the
+        best pass time (ms)."""
+        ms = ctypes.c_double()
+        _check(self._lib.sl_batch_autotune(self._h, int(reps), ctypes.byref(ms)))
+        return ms.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

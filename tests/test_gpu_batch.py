@@ -95,3 +95,37 @@ def test_batch_rejects_mismatched_members():
     osc = sl.from_recipe(synth.oscillon(n=32))
     with pytest.raises(sl.SymlatError):
         b.add(osc)                   # different potential family
+
+
+def test_batch_autotune_keeps_state_and_equals_alone():
+    """The batch tuner leaves every member's state untouched, applies its
+    shapes to the members, and the batch stays bit-identical to the members
+    advanced alone with those shapes; a later member of a tuned size starts
+    with the tuned shape."""
+    sl.symlat.load().sl_autotune_forget()
+    recipes = _runs("f32", [32, 64, 48, 32])
+    mixed = [sl.from_recipe(r) for r in recipes]
+    before = [m.get_fields() for m in mixed]
+    b = sl.Batch()
+    for m in mixed:
+        b.add(m)
+    ms = b.autotune(reps=2)
+    say("batch autotune best pass ms", ms, [m.tile() for m in mixed])
+    assert ms > 0
+    for m, (f0, p0) in zip(mixed, before):
+        f1, p1 = m.get_fields()
+        assert np.array_equal(f0, f1) and np.array_equal(p0, p1)
+    alone = [sl.from_recipe(r) for r in recipes]
+    for a, m in zip(alone, mixed):
+        tx, vx, _, tz, pf = m.tile()
+        a.set_tile(tx, vx, tz, pf)
+    b.step(12, 0.005, 4)
+    for a in alone:
+        a.evolve(12, 0.005, 4)
+    b.synchronize()
+    for a, m in zip(alone, mixed):
+        assert _same(a, m)
+    late = sl.from_recipe(_runs("f32", [64], base_seed=20120400)[0])
+    b2 = sl.Batch()
+    b2.add(late)
+    assert late.tile() == mixed[1].tile()

@@ -31,6 +31,8 @@ def test_served_results_equal_alone():
     for res in results:
         req = reqs[res["id"]]
         alone = sl.from_recipe(req.recipe)
+        tx, vx, _, tz, pf = res["tile"]
+        alone.set_tile(tx, vx, tz, pf)      # the shape the served run used
         alone.evolve(req.steps, 0.005, 4)
         phi, pi = alone.get_fields()
         eta, a, p_a = alone.background()
