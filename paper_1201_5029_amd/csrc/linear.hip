@@ -41,7 +41,15 @@ namespace symlat {
 namespace {
 
 constexpr int kLinMaxFields = 4;
-constexpr int kLinChunk = 2048;  // stages per background-table chunk
+constexpr int kLinChunk = 512;   // stages per background-table chunk (two buffers)
+// Growth-function columns per lane: the variants are 1, 2 and (one or two
+// fields) a whole class of 2 NF columns.  More columns per lane share each
+// coefficient load and give more independent chains; fewer give more waves.
+// The handle times the variants on its first evolve call and keeps the
+// fastest.
+constexpr int kGrowthVariants = 3;
+template <int NF>
+constexpr int cols_variant(int v) { return v == 0 ? 1 : (v == 1 ? 2 : (NF <= 2 ? 2 * NF : 2)); }
 constexpr int kMaxStages = 15;
 
 struct LinScalars {
@@ -179,8 +187,9 @@ __global__ void lin_constraint_kernel(LinScalars* S, LinConsts K, PotArgs prm) {
 
 // One lane integrates the background through `steps` composed steps and
 // writes the per-stage growth coefficients: tab[st * E + 0] = t/(2 a^2)
-// (the H4 drift), [1] = a^2 t/dx^2 (H5, times k_eff^2), [2 + i NF + j] =
-// a^4 t H_ij(phi0), with a and phi0 at the H4/H5 part of the stage.
+// (the H4 drift), [1] = -a^2 t/dx^2 (H5, times k_eff^2), [2 + i NF + j] =
+// -a^4 t H_ij(phi0), with a and phi0 at the H4/H5 part of the stage (kick
+// terms negated so the growth kernel applies them as fused multiply-adds).
 template <int KIND, int NF>
 __global__ void lin_table_kernel(LinScalars* S, LinConsts K, PotArgs prm, Weights W, double h,
                                  int steps, double* tab) {
@@ -221,11 +230,11 @@ __global__ void lin_table_kernel(LinScalars* S, LinConsts K, PotArgs prm, Weight
       hessian<KIND, NF>(f, pot, H);
       double* t = tab + size_t(k) * E;
       t[0] = cdr;
-      t[1] = a2 * tau * K.inv_dx2;
+      t[1] = -(a2 * tau * K.inv_dx2);
 #pragma unroll
       for (int i = 0; i < NF; ++i)
 #pragma unroll
-        for (int jj = 0; jj < NF; ++jj) t[2 + i * NF + jj] = a4 * tau * H[i][jj];
+        for (int jj = 0; jj < NF; ++jj) t[2 + i * NF + jj] = -(a4 * tau * H[i][jj]);
       for (int rep = 0; rep < 2; ++rep) {
         if (K.expand) pa = pa - 4.0 * a2 * a * K.VL * V * half;
 #pragma unroll
@@ -253,10 +262,13 @@ __global__ void lin_table_kernel(LinScalars* S, LinConsts K, PotArgs prm, Weight
   *S = s;
 }
 
-// Growth functions: lane (class q, column col) holds column col of M(q) --
-// the evolved state that starts as unit vector col -- as NF field rows x
-// and NF momentum rows p, and applies `nst` stages of drift-kick-drift.
-template <int NF>
+// Growth functions: lane (class q, columns c0 .. c0 + CPL - 1) holds those
+// columns of M(q) -- each the evolved state that starts as its unit vector
+// -- as NF field rows x and NF momentum rows p, and applies `nst` stages of
+// drift-kick-drift.  The stage coefficients are wave-uniform; the next
+// stage's are loaded while the current one computes, and CPL columns per
+// lane share each load.
+template <int NF, int CPL>
 __global__ __launch_bounds__(kBlock) void lin_growth_kernel(double* __restrict__ M,
                                                             const double* __restrict__ k2,
                                                             long long ncls,
@@ -264,47 +276,62 @@ __global__ __launch_bounds__(kBlock) void lin_growth_kernel(double* __restrict__
                                                             int nst, int identity) {
   constexpr int R = 2 * NF;
   constexpr int E = 2 + NF * NF;
+  constexpr int LPC = R / CPL;  // lanes per class
+  static_assert(R % CPL == 0, "columns per lane must divide 2 NF");
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ncls * R) return;
-  const long long q = g / R;
-  const int col = int(g - q * R);
-  double x[NF], p[NF];
-  double* m = M + g * R;
-  if (identity) {
+  if (g >= ncls * LPC) return;
+  const long long q = g / LPC;
+  const int c0 = int(g - q * LPC) * CPL;
+  double x[CPL][NF], p[CPL][NF];
+  double* m = M + (q * R + c0) * R;
+#pragma unroll
+  for (int k = 0; k < CPL; ++k)
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      x[i] = (col == i) ? 1.0 : 0.0;
-      p[i] = (col == NF + i) ? 1.0 : 0.0;
+      if (identity) {
+        x[k][i] = (c0 + k == i) ? 1.0 : 0.0;
+        p[k][i] = (c0 + k == NF + i) ? 1.0 : 0.0;
+      } else {
+        x[k][i] = m[k * R + i];
+        p[k][i] = m[k * R + NF + i];
+      }
     }
-  } else {
-#pragma unroll
-    for (int i = 0; i < NF; ++i) {
-      x[i] = m[i];
-      p[i] = m[NF + i];
-    }
-  }
   const double kk = k2[q];
+  double t[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) t[e] = tab[e];
   for (int st = 0; st < nst; ++st) {
-    const double* t = tab + size_t(st) * E;
+    // next stage's coefficients (past the end: the last stage again)
+    const double* tn = tab + size_t(st + 1 < nst ? st + 1 : st) * E;
+    double u[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) u[e] = tn[e];
     const double c = t[0];
-    const double gk = t[1] * kk;
+    const double ngk = t[1] * kk;  // -a^2 t k_eff^2 / dx^2
 #pragma unroll
-    for (int i = 0; i < NF; ++i) x[i] = fma(c, p[i], x[i]);
+    for (int k = 0; k < CPL; ++k) {
 #pragma unroll
-    for (int i = 0; i < NF; ++i) {
-      double f = gk * x[i];
+      for (int i = 0; i < NF; ++i) x[k][i] = fma(c, p[k][i], x[k][i]);
 #pragma unroll
-      for (int j = 0; j < NF; ++j) f = fma(t[2 + i * NF + j], x[j], f);
-      p[i] = p[i] - f;
+      for (int i = 0; i < NF; ++i) {
+        double q = fma(ngk, x[k][i], p[k][i]);
+#pragma unroll
+        for (int j = 0; j < NF; ++j) q = fma(t[2 + i * NF + j], x[k][j], q);
+        p[k][i] = q;
+      }
+#pragma unroll
+      for (int i = 0; i < NF; ++i) x[k][i] = fma(c, p[k][i], x[k][i]);
     }
 #pragma unroll
-    for (int i = 0; i < NF; ++i) x[i] = fma(c, p[i], x[i]);
+    for (int e = 0; e < E; ++e) t[e] = u[e];
   }
 #pragma unroll
-  for (int i = 0; i < NF; ++i) {
-    m[i] = x[i];
-    m[NF + i] = p[i];
-  }
+  for (int k = 0; k < CPL; ++k)
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      m[k * R + i] = x[k][i];
+      m[k * R + NF + i] = p[k][i];
+    }
 }
 
 // Every Fourier mode times its class's M: (dPhi, dPi) <- M (dPhi, dPi).
@@ -366,13 +393,18 @@ int grid_of(size_t work) {
 struct LinFns {
   void (*constraint)(LinScalars*, LinConsts, PotArgs);
   void (*table)(LinScalars*, LinConsts, PotArgs, Weights, double, int, double*);
-  void (*growth)(double*, const double*, long long, const double*, int, int);
+  void (*growth[kGrowthVariants])(double*, const double*, long long, const double*, int, int);
+  int cols[kGrowthVariants];
   void (*apply)(double2*, double2*, const double*, int);
 };
 
 template <int KIND, int NF>
 LinFns fns_t() {
-  return LinFns{lin_constraint_kernel<KIND, NF>, lin_table_kernel<KIND, NF>, lin_growth_kernel<NF>,
+  return LinFns{lin_constraint_kernel<KIND, NF>,
+                lin_table_kernel<KIND, NF>,
+                {lin_growth_kernel<NF, cols_variant<NF>(0)>, lin_growth_kernel<NF, cols_variant<NF>(1)>,
+                 lin_growth_kernel<NF, cols_variant<NF>(2)>},
+                {cols_variant<NF>(0), cols_variant<NF>(1), cols_variant<NF>(2)},
                 lin_apply_kernel<NF>};
 }
 
@@ -419,16 +451,21 @@ struct sl_linear {
   double2* dpi = nullptr;     // nf * n^3 modes of the momentum perturbations
   double* M = nullptr;        // ncls * (2 nf)^2 growth functions
   double* k2 = nullptr;       // ncls values of k_eff^2
-  double* tab = nullptr;      // kLinChunk stages of background coefficients
+  double* tab = nullptr;      // two buffers of kLinChunk stages of coefficients
+  hipStream_t aux = nullptr;  // background-table stream, overlapped with growth
+  hipEvent_t ev_tab[2] = {nullptr, nullptr};   // table chunk ready (per buffer)
+  hipEvent_t ev_grow[2] = {nullptr, nullptr};  // growth chunk done with a buffer
+  hipEvent_t ev_sync = nullptr;
   double* stage = nullptr;    // n^3 doubles of host<->device staging
   double2* fa = nullptr;      // transform scratch
   double2* fb = nullptr;
   double2* tw = nullptr;
+  int growth_variant = -1;  // columns-per-lane variant, -1 until timed
   bool timing = false;
-  // kind 0: one chunk (e0 -> e1 table, e1 -> e2 growth); kind 1: the apply
-  // launch (e0 -> e1)
+  // kind 0: one chunk (e0 -> e1 table on the aux stream, e2 -> e3 growth);
+  // kind 1: the apply launch (e0 -> e1)
   struct Rec {
-    hipEvent_t e[3];
+    hipEvent_t e[4];
     int kind;
   };
   std::vector<Rec> recs;
@@ -444,15 +481,28 @@ void lin_free(sl_linear* L) {
     for (hipEvent_t e : r.e)
       if (e) (void)hipEventDestroy(e);
   L->recs.clear();
+  for (int k = 0; k < 2; ++k) {
+    if (L->ev_tab[k]) (void)hipEventDestroy(L->ev_tab[k]);
+    if (L->ev_grow[k]) (void)hipEventDestroy(L->ev_grow[k]);
+  }
+  if (L->ev_sync) (void)hipEventDestroy(L->ev_sync);
+  if (L->aux) (void)hipStreamDestroy(L->aux);
   if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
 }
 
-sl_status new_rec(sl_linear* L, int kind, sl_linear::Rec** out) {
-  sl_linear::Rec r{{nullptr, nullptr, nullptr}, kind};
-  const int ne = kind == 0 ? 3 : 2;
-  for (int i = 0; i < ne; ++i) HIP_TRY(hipEventCreate(&r.e[i]));
+// Append a timing record; *index is its position in L->recs (indices stay
+// valid as the vector grows).
+sl_status new_rec(sl_linear* L, int kind, size_t* index) {
+  sl_linear::Rec r{{nullptr, nullptr, nullptr, nullptr}, kind};
+  const int ne = kind == 0 ? 4 : 2;
+  for (int i = 0; i < ne; ++i) {
+    if (hipEventCreate(&r.e[i]) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipEventDestroy(r.e[j]);
+      return fail(SL_E_DEVICE, "cannot create a timing event");
+    }
+  }
   L->recs.push_back(r);
-  *out = &L->recs.back();
+  *index = L->recs.size() - 1;
   return SL_OK;
 }
 
@@ -538,7 +588,13 @@ sl_status sl_linear_create(const sl_config* cfg, void* hip_stream, sl_linear** o
   ok = ok && hipMalloc(reinterpret_cast<void**>(&L->M), size_t(L->ncls) * R * R * sizeof(double)) == hipSuccess;
   ok = ok && hipMalloc(reinterpret_cast<void**>(&L->k2), size_t(L->ncls) * sizeof(double)) == hipSuccess;
   ok = ok && hipMalloc(reinterpret_cast<void**>(&L->tab),
-                       size_t(kLinChunk) * (2 + nf * nf) * sizeof(double)) == hipSuccess;
+                       2 * size_t(kLinChunk) * (2 + nf * nf) * sizeof(double)) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&L->aux, hipStreamNonBlocking) == hipSuccess;
+  for (int k = 0; k < 2 && ok; ++k) {
+    ok = ok && hipEventCreateWithFlags(&L->ev_tab[k], hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&L->ev_grow[k], hipEventDisableTiming) == hipSuccess;
+  }
+  ok = ok && hipEventCreateWithFlags(&L->ev_sync, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipMalloc(reinterpret_cast<void**>(&L->stage), L->n3 * sizeof(double)) == hipSuccess;
   ok = ok && hipMalloc(reinterpret_cast<void**>(&L->fa), L->n3 * sizeof(double2)) == hipSuccess;
   ok = ok && hipMalloc(reinterpret_cast<void**>(&L->fb), L->n3 * sizeof(double2)) == hipSuccess;
@@ -695,38 +751,95 @@ sl_status sl_linear_evolve(sl_linear* L, int64_t steps, double dt, int32_t order
   Weights W{};
   W.s = int(w.size());
   for (int j = 0; j < W.s; ++j) W.w[j] = w[j];
+  const int E = 2 + nf * nf;
   const int steps_per_chunk = kLinChunk / W.s;
-  const long long lanes = L->ncls * 2 * nf;
-  const unsigned ggrid = unsigned((lanes + kBlock - 1) / kBlock);
-  int64_t done = 0;
-  bool first = true;
-  while (done < steps) {
-    const int k = int(steps - done < steps_per_chunk ? steps - done : steps_per_chunk);
-    hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+  auto grid_for_variant = [&](int v) {
+    const long long lanes = L->ncls * (2 * nf / f.cols[v]);
+    return unsigned((lanes + kBlock - 1) / kBlock);
+  };
+  const int nchunks = int((steps + steps_per_chunk - 1) / steps_per_chunk);
+  // The background runs ahead on the aux stream, one chunk of stages into
+  // one of two coefficient buffers; growth chunk k waits for table k, and
+  // table k + 2 waits for growth k (it reuses that buffer).
+  HIP_TRY(hipEventRecord(L->ev_sync, L->stream));
+  HIP_TRY(hipStreamWaitEvent(L->aux, L->ev_sync, 0));
+  std::vector<size_t> recs(nchunks, 0);
+  auto enqueue_table = [&](int c) -> sl_status {
+    const int64_t s0 = int64_t(c) * steps_per_chunk;
+    const int k = int(steps - s0 < steps_per_chunk ? steps - s0 : steps_per_chunk);
+    if (c >= 2) HIP_TRY(hipStreamWaitEvent(L->aux, L->ev_grow[c & 1], 0));
     if (L->timing) {
-      sl_linear::Rec* r = nullptr;
-      st = new_rec(L, 0, &r);
-      if (st != SL_OK) return st;
-      for (int i = 0; i < 3; ++i) e[i] = r->e[i];
-      HIP_TRY(hipEventRecord(e[0], L->stream));
+      sl_status s2 = new_rec(L, 0, &recs[c]);
+      if (s2 != SL_OK) return s2;
+      HIP_TRY(hipEventRecord(L->recs[recs[c]].e[0], L->aux));
     }
-    hipLaunchKernelGGL(f.table, dim3(1), dim3(64), 0, L->stream, L->sc, L->K, L->prm, W, dt, k, L->tab);
+    hipLaunchKernelGGL(f.table, dim3(1), dim3(64), 0, L->aux, L->sc, L->K, L->prm, W, dt, k,
+                       L->tab + size_t(c & 1) * kLinChunk * E);
     HIP_TRY(hipGetLastError());
-    if (L->timing) HIP_TRY(hipEventRecord(e[1], L->stream));
-    hipLaunchKernelGGL(f.growth, dim3(ggrid), dim3(kBlock), 0, L->stream, L->M, L->k2, L->ncls, L->tab,
-                       k * W.s, first ? 1 : 0);
+    if (L->timing) HIP_TRY(hipEventRecord(L->recs[recs[c]].e[1], L->aux));
+    HIP_TRY(hipEventRecord(L->ev_tab[c & 1], L->aux));
+    return SL_OK;
+  };
+  st = enqueue_table(0);
+  if (st != SL_OK) return st;
+  for (int c = 0; c < nchunks; ++c) {
+    if (c + 1 < nchunks) {
+      st = enqueue_table(c + 1);
+      if (st != SL_OK) return st;
+    }
+    const int64_t s0 = int64_t(c) * steps_per_chunk;
+    const int k = int(steps - s0 < steps_per_chunk ? steps - s0 : steps_per_chunk);
+    HIP_TRY(hipStreamWaitEvent(L->stream, L->ev_tab[c & 1], 0));
+    const double* tb = L->tab + size_t(c & 1) * kLinChunk * E;
+    if (c == 0 && L->growth_variant < 0) {
+      // first call: time each variant on chunk 0, which starts from the
+      // identity, so repeating it leaves the same M (every variant applies
+      // the same operations to a column)
+      hipEvent_t t0, t1;
+      HIP_TRY(hipEventCreate(&t0));
+      HIP_TRY(hipEventCreate(&t1));
+      float best = 1e30f;
+      int win = 1;
+      hipError_t err = hipSuccess;
+      for (int v = 0; v < kGrowthVariants && err == hipSuccess; ++v) {
+        err = hipEventRecord(t0, L->stream);
+        if (err == hipSuccess) {
+          hipLaunchKernelGGL(f.growth[v], dim3(grid_for_variant(v)), dim3(kBlock), 0, L->stream,
+                             L->M, L->k2, L->ncls, tb, k * W.s, 1);
+          err = hipGetLastError();
+        }
+        if (err == hipSuccess) err = hipEventRecord(t1, L->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(t1);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, t0, t1);
+        if (err == hipSuccess && ms < best) {
+          best = ms;
+          win = v;
+        }
+      }
+      (void)hipEventDestroy(t0);
+      (void)hipEventDestroy(t1);
+      if (err != hipSuccess) return fail(SL_E_DEVICE, "growth variant timing: %s", hipGetErrorString(err));
+      L->growth_variant = win;
+    }
+    const int gv = L->growth_variant;
+    if (L->timing) HIP_TRY(hipEventRecord(L->recs[recs[c]].e[2], L->stream));
+    hipLaunchKernelGGL(f.growth[gv], dim3(grid_for_variant(gv)), dim3(kBlock), 0, L->stream, L->M,
+                       L->k2, L->ncls, tb, k * W.s, c == 0 ? 1 : 0);
     HIP_TRY(hipGetLastError());
-    if (L->timing) HIP_TRY(hipEventRecord(e[2], L->stream));
-    done += k;
-    first = false;
+    if (L->timing) HIP_TRY(hipEventRecord(L->recs[recs[c]].e[3], L->stream));
+    HIP_TRY(hipEventRecord(L->ev_grow[c & 1], L->stream));
   }
+  // later work on the handle's stream sees the final background
+  HIP_TRY(hipEventRecord(L->ev_sync, L->aux));
+  HIP_TRY(hipStreamWaitEvent(L->stream, L->ev_sync, 0));
   hipEvent_t a0 = nullptr, a1 = nullptr;
   if (L->timing) {
-    sl_linear::Rec* r = nullptr;
+    size_t r = 0;
     st = new_rec(L, 1, &r);
     if (st != SL_OK) return st;
-    a0 = r->e[0];
-    a1 = r->e[1];
+    a0 = L->recs[r].e[0];
+    a1 = L->recs[r].e[1];
     HIP_TRY(hipEventRecord(a0, L->stream));
   }
   hipLaunchKernelGGL(f.apply, dim3(unsigned(grid_of(L->n3))), dim3(kBlock), 0, L->stream, L->dphi,
@@ -812,7 +925,7 @@ sl_status sl_linear_kernel_timing(sl_linear* L, int64_t* growth_launches, double
     if (r.kind == 0) {
       HIP_TRY(hipEventElapsedTime(&ms, r.e[0], r.e[1]));
       t += ms;
-      HIP_TRY(hipEventElapsedTime(&ms, r.e[1], r.e[2]));
+      HIP_TRY(hipEventElapsedTime(&ms, r.e[2], r.e[3]));
       g += ms;
       ++ng;
     } else {
