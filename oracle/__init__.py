@@ -27,7 +27,7 @@ from .lattice import (  # noqa: F401
     TABLE1_ORDER6, TABLE1_ORDER8, composition_weights, lap, grad_energy,
     Potential, Lattice, spectrum, stability_limit, linear_stage_matrix,
     STENCIL_7, STENCIL_19, STENCIL_27, isotropic_stencil, stencil_symbol,
-    stencil_ok, stencil_max_keff2, keff2_modes,
+    stencil_ok, stencil_max_keff2, keff2_modes, mode_spectra,
 )
 from .linear import LinearLattice  # noqa: F401
 from . import rng  # noqa: F401

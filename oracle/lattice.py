@@ -262,6 +262,27 @@ class Potential:
         base = m2 * (1.0 + K + K * math.log(u / M2))
         return [base + m2 * K * phi0[0] ** 2 / u, base + m2 * K * phi0[1] ** 2 / u]
 
+    def d2V_sites(self, phi):
+        """Array [field][...] of d^2V/dphi_i^2 at every site of phi."""
+        k, p = self.kind, self.params
+        if k == "free":
+            return np.stack([p[i] + 0.0 * phi[i] for i in range(self.nfields)])
+        if k == "chaotic2":
+            m2, G = p
+            f, c = phi[0], phi[1]
+            return np.stack([m2 + G * c * c, G * f * f])
+        if k == "oscillon":
+            m2, lam, g = p
+            f = phi[0]
+            return np.stack([m2 - 3.0 * lam * f * f + 5.0 * g * f ** 4])
+        m2, K, M2 = p
+        u = 0.5 * (phi[0] ** 2 + phi[1] ** 2)
+        pos, lg = self._u_log(u, M2)
+        base = m2 * (1.0 + K + K * lg)
+        safe = np.where(pos, u, 1.0)
+        return np.stack([np.where(pos, base + m2 * K * phi[i] ** 2 / safe, 0.0 * u)
+                         for i in range(2)])
+
     def hessian(self, phi0):
         """Matrix d^2V/dphi_i dphi_j at a homogeneous point phi0: the
         quadratic form of V^(2), eq. (2.26), is delta^T H delta / 2."""
@@ -544,6 +565,46 @@ def spectrum(field, L, nbins):
         P = np.where(cnt > 0, ps / np.maximum(cnt, 1), 0.0)
         k = np.where(cnt > 0, 2.0 * np.pi * ks / np.maximum(cnt, 1) / L, 0.0)
     return k, P, cnt.astype(np.int64)
+
+
+def mode_spectra(lat, field, nbins):
+    """Field, energy-density and number-density spectra of one field
+    (the post-processing spectra of Sec. 2.4; the paper refers to the
+    LATTICEEASY definitions without printing them, the reading used here is
+    listed in the design doc).  With F_n = FFT(phi_i)/N^3 and P_n = FFT(pi_i)/N^3,
+    k_eff^2(n) of the lattice's stencil and m_eff^2 the lattice mean of
+    d^2V/dphi_i^2:
+
+      rho_n   = |P_n|^2/(2 a^6) + (k_eff^2/(2 a^2 dx^2) + m_eff^2/2) |F_n|^2
+      omega_n = sqrt(k_eff^2/(a^2 dx^2) + m_eff^2),  n_n = rho_n / omega_n
+
+    (n_n = 0 where omega_n^2 <= 0).  rho_n is mode n's share of the
+    quadratic energy density; summed over n != 0 it is the kinetic, gradient
+    and m_eff^2 energy of the fluctuations.  Binned as spectrum(): returns
+    k_b, and per bin the means of |F_n|^2, rho_n, n_n, the counts and
+    m_eff^2."""
+    n = lat.n
+    a, dx2 = lat.a, lat.dx ** 2
+    F = np.fft.fftn(lat.phi[field]) / n ** 3
+    P = np.fft.fftn(lat.pi[field]) / n ** 3
+    m2 = float(np.mean(lat.pot.d2V_sites(lat.phi)[field]))
+    k2 = keff2_modes(n, lat.c)
+    f2 = F.real ** 2 + F.imag ** 2
+    p2 = P.real ** 2 + P.imag ** 2
+    rho = p2 / (2.0 * a ** 6) + (k2 / (2.0 * a * a * dx2) + 0.5 * m2) * f2
+    w2 = k2 / (a * a * dx2) + m2
+    num = np.where(w2 > 0, rho / np.sqrt(np.where(w2 > 0, w2, 1.0)), 0.0)
+    b, kn, m = spectrum_bins(n)
+    b, kn, m = b.ravel(), kn.ravel(), m.ravel()
+    keep = (m > 0) & (b < nbins)
+    cnt = np.bincount(b[keep], minlength=nbins)[:nbins]
+
+    def binmean(v):
+        sm = np.bincount(b[keep], weights=v.ravel()[keep], minlength=nbins)[:nbins]
+        return np.where(cnt > 0, sm / np.maximum(cnt, 1), 0.0)
+
+    k = np.where(cnt > 0, 2.0 * np.pi * binmean(kn) / lat.L, 0.0)
+    return k, binmean(f2), binmean(rho), binmean(num), cnt.astype(np.int64), m2
 
 
 # ---------------------------------------------------------------------------

@@ -123,6 +123,25 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
     return sorted(results, key=lambda r: r["id"]), stats
 
 
+def delta_n(phi0, efolds):
+    """Separate-universe statistics of a scan over initial homogeneous values
+    (the Delta N use of Sec. 2.4): the e-fold count N of each run against
+    its initial field phi0 is fitted by least squares with
+    N = N0 + N1 d + N2 d^2 / 2, d = phi0 - mean(phi0).  Returns N0, N1, N2,
+    the spread sigma_N of N over the scan and the local non-Gaussianity
+    f_NL = (5/6) N2 / N1^2 of the Delta N expansion."""
+    phi0 = np.asarray(phi0, dtype=np.float64)
+    N = np.asarray(efolds, dtype=np.float64)
+    if phi0.shape != N.shape or phi0.size < 3:
+        raise ValueError("need matching phi0 and N arrays with at least 3 runs")
+    d = phi0 - phi0.mean()
+    A = np.stack([np.ones_like(d), d, 0.5 * d * d], axis=1)
+    (N0, N1, N2), *_ = np.linalg.lstsq(A, N, rcond=None)
+    return dict(N0=float(N0), N1=float(N1), N2=float(N2), sigma_N=float(np.std(N)),
+                f_NL=float(5.0 / 6.0 * N2 / (N1 * N1)) if N1 != 0 else float("nan"),
+                runs=int(N.size))
+
+
 def req_nf(requests, rid):
     for r in requests:
         if r.id == rid:

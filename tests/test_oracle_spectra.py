@@ -1,0 +1,108 @@
+"""Pins of the energy- and number-density spectra (Sec. 2.4 post-processing
+spectra; definitions as read in the design doc) and of the per-site second
+derivative of V: Parseval against the independently pinned observables,
+conservation of every mode's energy for a free field in a static
+background (a != 1), closed forms on plane waves, rho = omega n on a shell
+of equal frequencies, and the Delta-N fit on exact quadratic data."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+@pytest.mark.parametrize("pot", [oracle.Potential("chaotic2", (1.0, 3.0)),
+                                 oracle.Potential("oscillon", (1.0, 1.0, 0.2)),
+                                 oracle.Potential("qball", (1.0, -0.1, 1.0)),
+                                 oracle.Potential("free", (1.0, 2.0, 0.5))],
+                         ids=lambda p: p.kind)
+def test_d2V_sites_matches_hessian_diagonal(pot):
+    rng = np.random.default_rng(4)
+    phi = 0.3 + 0.2 * rng.standard_normal((pot.nfields, 5))
+    d = pot.d2V_sites(phi)
+    for j in range(5):
+        np.testing.assert_allclose(d[:, j], np.diag(pot.hessian(phi[:, j])), rtol=1e-14)
+
+
+@pytest.mark.parametrize("stencil", [oracle.STENCIL_7, oracle.STENCIL_27], ids=["7", "27"])
+def test_energy_spectrum_parseval(stencil):
+    """sum_b count_b rho_b = kinetic (fluctuation part) + gradient +
+    m_eff^2/2 var(phi), with the observables of eq. (2.16)."""
+    n, L = 10, 5.0
+    pot = oracle.Potential("chaotic2", (1.0, 3.0))
+    lat = oracle.Lattice(n, L, pot, mpl=0.9, a0=1.4, stencil=stencil)
+    phi, pi = synth.gaussian_state(n, 2, 31, phi_base=[0.8, 0.1], phi_amp=0.05,
+                                   pi_base=[0.02, 0.0], pi_amp=0.03)
+    lat.phi[...] = phi
+    lat.pi[...] = pi
+    lat.solve_constraint()
+    nb = int(math.ceil(math.sqrt(3) * n / 2)) + 2
+    e = lat.energies()
+    a = lat.a
+    for i in range(2):
+        k, pf, pe, pn, cnt, m2 = oracle.mode_spectra(lat, i, nb)
+        assert cnt.sum() == n ** 3 - 1
+        assert m2 == pytest.approx(float(np.mean(pot.d2V_sites(phi)[i])), rel=1e-14)
+        kin_fluct = e["kin"][i] - np.mean(pi[i]) ** 2 / (2 * a ** 6)
+        want = kin_fluct + e["grad"][i] + 0.5 * m2 * e["var"][i]
+        assert float(np.sum(cnt * pe)) == pytest.approx(want, rel=1e-12)
+        assert float(np.sum(cnt * pf)) == pytest.approx(e["var"][i], rel=1e-12)
+
+
+def test_mode_energy_conserved_free_static():
+    """A free field with a = 1.3 fixed: each mode's a^4 rho_n is the
+    conserved energy of its oscillator, so every bin of the energy and
+    number spectra is constant up to the integrator's O((omega dt)^6)."""
+    n, L = 8, 4.0
+    pot = oracle.Potential("free", (0.6,))
+    lat = oracle.Lattice(n, L, pot, a0=1.3, expand=False)
+    phi, pi = synth.gaussian_state(n, 1, 32, phi_amp=0.2, pi_amp=0.2)
+    lat.phi[...] = phi
+    lat.pi[...] = pi
+    nb = 8
+    _, _, pe0, pn0, cnt, _ = oracle.mode_spectra(lat, 0, nb)
+    lat.evolve(200, 0.01, 6)
+    _, _, pe1, pn1, _, _ = oracle.mode_spectra(lat, 0, nb)
+    sel = cnt > 0
+    assert np.max(np.abs(pe1[sel] / pe0[sel] - 1)) < 1e-8
+    assert np.max(np.abs(pn1[sel] / pn0[sel] - 1)) < 1e-8
+
+
+def test_plane_wave_closed_forms():
+    """phi = A cos(2 pi x/L) + phi0 (free field, pi = 0): only the |n| = 1
+    bin is filled (|n|^2 = 1 and 2 round to 1: 6 + 12 modes); it holds the
+    two modes of the wave, each
+    with |F|^2 = A^2/4 and rho = (k_eff^2/(2 a^2 dx^2) + m^2/2) A^2/4, and
+    there n = rho/omega exactly."""
+    n, L, A, m2, a = 12, 6.0, 0.3, 0.8, 1.2
+    lat = oracle.Lattice(n, L, oracle.Potential("free", (m2,)), a0=a, expand=False)
+    x = np.arange(n)
+    lat.phi[0] = 0.5 + A * np.cos(2 * np.pi * x / n)[None, None, :]
+    k, pf, pe, pn, cnt, m2e = oracle.mode_spectra(lat, 0, 4)
+    assert cnt[1] == 18 and m2e == pytest.approx(m2)
+    dx = L / n
+    keff2 = 4 * math.sin(math.pi / n) ** 2
+    assert cnt[1] * pf[1] == pytest.approx(2 * A * A / 4, rel=1e-13)
+    rho = (keff2 / (2 * a * a * dx * dx) + m2 / 2) * A * A / 4
+    assert cnt[1] * pe[1] == pytest.approx(2 * rho, rel=1e-13)
+    omega = math.sqrt(keff2 / (a * a * dx * dx) + m2)
+    assert pn[1] == pytest.approx(pe[1] / omega, rel=1e-13)
+    assert k[1] == pytest.approx(2 * math.pi / L * (6 + 12 * math.sqrt(2)) / 18, rel=1e-13)
+    assert np.all(pe[2:] < 1e-30) and np.all(pf[2:] < 1e-30)
+
+
+def test_delta_n_statistics_exact_on_quadratic():
+    from paper_1201_5029_amd import serve
+    phi0 = 1.0 + (np.arange(40) - 20) * 1e-5
+    d = phi0 - phi0.mean()
+    N0, N1, N2 = 3.2, -41.0, 5.0e4
+    N = N0 + N1 * d + 0.5 * N2 * d * d
+    st = serve.delta_n(phi0, N)
+    assert st["N0"] == pytest.approx(N0, rel=1e-12)
+    assert st["N1"] == pytest.approx(N1, rel=1e-8)
+    assert st["N2"] == pytest.approx(N2, rel=1e-6)
+    assert st["f_NL"] == pytest.approx(5.0 / 6.0 * N2 / N1 ** 2, rel=1e-6)
+    assert st["sigma_N"] == pytest.approx(float(np.std(N)), rel=1e-12)
+    assert st["runs"] == 40
