@@ -146,6 +146,8 @@ def measure_served(sl, nruns, steps):
                     "p99_s": pois["p99_s"], "peak_resident": pois["peak_resident"]},
         "fp64_single_runs": {"wall_s": t64, "value": sups / t64},
         "efolds_rel_err_fp32_vs_fp64_max": float(max(errs)),
+        "delta_n": serve.delta_n([r["phi0"][0] for r in recipes],
+                                 [res["efolds"] for res in burst_res]),
         "unit": "field-site-updates/s",
     }
 

@@ -191,6 +191,22 @@ sl_status sl_energies(sl_lattice* lat, sl_energies_t* out);
 sl_status sl_spectrum(sl_lattice* lat, int32_t field, int32_t nbins,
                       double* k_out, double* p_out, int64_t* count_out);
 
+/* Field, energy-density and number-density spectra of phi_field (the
+ * post-processing spectra of Sec. 2.4), from F_n = DFT(phi)/n^3 and
+ * P_n = DFT(pi)/n^3 of the synchronised state, k_eff^2 of the lattice's
+ * stencil and m_eff^2 = the lattice mean of d^2V/dphi_field^2:
+ *   rho_n = |P_n|^2/(2 a^6) + (k_eff^2/(2 a^2 dx^2) + m_eff^2/2) |F_n|^2,
+ *   n_n = rho_n / omega_n, omega_n^2 = k_eff^2/(a^2 dx^2) + m_eff^2
+ *   (n_n = 0 where omega_n^2 <= 0).
+ * Binned as sl_spectrum; per bin the means of |F_n|^2 (pf_out), rho_n
+ * (pe_out) and n_n (pn_out), k_out and count_out as sl_spectrum; *m2eff_out
+ * (may be NULL) receives m_eff^2.  The sum of count * pe over all bins is
+ * the fluctuations' kinetic, gradient and m_eff^2 energy density.  Host
+ * arrays of nbins entries; 1 <= nbins <= 2048.  Synchronises. */
+sl_status sl_spectra(sl_lattice* lat, int32_t field, int32_t nbins, double* k_out,
+                     double* pf_out, double* pe_out, double* pn_out, int64_t* count_out,
+                     double* m2eff_out);
+
 /* Copy the synchronised fields to host FP64 arrays of nfields*n^3 each
  * (either pointer may be NULL).  Synchronises. */
 sl_status sl_get_fields(sl_lattice* lat, double* phi_out, double* pi_out);

@@ -209,4 +209,18 @@ int spectrum_blocks(int n);
 hipError_t launch_spectrum_bins(int n, double L, const double2* cbuf, int nbins, double* part,
                                 double* out3, hipStream_t s);
 
+// ---- energy / number spectra (spectra.hip) ---------------------------------
+// m_eff^2 = lattice mean of d^2V/dphi_i^2 at the synchronised fields, per
+// field, into m2_dev (part: meff_partial_doubles(nf) doubles of scratch).
+size_t meff_partial_doubles(int nf);
+hipError_t launch_meff(const LatView& v, double* part, double* m2_dev, hipStream_t s);
+// The stored momenta of one field as the real part of cbuf.
+hipError_t launch_momentum_to_complex(const LatView& v, int field, double2* cbuf, hipStream_t s);
+// Binned field, energy and number spectra from the transforms F (field) and
+// P (momentum) of one field; out5 = [k | <|F|^2> | <rho> | <n> | count].
+int mode_spectra_blocks(int n);
+hipError_t launch_mode_spectra(const LatView& v, int field, const double2* F, const double2* P,
+                               int nbins, double* part, const double* m2_dev, double* out5,
+                               hipStream_t s);
+
 }  // namespace symlat

@@ -717,6 +717,76 @@ sl_status sl_spectrum(sl_lattice* L, int32_t field, int32_t nbins, double* k_out
   return read_scalars(L, &Sc);
 }
 
+sl_status sl_spectra(sl_lattice* L, int32_t field, int32_t nbins, double* k_out, double* pf_out,
+                     double* pe_out, double* pn_out, int64_t* count_out, double* m2eff_out) {
+  sl_status st = require_state(L);
+  if (st != SL_OK) return st;
+  if (field < 0 || field >= L->cfg.nfields) return fail(SL_E_INVALID, "field index out of range");
+  if (nbins < 1 || nbins > kMaxBins) return fail(SL_E_INVALID, "nbins must be in [1, %d]", kMaxBins);
+  if (!k_out || !pf_out || !pe_out || !pn_out || !count_out)
+    return fail(SL_E_INVALID, "output array is NULL");
+  FftScratch S;
+  st = fft_alloc(L, S);
+  if (st != SL_OK) return st;
+  const int nb = mode_spectra_blocks(L->cfg.n);
+  const size_t mparts = meff_partial_doubles(L->cfg.nfields);
+  double* part = nullptr;
+  double* mpart = nullptr;
+  double* m2 = nullptr;
+  double* out5 = nullptr;
+  double2* F = nullptr;
+  auto release = [&]() {
+    for (void* p : {static_cast<void*>(part), static_cast<void*>(mpart), static_cast<void*>(m2),
+                    static_cast<void*>(out5), static_cast<void*>(F)})
+      if (p) (void)hipFree(p);
+  };
+  if (hipMalloc(&part, size_t(nb) * 5 * nbins * sizeof(double)) != hipSuccess ||
+      hipMalloc(&mpart, mparts * sizeof(double)) != hipSuccess ||
+      hipMalloc(&m2, kMaxFields * sizeof(double)) != hipSuccess ||
+      hipMalloc(&out5, size_t(5) * nbins * sizeof(double)) != hipSuccess ||
+      hipMalloc(&F, L->n3 * sizeof(double2)) != hipSuccess) {
+    release();
+    return fail(SL_E_NOMEM, "cannot allocate spectrum scratch");
+  }
+  std::vector<double> host(size_t(5) * nbins);
+  double m2h[kMaxFields] = {0};
+  hipError_t e = launch_meff(L->v, mpart, m2, L->stream);
+  if (e == hipSuccess) e = launch_field_to_complex(L->v, field, S.a, L->stream);
+  if (e == hipSuccess) {
+    st = dft3(L, S, -1);
+    if (st != SL_OK) {
+      release();
+      return st;
+    }
+    e = hipMemcpyAsync(F, S.b, L->n3 * sizeof(double2), hipMemcpyDeviceToDevice, L->stream);
+  }
+  if (e == hipSuccess) e = launch_momentum_to_complex(L->v, field, S.a, L->stream);
+  if (e == hipSuccess) {
+    st = dft3(L, S, -1);
+    if (st != SL_OK) {
+      release();
+      return st;
+    }
+    e = launch_mode_spectra(L->v, field, F, S.b, nbins, part, m2, out5, L->stream);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host.data(), out5, host.size() * sizeof(double), hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(m2h, m2, sizeof m2h, hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  release();
+  if (e != hipSuccess) return fail(SL_E_DEVICE, "spectra: %s", hipGetErrorString(e));
+  for (int b = 0; b < nbins; ++b) {
+    k_out[b] = host[b];
+    pf_out[b] = host[nbins + b];
+    pe_out[b] = host[2 * nbins + b];
+    pn_out[b] = host[3 * nbins + b];
+    count_out[b] = int64_t(host[4 * nbins + b]);
+  }
+  if (m2eff_out) *m2eff_out = m2h[field];
+  DevScalars Sc;
+  return read_scalars(L, &Sc);
+}
+
 sl_status sl_set_kernel_timing(sl_lattice* L, int32_t enable) {
   if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
   L->timing = enable != 0;

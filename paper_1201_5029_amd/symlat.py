@@ -35,7 +35,7 @@ EXPORTS = (
     "sl_linear_set_stencil", "sl_linear_set_fields", "sl_linear_evolve",
     "sl_linear_get_fields", "sl_linear_get_background", "sl_linear_classes",
     "sl_linear_synchronize", "sl_linear_set_kernel_timing", "sl_linear_kernel_timing",
-    "sl_batch_autotune",
+    "sl_batch_autotune", "sl_spectra",
 )
 
 #: Members of the cubic stencil family of eq. (2.7): (centre, face, edge,
@@ -128,6 +128,7 @@ def load():
         "sl_linear_set_kernel_timing": (I32, [P, I32]),
         "sl_linear_kernel_timing": (I32, [P, ctypes.POINTER(I64), dp, dp, dp]),
         "sl_batch_autotune": (I32, [P, I32, dp]),
+        "sl_spectra": (I32, [P, I32, I32, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int64), dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -293,6 +294,20 @@ class Lattice:
                                      p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      c.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
         return k, p, c
+
+    def spectra(self, field, nbins):
+        """(k_b, <|F|^2>_b, <rho>_b, <n>_b, counts, m_eff^2): field,
+        energy-density and number-density spectra of one field."""
+        dp = ctypes.POINTER(ctypes.c_double)
+        k, pf, pe, pn = (np.zeros(nbins) for _ in range(4))
+        c = np.zeros(nbins, dtype=np.int64)
+        m2 = ctypes.c_double()
+        _check(self._lib.sl_spectra(self._h, int(field), int(nbins), k.ctypes.data_as(dp),
+                                    pf.ctypes.data_as(dp), pe.ctypes.data_as(dp),
+                                    pn.ctypes.data_as(dp),
+                                    c.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    ctypes.byref(m2)))
+        return k, pf, pe, pn, c, m2.value
 
     # -- launch shape and timing ---------------------------------------------
     def tile(self):
