@@ -332,7 +332,7 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
 
 // The same stage pass with any member of the cubic stencil family of
 // eq. (2.7): D = c0 f + c1 (6 faces) + c2 (12 edges) + c3 (8 corners).  Per
-// plane p of the own column the lane forms, from the drifted plane in LDS
+// plane p of the own sites the lane forms, from the drifted plane in LDS
 // (halo ring including the four corner cells), the centre value f(p), the
 // in-plane face sum F(p) = f(x+-1) + f(y+-1) and the in-plane corner sum
 // C(p) = f(x+-1, y+-1).  Then, for the site at plane z,
@@ -340,11 +340,13 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
 //   corners = C(z-1) + C(z+1),
 // so a ring of three (f, F, C) triples in registers replaces a second LDS
 // plane.  The ring lags the loads by one plane: the chunk walks planes
-// z0 - 1 .. zend and writes plane p - 1 while plane p is in LDS.  One site
-// per lane; the memory instructions are uniform across lanes (idle lanes
-// load the tile's first column and store into the sink), and the loads of
-// plane p + 1 go out after the barrier, before the stores of plane p - 1.
-template <typename T, int NF, int KIND>
+// z0 - 1 .. zend and writes plane p - 1 while plane p is in LDS.  VX
+// consecutive sites per lane (one vector load/store); the memory
+// instructions are uniform across lanes (idle lanes load the tile's first
+// column and store into the sink; x-halo and corner cells are fetched as the
+// aligned VX-wide group that contains them), and the loads of plane p + 1 go
+// out after the barrier, before the stores of plane p - 1.
+template <typename T, int NF, int KIND, int VX>
 __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T* lds,
                                             KSum* red_scratch) {
   const int par = P.sc->parity;
@@ -370,7 +372,7 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T*
   b /= P.ntx;
   const int yt = b % P.nty;
   const int zt = b / P.nty;
-  const int TW = P.tx;
+  const int TW = P.tx * VX;
   const int x0 = xt * TW, y0 = yt * P.ty, z0 = zt * P.tz;
   const int wx = min(TW, n - x0), wy = min(P.ty, n - y0), zc = min(P.tz, n - z0);
   const int zend = z0 + zc;
@@ -378,135 +380,161 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T*
   const int tid = threadIdx.x;
   const int tx = tid & (P.tx - 1);
   const int ty = tid >> P.logtx;
-  const bool active = (tx < wx) && (ty < wy);
+  const bool active = (tx * VX < wx) && (ty < wy);
   const int LX = TW + 2;
   const int plane = LX * (P.ty + 2);
-  const int own = (ty + 1) * LX + 1 + tx;
-  const size_t col = active ? size_t(y0 + ty) * n + (x0 + tx) : size_t(y0) * n + x0;
+  const int own = (ty + 1) * LX + 1 + tx * VX;
+  const size_t col = active ? size_t(y0 + ty) * n + (x0 + tx * VX) : size_t(y0) * n + x0;
 
-  // halo cell of this lane (one site): rows above/below, columns left/right,
-  // then the four corners; lanes without one re-load their own column
-  bool hjob = false;
-  int hl = 0;
+  // halo job: 1 = VX-wide row segment above/below, 2 = the cell at element
+  // VX - 1 of the aligned group left of the tile, 3 = element 0 of the
+  // group right of it (columns and corners); 0 = none (own column re-read)
+  int hjob = 0, hl = 0;
   size_t hcol = col;
   {
     const int TX = P.tx, TY = P.ty;
     int hx = -1, hy = 0;
-    const int xl = (x0 - 1 + n) % n, xr = (x0 + wx) % n;
-    const int yb = (y0 - 1 + n) % n, yt2 = (y0 + wy) % n;
+    const int gl = (x0 - VX + n) % n, gr = (x0 + wx) % n;  // aligned groups
+    const int yb = (y0 - 1 + n) % n, ya = (y0 + wy) % n;
     if (tid < TX) {
-      if (tid < wx) { hx = x0 + tid; hy = yb; hl = 1 + tid; }
+      if (tid * VX < wx) { hjob = 1; hx = x0 + tid * VX; hy = yb; hl = 1 + tid * VX; }
     } else if (tid < 2 * TX) {
       const int t = tid - TX;
-      if (t < wx) { hx = x0 + t; hy = yt2; hl = (wy + 1) * LX + 1 + t; }
+      if (t * VX < wx) { hjob = 1; hx = x0 + t * VX; hy = ya; hl = (wy + 1) * LX + 1 + t * VX; }
     } else if (tid < 2 * TX + TY) {
       const int r = tid - 2 * TX;
-      if (r < wy) { hx = xl; hy = y0 + r; hl = (r + 1) * LX; }
+      if (r < wy) { hjob = 2; hx = gl; hy = y0 + r; hl = (r + 1) * LX; }
     } else if (tid < 2 * TX + 2 * TY) {
       const int r = tid - 2 * TX - TY;
-      if (r < wy) { hx = xr; hy = y0 + r; hl = (r + 1) * LX + wx + 1; }
+      if (r < wy) { hjob = 3; hx = gr; hy = y0 + r; hl = (r + 1) * LX + wx + 1; }
     } else if (tid < 2 * TX + 2 * TY + 4) {
       const int k = tid - 2 * TX - 2 * TY;
-      hx = (k & 1) ? xr : xl;
-      hy = (k & 2) ? yt2 : yb;
+      hjob = (k & 1) ? 3 : 2;
+      hx = (k & 1) ? gr : gl;
+      hy = (k & 2) ? ya : yb;
       hl = ((k & 2) ? (wy + 1) * LX : 0) + ((k & 1) ? wx + 1 : 0);
     }
-    if (hx >= 0) {
-      hjob = true;
-      hcol = size_t(hy) * n + hx;
-    }
+    if (hx >= 0) hcol = size_t(hy) * n + hx;
   }
   auto wrapz = [n](int z) { return z < 0 ? z + n : (z >= n ? z - n : z); };
 
   KSum acc_dd{0.0, 0.0}, acc_v{0.0, 0.0}, acc_p{0.0, 0.0};
   // ring: (f, F, C) of planes p-2 (A) and p-1 (B); momenta of plane p-1
-  T fA[NF], FA[NF], CA[NF], fB[NF], FB[NF], CB[NF], qB[NF];
-  // raw loads in flight (plane p): own column and halo cell
-  T nph[NF], npi[NF], hph[NF], hpi[NF];
+  T fA[NF][VX], FA[NF][VX], CA[NF][VX], fB[NF][VX], FB[NF][VX], CB[NF][VX], qB[NF][VX];
+  // raw loads in flight (plane p): own sites and halo group
+  T nph[NF][VX], npi[NF][VX], hph[NF][VX], hpi[NF][VX];
 #pragma unroll
-  for (int i = 0; i < NF; ++i) fA[i] = FA[i] = CA[i] = fB[i] = FB[i] = CB[i] = qB[i] = T(0);
+  for (int i = 0; i < NF; ++i)
+#pragma unroll
+    for (int v = 0; v < VX; ++v)
+      fA[i][v] = FA[i][v] = CA[i][v] = fB[i][v] = FB[i][v] = CB[i][v] = qB[i][v] = T(0);
 
   auto load_plane = [&](int zz) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
       const size_t o = i * n3 + size_t(zz) * n2;
-      nph[i] = phi_in[o + col];
-      npi[i] = pi_in[o + col];
-      hph[i] = phi_in[o + hcol];
-      hpi[i] = pi_in[o + hcol];
+      const Vec<T, VX> u = ldv<T, VX>(phi_in + o + col), w = ldv<T, VX>(pi_in + o + col);
+      const Vec<T, VX> hu = ldv<T, VX>(phi_in + o + hcol), hw = ldv<T, VX>(pi_in + o + hcol);
+#pragma unroll
+      for (int v = 0; v < VX; ++v) {
+        nph[i][v] = u.v[v];
+        npi[i][v] = w.v[v];
+        hph[i][v] = hu.v[v];
+        hpi[i][v] = hw.v[v];
+      }
     }
   };
 
-  T* sink = static_cast<T*>(P.sink) + size_t(tid) * (2 * NF);
+  T* sink = static_cast<T*>(P.sink) + size_t(tid) * (2 * NF * VX);
   load_plane(wrapz(z0 - 1));
   // same trailing sequence as an iteration (loads, then 2 NF stores) so the
   // wait at the loop head covers the loads only
 #pragma unroll
   for (int i = 0; i < NF; ++i) {
-    sink[2 * i] = fB[i];
-    sink[2 * i + 1] = qB[i];
+    stv<T, VX>(sink + (2 * i) * VX, fB[i]);
+    stv<T, VX>(sink + (2 * i + 1) * VX, qB[i]);
   }
 
   int buf = 0;
   for (int p = z0 - 1; p <= zend; ++p) {
     T* L = lds + size_t(buf) * NF * plane;
-    T qN[NF];
+    T qN[NF][VX];
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      qN[i] = npi[i];
-      const T f = drift(nph[i], npi[i], c);
-      if (active) L[i * plane + own] = f;
-      if (hjob) L[i * plane + hl] = drift(hph[i], hpi[i], c);
+#pragma unroll
+      for (int v = 0; v < VX; ++v) {
+        qN[i][v] = npi[i][v];
+        const T f = drift(nph[i][v], npi[i][v], c);
+        if (active) L[i * plane + own + v] = f;
+      }
+      if (hjob == 1) {
+#pragma unroll
+        for (int v = 0; v < VX; ++v) L[i * plane + hl + v] = drift(hph[i][v], hpi[i][v], c);
+      } else if (hjob >= 2) {
+        const T f = hjob == 2 ? hph[i][VX - 1] : hph[i][0];
+        const T q = hjob == 2 ? hpi[i][VX - 1] : hpi[i][0];
+        L[i * plane + hl] = drift(f, q, c);
+      }
     }
     __syncthreads();
     load_plane(wrapz(min(p + 1, zend)));  // past the end: the last plane again
-    T fN[NF], FN[NF], CN[NF];
+    T fN[NF][VX], FN[NF][VX], CN[NF][VX];
 #pragma unroll
-    for (int i = 0; i < NF; ++i) {
-      const T* Li = L + i * plane + own;
-      fN[i] = Li[0];
-      FN[i] = (Li[-1] + Li[1]) + (Li[-LX] + Li[LX]);
-      CN[i] = (Li[-LX - 1] + Li[-LX + 1]) + (Li[LX - 1] + Li[LX + 1]);
-    }
-    // site at plane z = p - 1: ring (A, B, N) = planes (z - 1, z, z + 1)
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+      for (int v = 0; v < VX; ++v) {
+        const T* Li = L + i * plane + own + v;
+        fN[i][v] = Li[0];
+        FN[i][v] = (Li[-1] + Li[1]) + (Li[-LX] + Li[LX]);
+        CN[i][v] = (Li[-LX - 1] + Li[-LX + 1]) + (Li[LX - 1] + Li[LX + 1]);
+      }
+    // sites at plane z = p - 1: ring (A, B, N) = planes (z - 1, z, z + 1)
     const bool out = active && p >= z0 + 1;
     {
-      T D[NF], dV[NF], V, pn[NF];
+      double dd = 0.0, p2 = 0.0, vs = 0.0;
+      T pn[NF][VX];
 #pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        const T faces = FB[i] + (fA[i] + fN[i]);
-        const T edges = CB[i] + (FA[i] + FN[i]);
-        const T corners = CA[i] + CN[i];
-        D[i] = ((w0 * fB[i] + w1 * faces) + w2 * edges) + w3 * corners;
-      }
-      potential<KIND, NF, T>(fB, pot, V, dV);
-      double dd = 0.0, p2 = 0.0;
+      for (int v = 0; v < VX; ++v) {
+        T f[NF], D[NF], dV[NF], V;
 #pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        pn[i] = qB[i] + alpha * D[i] - beta * dV[i];
-        dd += double(fB[i]) * double(D[i]);
-        p2 += double(pn[i]) * double(pn[i]);
+        for (int i = 0; i < NF; ++i) {
+          const T faces = FB[i][v] + (fA[i][v] + fN[i][v]);
+          const T edges = CB[i][v] + (FA[i][v] + FN[i][v]);
+          const T corners = CA[i][v] + CN[i][v];
+          f[i] = fB[i][v];
+          D[i] = ((w0 * f[i] + w1 * faces) + w2 * edges) + w3 * corners;
+        }
+        potential<KIND, NF, T>(f, pot, V, dV);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+          pn[i][v] = qB[i][v] + alpha * D[i] - beta * dV[i];
+          dd += double(f[i]) * double(D[i]);
+          p2 += double(pn[i][v]) * double(pn[i][v]);
+        }
+        vs += double(V);
       }
       const size_t oc = size_t(wrapz(p - 1)) * n2 + col;
 #pragma unroll
       for (int i = 0; i < NF; ++i) {
-        T* po = out ? phi_out + i * n3 + oc : sink + 2 * i;
-        T* qo = out ? pi_out + i * n3 + oc : sink + 2 * i + 1;
-        *po = fB[i];
-        *qo = pn[i];
+        T* po = out ? phi_out + i * n3 + oc : sink + (2 * i) * VX;
+        T* qo = out ? pi_out + i * n3 + oc : sink + (2 * i + 1) * VX;
+        stv<T, VX>(po, fB[i]);
+        stv<T, VX>(qo, pn[i]);
       }
       if (out) {
         kadd(acc_dd, dd);
-        kadd(acc_v, double(V));
+        kadd(acc_v, vs);
         kadd(acc_p, p2);
       }
     }
 #pragma unroll
-    for (int i = 0; i < NF; ++i) {
-      fA[i] = fB[i]; FA[i] = FB[i]; CA[i] = CB[i];
-      fB[i] = fN[i]; FB[i] = FN[i]; CB[i] = CN[i];
-      qB[i] = qN[i];
-    }
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+      for (int v = 0; v < VX; ++v) {
+        fA[i][v] = fB[i][v]; FA[i][v] = FB[i][v]; CA[i][v] = CB[i][v];
+        fB[i][v] = fN[i][v]; FB[i][v] = FN[i][v]; CB[i][v] = CN[i][v];
+        qB[i][v] = qN[i][v];
+      }
     buf ^= 1;
   }
 
@@ -525,7 +553,7 @@ __device__ __forceinline__ void pass_any(const PassParams& P, int tile_id, T* ld
   if constexpr (ST == 0)
     pass_tile<T, NF, KIND, VX, PF>(P, tile_id, lds, red);
   else
-    pass_tile27<T, NF, KIND>(P, tile_id, lds, red);
+    pass_tile27<T, NF, KIND, VX>(P, tile_id, lds, red);
 }
 
 template <typename T, int NF, int KIND, int VX, int PF, int ST>
@@ -712,7 +740,15 @@ PassKernel pick_t(const Tile& t, int st) {
   PassKernel k;
   k.lds = size_t(2) * NF * (t.tx * t.vx + 2) * (t.ty + 2) * sizeof(T);
   if (st != 0) {
-    // any cubic-family stencil: one site per lane, lagged ring (see pass_tile27)
+    // any cubic-family stencil: lagged (f, F, C) ring (see pass_tile27); two
+    // sites per lane for up to two fields
+    if constexpr (NF <= 2) {
+      if (t.vx == 2) {
+        k.fn = pass_kernel<T, NF, KIND, 2, 1, 1>;
+        k.bfn = batched_pass_kernel<T, NF, KIND, 2, 1, 1>;
+        return k;
+      }
+    }
     k.fn = pass_kernel<T, NF, KIND, 1, 1, 1>;
     k.bfn = batched_pass_kernel<T, NF, KIND, 1, 1, 1>;
     return k;
@@ -769,8 +805,8 @@ PassKernel pick(int prec, int pot, int nf, const Tile& t, int st) {
 
 hipError_t launch_pass(const LatView& v, hipStream_t s) {
   if (v.nf < 1 || v.nf > kMaxFields) return hipErrorInvalidValue;
-  if ((v.nf > 2 || v.st.kind != 0) && (v.tile.vx != 1 || v.tile.pf != 1))
-    return hipErrorInvalidValue;
+  if (v.nf > 2 && (v.tile.vx != 1 || v.tile.pf != 1)) return hipErrorInvalidValue;
+  if (v.st.kind != 0 && (v.tile.vx > 2 || v.tile.pf != 1)) return hipErrorInvalidValue;
   // the 27-point pass needs lanes for 2 rows + 2 columns + 4 corners of halo
   if (v.st.kind != 0 && 2 * v.tile.tx + 2 * v.tile.ty + 4 > kBlock) return hipErrorInvalidValue;
   const PassKernel k = pick(v.prec, v.pot, v.nf, v.tile, v.st.kind);

@@ -823,18 +823,20 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
     return fail(SL_E_INVALID, "vx_only must be 0, 1, 2 or 4");
   if (pf_only != 0 && pf_only != 1 && pf_only != 2) return fail(SL_E_INVALID, "pf_only must be 0, 1 or 2");
   const int n = L->cfg.n;
-  // more than two fields, or the 27-point pass: one site per lane, pf = 1
-  const bool many = L->cfg.nfields > 2 || L->v.st.kind != 0;
+  // more than two fields: one site per lane, pf = 1; the 27-point pass:
+  // one or two sites per lane, pf = 1
+  const bool many = L->cfg.nfields > 2;
+  const bool st27 = L->v.st.kind != 0;
   struct Cand {
     int tx, vx, tz, pf;
   };
   std::vector<Cand> cands;
   for (int vx : {1, 2, 4}) {
-    if (n % vx != 0 || (many && vx != 1) || (vx_only && vx != vx_only)) continue;
+    if (n % vx != 0 || (many && vx != 1) || (st27 && vx > 2) || (vx_only && vx != vx_only)) continue;
     for (int tx : {16, 32, 64}) {
       if (tx * vx > 2 * n && tx != 16) continue;  // tile far wider than the lattice
       for (int pf : {1, 2}) {
-        if ((many && pf != 1) || (pf_only && pf != pf_only)) continue;
+        if (((many || st27) && pf != 1) || (pf_only && pf != pf_only)) continue;
         std::vector<int> tzs = {0};
         for (int d : {16, 8, 4, 2}) {
           const int tz = n / d;
@@ -932,8 +934,8 @@ sl_status sl_set_tile(sl_lattice* L, int32_t tx, int32_t vx, int32_t tz, int32_t
   if (pf != 1 && pf != 2) return fail(SL_E_INVALID, "pf must be 1 or 2");
   if (L->cfg.nfields > 2 && (vx != 1 || pf != 1))
     return fail(SL_E_INVALID, "more than two fields run with vx = 1 and pf = 1 only");
-  if (L->v.st.kind != 0 && (vx != 1 || pf != 1))
-    return fail(SL_E_INVALID, "the 27-point stencil runs with vx = 1 and pf = 1 only");
+  if (L->v.st.kind != 0 && (vx > 2 || pf != 1))
+    return fail(SL_E_INVALID, "the 27-point stencil runs with vx = 1 or 2 and pf = 1");
   if (L->batch && (vx != L->v.tile.vx || pf != L->v.tile.pf))
     return fail(SL_E_STATE, "a batch member keeps its vx and pf (remove it from the batch first)");
   if (tz < 0 || tz > L->cfg.n) return fail(SL_E_INVALID, "tz must be in [0, n]");
@@ -979,8 +981,10 @@ sl_status sl_set_stencil(sl_lattice* L, const double* c) {
   if (kind != old_kind) {
     int tx = L->v.tile.tx, vx = L->v.tile.vx, pf = L->v.tile.pf;
     if (kind != 0) {
-      vx = 1;
+      vx = (L->cfg.nfields <= 2 && L->cfg.n % 2 == 0 && L->cfg.n >= 32) ? 2 : 1;
       pf = 1;
+      const int width = L->cfg.n / vx;
+      tx = width >= 64 ? 64 : (width >= 32 ? 32 : 16);
     } else {
       default_shape(L->cfg.n, L->cfg.precision, L->cfg.nfields, &tx, &vx, &pf);
     }

@@ -52,7 +52,9 @@ def test_stencil_member_fp64_100_steps(name):
 
 
 @pytest.mark.parametrize("n,tile", [(20, (16, 1, 3, 1)), (33, (32, 1, 7, 1)),
-                                    (36, (64, 1, 5, 1)), (18, (16, 1, 18, 1))])
+                                    (36, (64, 1, 5, 1)), (18, (16, 1, 18, 1)),
+                                    (20, (16, 2, 3, 1)), (36, (32, 2, 5, 1)),
+                                    (34, (64, 2, 7, 1)), (32, (16, 2, 32, 1))])
 def test_stencil27_ragged_tiles(n, tile):
     c, phi, pi = _state(n, seed=304)
     o, g = _pair(c, phi, pi, oracle.STENCIL_27, tile=tile)
@@ -120,9 +122,11 @@ def test_stencil_validation_and_stability_bound():
     with pytest.raises(sl.SymlatError):
         g.set_stencil((math.nan, 1.0, 0.0, 0.0))
     g.set_stencil("27")
-    assert g.tile()[1] == 1 and g.tile()[4] == 1      # one site per lane, pf = 1
+    assert g.tile()[4] == 1                            # pf = 1
     with pytest.raises(sl.SymlatError):
-        g.set_tile(64, 2, 0, 1)                        # the 27-point pass has vx = 1
+        g.set_tile(64, 4, 0, 1)                        # the 27-point pass has vx <= 2
+    with pytest.raises(sl.SymlatError):
+        g.set_tile(64, 2, 0, 2)                        # and pf = 1
     g.init_fluctuations([1.0, 0.0], [0.0, 0.0], "none")
     # omega_max = sqrt(k_max^2/dx^2 + max m^2): the 27-point zone maximum is
     # at k = (pi, pi, pi), 64/15, below the 7-point 12
@@ -139,13 +143,13 @@ def test_stencil_validation_and_stability_bound():
 
 def test_stencil27_batched_equals_alone():
     recipes = [dict(synth.preheat(n=n, order=4, dt=0.005, precision="f32", seed=20120300 + j),
-                    stencil="27") for j, n in enumerate([16, 32, 24])]
+                    stencil="27") for j, n in enumerate([32, 64, 48])]
     alone = [sl.from_recipe(r) for r in recipes]
     mixed = [sl.from_recipe(r) for r in recipes]
     b = sl.Batch()
     for m in mixed:
         b.add(m)
-    plain = sl.from_recipe(synth.preheat(n=16, precision="f32"))
+    plain = sl.from_recipe(synth.preheat(n=32, precision="f32"))
     with pytest.raises(sl.SymlatError):
         b.add(plain)                       # 7-point member in a 27-point batch
     with pytest.raises(sl.SymlatError):
