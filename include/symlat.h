@@ -277,8 +277,10 @@ sl_status sl_autotune_forget(void);
 /* Batched form: many lattices advanced together, as in the ensemble of
  * runs with different initial values that the separate-universe
  * calculation needs (Sec. 2.4, Sec. 4).  Members share storage precision,
- * potential family, field count and the per-lane shape (vx, pf) of the
- * fused pass; sizes, parameters, tile widths and z-chunks may differ.  Each
+ * potential family, field count and stencil kind; sizes, parameters, tile
+ * widths and z-chunks may differ.  A joining lattice takes the batch's
+ * per-lane shape (vx, pf) of the fused pass (its tx and z-chunk are reset,
+ * or set from the batch tuner's record for its size).  Each
  * stage is one fused pass over the concatenated tiles of all members (each
  * XCD strides through a contiguous range of them) and one finalize with a
  * workgroup per member; an evolve call is captured as a HIP graph and
@@ -295,12 +297,14 @@ sl_status sl_batch_remove(sl_batch* batch, sl_lattice* lat);
 sl_status sl_batch_count(const sl_batch* batch, int32_t* count);
 /* Advance every member `steps` steps (same dt and order for all). */
 sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order);
-/* Batch autotuner: per member size (largest share of sites first, two
- * rounds of coordinate descent) try tx in {16, 32, 64} and z-chunks n/{1, 2,
- * 4, 8} for all members of that size, timing the batched pass alone (best
- * of `reps` HIP-event timings of two passes; the members' states are left
- * unchanged), and keep a shape only if it is at least 0.5 % faster.  vx
- * and pf stay the batch's.  The chosen shapes are applied to the members
+/* Batch autotuner: for every per-lane shape (vx in {1, 2, 4} dividing all
+ * member sizes, pf in {1, 2}, as the field count and stencil allow), and per
+ * member size (largest share of sites first, two rounds of coordinate
+ * descent) try tx in {16, 32, 64} and z-chunks n/{1, 2, 4, 8} for all
+ * members of that size, timing the batched pass alone (best of `reps`
+ * HIP-event timings of two passes; the members' states are left
+ * unchanged), and keep a shape only if it is at least 0.5 % faster.  The
+ * chosen shapes are applied to the members
  * (also for their own sl_evolve calls) and remembered for this process:
  * lattices of a tuned size that join a batch later are given that shape.
  * best_ms (may be NULL) receives the final pass time.  SL_E_STATE for an

@@ -1179,31 +1179,44 @@ sl_status sl_batch_add(sl_batch* B, sl_lattice* L) {
   sl_status st = require_state(L);
   if (st != SL_OK) return st;
   if (L->batch) return fail(SL_E_INVALID, "lattice already belongs to a batch");
+  if (!B->runs.empty() &&
+      (L->cfg.precision != B->prec || L->v.pot != B->pot || L->cfg.nfields != B->nf ||
+       L->v.st.kind != B->st_kind))
+    return fail(SL_E_INVALID,
+                "batch members share precision, potential family, field count and stencil kind");
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  // a size the batch tuner has seen starts with its tuned shape; a member
+  // takes the batch's per-lane shape (vx, pf)
+  int tx = L->v.tile.tx, vx = L->v.tile.vx, tz = L->tz_user, pf = L->v.tile.pf;
+  const BatchTuneKey key{{L->device, L->cfg.n, L->cfg.nfields, L->cfg.precision, L->v.pot, L->v.st.kind},
+                         0, 0};
+  for (const auto& kv : batch_tune_cache())
+    if (kv.first == key) {
+      tx = kv.second.tx;
+      vx = kv.second.vx;
+      tz = kv.second.tz;
+      pf = kv.second.pf;
+    }
+  if (!B->runs.empty() && (vx != B->shape.vx || pf != B->shape.pf)) {
+    vx = B->shape.vx;
+    pf = B->shape.pf;
+    if (L->cfg.n % vx != 0)
+      return fail(SL_E_INVALID, "n = %d is not a multiple of the batch's vx = %d", L->cfg.n, vx);
+    const int width = L->cfg.n / vx;
+    tx = width >= 64 ? 64 : (width >= 32 ? 32 : 16);
+    tz = 0;
+  }
+  if (tx != L->v.tile.tx || vx != L->v.tile.vx || pf != L->v.tile.pf || tz != L->tz_user) {
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    L->tz_user = tz;
+    retile(L, tx, vx, tz, pf);
+  }
   if (B->runs.empty()) {
     B->prec = L->cfg.precision;
     B->pot = L->v.pot;
     B->nf = L->cfg.nfields;
     B->shape = L->v.tile;
     B->st_kind = L->v.st.kind;
-  } else if (L->cfg.precision != B->prec || L->v.pot != B->pot || L->cfg.nfields != B->nf ||
-             L->v.tile.vx != B->shape.vx || L->v.tile.pf != B->shape.pf ||
-             L->v.st.kind != B->st_kind) {
-    return fail(SL_E_INVALID,
-                "batch members share precision, potential family, field count, stencil kind, vx "
-                "and pf");
-  }
-  HIP_TRY(hipStreamSynchronize(B->stream));
-  {
-    // a size the batch tuner has seen before starts with its tuned shape
-    const BatchTuneKey key{{L->device, L->cfg.n, L->cfg.nfields, L->cfg.precision, L->v.pot, L->v.st.kind},
-                           L->v.tile.vx, L->v.tile.pf};
-    for (const auto& kv : batch_tune_cache()) {
-      if (kv.first == key && (kv.second.tx != L->v.tile.tx || kv.second.tz != L->v.tile.tz)) {
-        HIP_TRY(hipStreamSynchronize(L->stream));
-        L->tz_user = kv.second.tz;
-        retile(L, kv.second.tx, L->v.tile.vx, kv.second.tz, L->v.tile.pf);
-      }
-    }
   }
   B->runs.push_back(L);
   L->batch = B;
@@ -1248,7 +1261,6 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
   std::sort(sizes.begin(), sizes.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
     return a.first > b.first;
   });
-  const int vx = B->shape.vx, pf = B->shape.pf;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -1275,73 +1287,119 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
     *ms_out = best;
     return SL_OK;
   };
-  auto apply = [&](int n, int tx, int tz) {
+  auto apply = [&](int n, int tx, int vx, int tz, int pf) {
     for (sl_lattice* L : B->runs)
       if (L->cfg.n == n) {
         L->tz_user = tz;
         retile(L, tx, vx, tz, pf);
       }
+    B->shape.vx = vx;
+    B->shape.pf = pf;
     B->dirty = true;
   };
+  auto cur_shape = [&](int n, int* tx, int* tz) {
+    for (sl_lattice* L : B->runs)
+      if (L->cfg.n == n) {
+        *tx = L->v.tile.tx;
+        *tz = L->v.tile.tz;
+      }
+  };
+  // per-lane shapes every member can take
+  std::vector<std::pair<int, int>> lane_shapes;
+  for (int vx : {1, 2, 4}) {
+    bool ok = !(B->nf > 2 && vx != 1) && !(B->st_kind != 0 && vx > 2);
+    for (const auto& sz : sizes) ok = ok && sz.second % vx == 0;
+    for (int pf : {1, 2})
+      if (ok && !((B->nf > 2 || B->st_kind != 0) && pf != 1)) lane_shapes.push_back({vx, pf});
+  }
   batch_drop_graph(B);
-  double cur = 0.0;
-  sl_status st = time_now(&cur);
-  for (int round = 0; round < 2 && st == SL_OK; ++round) {
+  struct Pick {
+    int tx, tz;
+  };
+  std::vector<Pick> best_pick(sizes.size());
+  int best_vx = B->shape.vx, best_pf = B->shape.pf;
+  double best_all = 1e300;
+  sl_status st = SL_OK;
+  for (const auto& ls : lane_shapes) {
+    const int vx = ls.first, pf = ls.second;
+    // start from the members' current shapes when the lane shape is the
+    // batch's, else from the width rule with a quarter-lattice z-chunk
     for (const auto& sz : sizes) {
       const int n = sz.second;
-      int ref_tx = 0, ref_tz = 0;
-      for (sl_lattice* L : B->runs)
-        if (L->cfg.n == n) {
-          ref_tx = L->v.tile.tx;
-          ref_tz = L->v.tile.tz;
-        }
-      int best_tx = ref_tx, best_tz = ref_tz;
-      for (int tx : {16, 32, 64}) {
-        if (tx * vx > 2 * n && tx != 16) continue;
-        if (B->st_kind != 0 && 2 * tx + 2 * (kBlock / tx) + 4 > kBlock) continue;
-        for (int d : {1, 2, 4, 8}) {
-          const int tz = n / d;
-          if (tz < 4 && d != 1) continue;
-          if (tx == ref_tx && tz == ref_tz) continue;
-          const Tile t = tile_geometry(n, tx, vx, tz, pf);
-          if (long(t.nblocks()) > kMaxPassBlocks) continue;
-          apply(n, tx, tz);
-          double ms = 0.0;
-          st = time_now(&ms);
-          if (st != SL_OK) break;
-          if (ms < cur * 0.995) {
-            cur = ms;
-            best_tx = tx;
-            best_tz = tz;
+      int tx = 0, tz = 0;
+      cur_shape(n, &tx, &tz);
+      if (vx != B->shape.vx || pf != B->shape.pf) {
+        const int width = n / vx;
+        tx = width >= 64 ? 64 : (width >= 32 ? 32 : 16);
+        tz = n / 4 >= 4 ? n / 4 : n;
+      }
+      apply(n, tx, vx, tz, pf);
+    }
+    double cur = 0.0;
+    st = time_now(&cur);
+    for (int round = 0; round < 2 && st == SL_OK; ++round) {
+      for (const auto& sz : sizes) {
+        const int n = sz.second;
+        int ref_tx = 0, ref_tz = 0;
+        cur_shape(n, &ref_tx, &ref_tz);
+        int btx = ref_tx, btz = ref_tz;
+        for (int tx : {16, 32, 64}) {
+          if (tx * vx > 2 * n && tx != 16) continue;
+          if (B->st_kind != 0 && 2 * tx + 2 * (kBlock / tx) + 4 > kBlock) continue;
+          for (int d : {1, 2, 4, 8}) {
+            const int tz = n / d;
+            if (tz < 4 && d != 1) continue;
+            if (tx == ref_tx && tz == ref_tz) continue;
+            const Tile t = tile_geometry(n, tx, vx, tz, pf);
+            if (long(t.nblocks()) > kMaxPassBlocks) continue;
+            apply(n, tx, vx, tz, pf);
+            double ms = 0.0;
+            st = time_now(&ms);
+            if (st != SL_OK) break;
+            if (ms < cur * 0.995) {
+              cur = ms;
+              btx = tx;
+              btz = tz;
+            }
           }
+          if (st != SL_OK) break;
         }
+        apply(n, btx, vx, btz, pf);
         if (st != SL_OK) break;
       }
-      apply(n, best_tx, best_tz);
-      if (st != SL_OK) break;
+    }
+    if (st != SL_OK) break;
+    if (cur < best_all * 0.995 || best_all == 1e300) {
+      best_all = cur;
+      best_vx = vx;
+      best_pf = pf;
+      for (size_t i = 0; i < sizes.size(); ++i) cur_shape(sizes[i].second, &best_pick[i].tx, &best_pick[i].tz);
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != SL_OK) return st;
+  for (size_t i = 0; i < sizes.size(); ++i)
+    apply(sizes[i].second, best_pick[i].tx, best_vx, best_pick[i].tz, best_pf);
   // remember the shapes for members added later (this batch or another)
-  for (const auto& sz : sizes) {
+  for (size_t i = 0; i < sizes.size(); ++i) {
     const sl_lattice* R = nullptr;
     for (sl_lattice* L : B->runs)
-      if (L->cfg.n == sz.second) R = L;
+      if (L->cfg.n == sizes[i].second) R = L;
     const BatchTuneKey key{{R->device, R->cfg.n, R->cfg.nfields, R->cfg.precision, R->v.pot, R->v.st.kind},
-                           vx, pf};
+                           0, 0};
+    const TuneVal val{best_pick[i].tx, best_vx, best_pick[i].tz, best_pf};
     bool found = false;
     for (auto& kv : batch_tune_cache())
       if (kv.first == key) {
-        kv.second = {R->v.tile.tx, vx, R->v.tile.tz, pf};
+        kv.second = val;
         found = true;
       }
-    if (!found) batch_tune_cache().push_back({key, {R->v.tile.tx, vx, R->v.tile.tz, pf}});
+    if (!found) batch_tune_cache().push_back({key, val});
   }
   B->dirty = true;
   ++B->version;
-  if (best_ms) *best_ms = cur;
+  if (best_ms) *best_ms = best_all;
   return SL_OK;
 }
 

@@ -29,6 +29,7 @@ def _same(a, b):
 
 @pytest.mark.parametrize("precision", ["f32", "f64"])
 def test_batched_equals_alone_over_graph_replays(precision):
+    sl.symlat.load().sl_autotune_forget()    # members keep their own shapes
     recipes = _runs(precision, [32, 64, 48, 32, 96])
     alone = [sl.from_recipe(r) for r in recipes]
     mixed = [sl.from_recipe(r) for r in recipes]
@@ -51,6 +52,7 @@ def test_batched_equals_alone_over_graph_replays(precision):
 
 
 def test_membership_changes_and_mixed_calls():
+    sl.symlat.load().sl_autotune_forget()
     recipes = _runs("f32", [32, 64, 96, 64])
     alone = [sl.from_recipe(r) for r in recipes]
     mixed = [sl.from_recipe(r) for r in recipes]
@@ -129,3 +131,8 @@ def test_batch_autotune_keeps_state_and_equals_alone():
     b2 = sl.Batch()
     b2.add(late)
     assert late.tile() == mixed[1].tile()
+    # a member whose own lane shape differs takes the batch's
+    odd = sl.from_recipe(_runs("f32", [40], base_seed=20120500)[0])
+    odd.set_tile(16, 1, 0, 1)
+    b2.add(odd)
+    assert odd.tile()[1] == late.tile()[1] and odd.tile()[4] == late.tile()[4]
