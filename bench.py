@@ -90,7 +90,9 @@ def measure(sl, recipe, steps, warmup, tile=None):
     else:
         shape, best = lat.autotune(reps=5)
         log("autotuned pass shape (tx, vx, tz, pf) =", shape, "best pass %.4f ms" % best)
-    lat.evolve(warmup, dt, order)
+    # at least 33 steps, so that the captured 32-step chunk of the evolve
+    # graph is built before the timed region
+    lat.evolve(max(warmup, 33), dt, order)
     lat.synchronize()
     t0 = time.perf_counter()
     lat.evolve(steps, dt, order)

@@ -173,6 +173,9 @@ sl_status sl_init_fluctuations(sl_lattice* lat, const double* phi0, const double
  * previous H2 flows, Laplacian, kick, FP64 block sums) and one device-side
  * scalar update; the trailing field drift of the last stage is kept
  * pending, so evolve(a) then evolve(b) equals evolve(a + b) bit for bit.
+ * Interior chunks of 32 steps replay a HIP graph captured on first use (the
+ * same launches as the eager path; recaptured when dt, order or the launch
+ * shape change); the final 1..32 steps and timed calls launch eagerly.
  * SL_E_INVALID for steps < 0, dt not finite, or an unknown order;
  * SL_E_UNSTABLE if omega_max |dt| exceeds the order's linear stability
  * limit (omega_max^2 = k_eff,max^2/dx^2 + a^2 max(m_eff^2, 0), with

@@ -141,6 +141,7 @@ bool config_ok(const sl_config* c, std::string* why) {
 namespace {
 
 constexpr long kMaxPassBlocks = 65536;  // bound of the per-block partial-sum buffer
+constexpr int64_t kEvolveChunk = 32;     // steps per captured evolve graph
 
 // Tile geometry for lanes tx (16/32/64), vx sites per lane, tz planes and
 // prefetch depth pf.
@@ -257,6 +258,13 @@ struct sl_lattice {
   sl_batch* batch = nullptr;  // batch this lattice belongs to, if any
   int tz_user = 0;  // 0: z-chunk chosen from the occupancy of the pass kernel
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  // captured interior chunk of evolve (kEvolveChunk steps, every finalize
+  // begins the next stage), replayed while (dt, order, launch view) match
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double g_dt = 0.0;
+  int g_order = 0;
+  LatView g_view{};
 };
 
 void batch_member_changed(sl_batch* B);
@@ -301,7 +309,15 @@ void refresh_m2max(sl_lattice* L) {
   }
 }
 
+void drop_graph(sl_lattice* L) {
+  if (L->gexec) (void)hipGraphExecDestroy(L->gexec);
+  if (L->graph) (void)hipGraphDestroy(L->graph);
+  L->gexec = nullptr;
+  L->graph = nullptr;
+}
+
 void free_all(sl_lattice* L) {
+  drop_graph(L);
   for (int k = 0; k < 2; ++k) {
     if (L->v.phi[k]) (void)hipFree(L->v.phi[k]);
     if (L->v.pi[k]) (void)hipFree(L->v.pi[k]);
@@ -611,27 +627,57 @@ sl_status sl_evolve(sl_lattice* L, int64_t steps, double dt, int32_t order) {
   if (st != SL_OK) return st;
   if (steps == 0) return SL_OK;
   const int s = int(w.size());
-  HIP_TRY(launch_begin(L->v, w[0], dt, L->stream));
-  for (int64_t step = 0; step < steps; ++step) {
-    for (int j = 0; j < s; ++j) {
-      const bool last_stage = j == s - 1;
-      const int has_next = !(last_stage && step == steps - 1);
-      const double wn = last_stage ? w[0] : w[j + 1];
-      if (L->timing) {
-        hipEvent_t e0, e1;
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
-        HIP_TRY(hipEventRecord(e0, L->stream));
-        HIP_TRY(launch_pass(L->v, L->stream));
-        HIP_TRY(hipEventRecord(e1, L->stream));
-        L->events.emplace_back(e0, e1);
-      } else {
-        HIP_TRY(launch_pass(L->v, L->stream));
+  // stage j of each step; has_next = 0 only for the last stage of the call
+  auto enqueue_steps = [&](int64_t nsteps, bool last_chunk) -> sl_status {
+    for (int64_t step = 0; step < nsteps; ++step) {
+      for (int j = 0; j < s; ++j) {
+        const bool last_stage = j == s - 1;
+        const int has_next = !(last_stage && last_chunk && step == nsteps - 1);
+        const double wn = last_stage ? w[0] : w[j + 1];
+        if (L->timing) {
+          hipEvent_t e0, e1;
+          HIP_TRY(hipEventCreate(&e0));
+          HIP_TRY(hipEventCreate(&e1));
+          HIP_TRY(hipEventRecord(e0, L->stream));
+          HIP_TRY(launch_pass(L->v, L->stream));
+          HIP_TRY(hipEventRecord(e1, L->stream));
+          L->events.emplace_back(e0, e1);
+        } else {
+          HIP_TRY(launch_pass(L->v, L->stream));
+        }
+        HIP_TRY(launch_stage_finalize(L->v, w[j], wn, dt, has_next, last_stage ? 1 : 0, L->stream));
       }
-      HIP_TRY(launch_stage_finalize(L->v, w[j], wn, dt, has_next, last_stage ? 1 : 0, L->stream));
     }
+    return SL_OK;
+  };
+  HIP_TRY(launch_begin(L->v, w[0], dt, L->stream));
+  // Interior chunks of kEvolveChunk steps replay one captured graph (the
+  // same kernels with the same arguments as the eager launches); the last
+  // 1 .. kEvolveChunk steps, whose final stage leaves its drift pending, and
+  // timed calls are launched eagerly.
+  const int64_t chunks = L->timing ? 0 : (steps - 1) / kEvolveChunk;
+  if (chunks > 0) {
+    if (!(L->gexec && L->g_dt == dt && L->g_order == order &&
+          std::memcmp(&L->g_view, &L->v, sizeof(LatView)) == 0)) {
+      drop_graph(L);
+      HIP_TRY(hipStreamBeginCapture(L->stream, hipStreamCaptureModeThreadLocal));
+      st = enqueue_steps(kEvolveChunk, false);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(L->stream, &g);
+      if (st != SL_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return fail(SL_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+      L->graph = g;
+      HIP_TRY(hipGraphInstantiate(&L->gexec, L->graph, nullptr, nullptr, 0));
+      L->g_dt = dt;
+      L->g_order = order;
+      std::memcpy(&L->g_view, &L->v, sizeof(LatView));
+    }
+    for (int64_t c = 0; c < chunks; ++c) HIP_TRY(hipGraphLaunch(L->gexec, L->stream));
   }
-  return SL_OK;
+  return enqueue_steps(steps - chunks * kEvolveChunk, true);
 }
 
 sl_status sl_synchronize(sl_lattice* L) {
