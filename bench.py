@@ -123,7 +123,15 @@ def measure_served(sl, nruns, steps):
     def reqs(arrivals):
         return [serve.Request(j, r, t) for j, (r, t) in enumerate(zip(recipes, arrivals))]
 
-    burst_res, burst = serve.serve(reqs([0.0] * nruns), dt, order, max_slots=nruns, tick_steps=25)
+    burst_res, burst = serve.serve(reqs([0.0] * nruns), dt, order, max_slots=nruns, tick_steps=25,
+                                   history=True)
+    # uniform-density Delta N: ln a where rho = 3 m_pl^2 H^2 first falls to
+    # the latest density every run reaches (the largest final density)
+    rho = [serve.friedmann_density(res["history"][1], res["history"][2], recipes[j]["n"],
+                                   recipes[j]["mpl"]) for j, res in enumerate(burst_res)]
+    rho_ref = max(r[-1] for r in rho)
+    n_ud = [serve.uniform_density_efolds(res["history"][1], rho[j], rho_ref)
+            for j, res in enumerate(burst_res)]
     capacity = nruns / burst["makespan_s"]
     arrivals = synth.poisson_arrivals(nruns, 0.8 * capacity)
     pois_res, pois = serve.serve(reqs(arrivals), dt, order, max_slots=nruns, tick_steps=25)
@@ -150,6 +158,9 @@ def measure_served(sl, nruns, steps):
         "efolds_rel_err_fp32_vs_fp64_max": float(max(errs)),
         "delta_n": serve.delta_n([r["phi0"][0] for r in recipes],
                                  [res["efolds"] for res in burst_res]),
+        "delta_n_uniform_density": serve.delta_n(
+            [r["phi0"][0] for r, nu in zip(recipes, n_ud) if nu == nu],
+            [nu for nu in n_ud if nu == nu]),
         "unit": "field-site-updates/s",
     }
 

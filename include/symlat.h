@@ -220,6 +220,18 @@ sl_status sl_get_fields(sl_lattice* lat, double* phi_out, double* pi_out);
 sl_status sl_set_fields(sl_lattice* lat, const double* phi, const double* pi,
                         double a, double p_a);
 
+/* Background history: with capacity > 0, every completed step (alone or in
+ * a batch) appends (eta, a, p_a) at its end to a device buffer of that many
+ * records (further steps are not recorded); capacity 0 releases it.  The
+ * record restarts at 0 entries here and whenever the state is reset
+ * (sl_init_fluctuations, sl_set_fields).  sl_get_history copies up to cap
+ * records to host arrays and reports the number recorded in *count.  Used
+ * for the uniform-density Delta N of a scan (Sec. 2.4): H = -p_a / (6 V_L
+ * m_pl^2 a^2) and rho = 3 m_pl^2 H^2 along the run.  Synchronises. */
+sl_status sl_set_history(sl_lattice* lat, int64_t capacity);
+sl_status sl_get_history(sl_lattice* lat, double* eta, double* a, double* p_a, int64_t cap,
+                         int64_t* count);
+
 /* Conformal time, scale factor and its momentum.  Synchronises. */
 sl_status sl_get_background(sl_lattice* lat, double* eta, double* a, double* p_a);
 
@@ -300,11 +312,12 @@ sl_status sl_batch_remove(sl_batch* batch, sl_lattice* lat);
 sl_status sl_batch_count(const sl_batch* batch, int32_t* count);
 /* Advance every member `steps` steps (same dt and order for all). */
 sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order);
-/* Batch autotuner: for every per-lane shape (vx in {1, 2, 4} dividing all
- * member sizes, pf in {1, 2}, as the field count and stencil allow), and per
- * member size (largest share of sites first, two rounds of coordinate
- * descent) try tx in {16, 32, 64} and z-chunks n/{1, 2, 4, 8} for all
- * members of that size, timing the batched pass alone (best of `reps`
+/* Batch autotuner: every per-lane shape (vx in {1, 2, 4} dividing all
+ * member sizes, pf in {1, 2}, as the field count and stencil allow) is timed
+ * at starting shapes; for the two fastest, per member size (largest share
+ * of sites first, two rounds of coordinate descent) tx in {16, 32, 64} and
+ * z-chunks n/{1, 2, 4, 8} are tried for all members of that size, timing
+ * the batched pass alone (best of `reps`
  * HIP-event timings of two passes; the members' states are left
  * unchanged), and keep a shape only if it is at least 0.5 % faster.  The
  * chosen shapes are applied to the members

@@ -62,6 +62,9 @@ struct DevScalars {
   double S3_last;  // last H3 lattice sum (diagnostic)
   int32_t parity;  // which ping-pong buffer holds the state
   int32_t status;  // sticky error bits
+  double* hist;      // optional record of (eta, a, p_a) at the end of each step
+  int64_t hist_cap;  // records the buffer holds
+  int64_t hist_n;    // records written since the last reset
 };
 
 // Per-lattice constants of the scalar updates.

@@ -328,7 +328,7 @@ __global__ void import_kernel(void* phi0, void* pi0, size_t count, const double*
 
 __global__ void reset_scalars_kernel(DevScalars* sc, double a, double p_a) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    DevScalars S;
+    DevScalars S = *sc;  // keeps the history buffer; a reset restarts it
     S.a = a;
     S.p_a = p_a;
     S.eta = 0.0;
@@ -341,6 +341,7 @@ __global__ void reset_scalars_kernel(DevScalars* sc, double a, double p_a) {
     S.S3_last = 0.0;
     S.parity = 0;
     S.status = 0;
+    S.hist_n = 0;
     *sc = S;
   }
 }

@@ -659,6 +659,13 @@ __device__ void finalize_body(DevScalars* sc, const double* partials, int nblock
     end_stage(S, K, w, h, SdD, SV, S2);
     S.parity ^= 1;
     if (end_of_step) S.eta = S.eta + h;
+    if (end_of_step && S.hist != nullptr && S.hist_n < S.hist_cap) {
+      double* r = S.hist + 3 * S.hist_n;
+      r[0] = S.eta;
+      r[1] = S.a;
+      r[2] = S.p_a;
+      S.hist_n = S.hist_n + 1;
+    }
     if (has_next) begin_stage(S, K, w_next, h);
     if (!(dev_finite(SdD) && dev_finite(SV) && dev_finite(S2) && dev_finite(S.a) &&
           dev_finite(S.p_a)))

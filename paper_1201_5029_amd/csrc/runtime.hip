@@ -254,6 +254,7 @@ struct sl_lattice {
   double* sums_dev = nullptr;
   sl_energies_t* energies_dev = nullptr;
   double* spec_dev = nullptr;
+  double* hist_dev = nullptr;  // per-step background record (sl_set_history)
   bool timing = false;
   sl_batch* batch = nullptr;  // batch this lattice belongs to, if any
   int tz_user = 0;  // 0: z-chunk chosen from the occupancy of the pass kernel
@@ -328,6 +329,7 @@ void free_all(sl_lattice* L) {
   if (L->sums_dev) (void)hipFree(L->sums_dev);
   if (L->energies_dev) (void)hipFree(L->energies_dev);
   if (L->spec_dev) (void)hipFree(L->spec_dev);
+  if (L->hist_dev) (void)hipFree(L->hist_dev);
   for (auto& e : L->events) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
@@ -459,6 +461,7 @@ sl_status sl_lattice_create(const sl_config* cfg, void* hip_stream, sl_lattice**
     (void)hipMemsetAsync(v.phi[k], 0, fbytes, L->stream);
     (void)hipMemsetAsync(v.pi[k], 0, fbytes, L->stream);
   }
+  (void)hipMemsetAsync(v.sc, 0, sizeof(DevScalars), L->stream);
   if (launch_reset_scalars(v, cfg->a0, 0.0, L->stream) != hipSuccess ||
       hipStreamSynchronize(L->stream) != hipSuccess) {
     free_all(L);
@@ -678,6 +681,55 @@ sl_status sl_evolve(sl_lattice* L, int64_t steps, double dt, int32_t order) {
     for (int64_t c = 0; c < chunks; ++c) HIP_TRY(hipGraphLaunch(L->gexec, L->stream));
   }
   return enqueue_steps(steps - chunks * kEvolveChunk, true);
+}
+
+sl_status sl_set_history(sl_lattice* L, int64_t capacity) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  if (capacity < 0 || capacity > (int64_t(1) << 31)) return fail(SL_E_INVALID, "capacity must be in [0, 2^31]");
+  // the lattice's stream and, if it is a batch member, the batch's stream
+  HIP_TRY(hipDeviceSynchronize());
+  DevScalars S;
+  HIP_TRY(hipMemcpy(&S, L->v.sc, sizeof S, hipMemcpyDeviceToHost));
+  if (L->hist_dev) {
+    (void)hipFree(L->hist_dev);
+    L->hist_dev = nullptr;
+  }
+  if (capacity > 0 &&
+      hipMalloc(reinterpret_cast<void**>(&L->hist_dev), size_t(capacity) * 3 * sizeof(double)) != hipSuccess) {
+    L->hist_dev = nullptr;
+    capacity = 0;
+    S.hist = nullptr;
+    S.hist_cap = 0;
+    S.hist_n = 0;
+    HIP_TRY(hipMemcpy(L->v.sc, &S, sizeof S, hipMemcpyHostToDevice));
+    return fail(SL_E_NOMEM, "cannot allocate the history buffer");
+  }
+  S.hist = L->hist_dev;
+  S.hist_cap = capacity;
+  S.hist_n = 0;
+  HIP_TRY(hipMemcpy(L->v.sc, &S, sizeof S, hipMemcpyHostToDevice));
+  return SL_OK;
+}
+
+sl_status sl_get_history(sl_lattice* L, double* eta, double* a, double* p_a, int64_t cap,
+                         int64_t* count) {
+  if (!L || !count) return fail(SL_E_INVALID, "lattice handle or count is NULL");
+  DevScalars S;
+  sl_status st = read_scalars(L, &S);
+  if (st != SL_OK) return st;
+  *count = S.hist_n;
+  const int64_t m = S.hist_n < cap ? S.hist_n : cap;
+  if (m > 0) {
+    if (!eta || !a || !p_a) return fail(SL_E_INVALID, "output array is NULL");
+    std::vector<double> h(size_t(m) * 3);
+    HIP_TRY(hipMemcpy(h.data(), L->hist_dev, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < m; ++i) {
+      eta[i] = h[3 * i];
+      a[i] = h[3 * i + 1];
+      p_a[i] = h[3 * i + 2];
+    }
+  }
+  return SL_OK;
 }
 
 sl_status sl_synchronize(sl_lattice* L) {
@@ -1366,10 +1418,9 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
   int best_vx = B->shape.vx, best_pf = B->shape.pf;
   double best_all = 1e300;
   sl_status st = SL_OK;
-  for (const auto& ls : lane_shapes) {
-    const int vx = ls.first, pf = ls.second;
-    // start from the members' current shapes when the lane shape is the
-    // batch's, else from the width rule with a quarter-lattice z-chunk
+  // set every size to a lane shape: the members' current shapes for the
+  // batch's own lane shape, else the width rule with a quarter-lattice chunk
+  auto start_shape = [&](int vx, int pf) {
     for (const auto& sz : sizes) {
       const int n = sz.second;
       int tx = 0, tz = 0;
@@ -1381,6 +1432,25 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
       }
       apply(n, tx, vx, tz, pf);
     }
+  };
+  // phase 1: every lane shape at its starting shapes; phase 2 refines the
+  // two best
+  const int orig_vx = B->shape.vx, orig_pf = B->shape.pf;
+  std::vector<std::pair<double, int>> ranked;
+  for (size_t q = 0; q < lane_shapes.size() && st == SL_OK; ++q) {
+    B->shape.vx = orig_vx;
+    B->shape.pf = orig_pf;
+    start_shape(lane_shapes[q].first, lane_shapes[q].second);
+    double ms = 0.0;
+    st = time_now(&ms);
+    ranked.push_back({ms, int(q)});
+  }
+  std::sort(ranked.begin(), ranked.end());
+  for (size_t r = 0; r < ranked.size() && r < 2 && st == SL_OK; ++r) {
+    const int vx = lane_shapes[ranked[r].second].first, pf = lane_shapes[ranked[r].second].second;
+    B->shape.vx = orig_vx;
+    B->shape.pf = orig_pf;
+    start_shape(vx, pf);
     double cur = 0.0;
     st = time_now(&cur);
     for (int round = 0; round < 2 && st == SL_OK; ++round) {
@@ -1415,7 +1485,7 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
       }
     }
     if (st != SL_OK) break;
-    if (cur < best_all * 0.995 || best_all == 1e300) {
+    if (cur < best_all) {
       best_all = cur;
       best_vx = vx;
       best_pf = pf;

@@ -24,6 +24,16 @@ import numpy as np
 from .symlat import Batch, device_memory, footprint_bytes, from_recipe
 
 
+# Run kinds the batch tuner has seen in this process; the library gives
+# later lattices of these kinds their tuned shapes when they join a batch.
+_TUNED = set()
+
+
+def _kind(recipe):
+    return (recipe["n"], recipe["nfields"], recipe.get("precision", "f64"), recipe["potential"],
+            str(recipe.get("stencil")))
+
+
 class Request:
     def __init__(self, rid, recipe, arrival, steps=None):
         self.id = rid
@@ -35,12 +45,17 @@ class Request:
 
 
 def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
-          keep_fields=False, tune=True, clock=time.perf_counter, sleep=time.sleep):
+          keep_fields=False, tune=True, history=False, clock=time.perf_counter,
+          sleep=time.sleep):
     """Run the request loop to completion.  Returns (results, stats).
 
+    history: record (eta, a, p_a) at the end of every step of each run on the
+    device and return it with the result (for the uniform-density Delta N).
+
     tune: before the first tick, let the batch autotuner pick the pass
-    shapes of the runs admitted first (a run is never retiled once it has
-    stepped; later runs of a tuned size start with the tuned shape).
+    shapes of the runs admitted first unless their kinds were tuned before
+    in this process (a run is never retiled once it has stepped; later runs
+    of a tuned size start with the tuned shape).
 
     results: one dict per request with id, n, arrival, admitted, completed,
     latency (s, completion - arrival), eta, a, p_a, efolds = ln a, the pass
@@ -77,6 +92,8 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
                     break
                 waiting.popleft()
                 lat = from_recipe(req.recipe)
+                if history:
+                    lat.set_history(req.steps)
                 batch.add(lat)
                 used += req.footprint
                 active[req.id] = [req, lat, 0, clock() - t0]
@@ -86,7 +103,10 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
                     sleep(max(0.0, pending[0].arrival - (clock() - t0)))
                 continue
             if not tuned:
-                batch.autotune(reps=3)
+                kinds = {_kind(a[0].recipe) for a in active.values()}
+                if not kinds <= _TUNED:
+                    batch.autotune(reps=3)
+                    _TUNED.update(kinds)
                 tuned = True
             k = min(tick_steps, min(a[0].steps - a[2] for a in active.values()))
             batch.step(k, dt, order)
@@ -104,6 +124,8 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
                                efolds=math.log(a), steps=req.steps, tile=lat.tile())
                     if keep_fields:
                         res["phi"], res["pi"] = lat.get_fields()
+                    if history:
+                        res["history"] = lat.history()
                     results.append(res)
                     batch.remove(lat)
                     lat.close()
@@ -140,6 +162,33 @@ def delta_n(phi0, efolds):
     return dict(N0=float(N0), N1=float(N1), N2=float(N2), sigma_N=float(np.std(N)),
                 f_NL=float(5.0 / 6.0 * N2 / (N1 * N1)) if N1 != 0 else float("nan"),
                 runs=int(N.size))
+
+
+def friedmann_density(a, p_a, n, mpl):
+    """rho = 3 m_pl^2 H^2 with H = -p_a / (6 V_L m_pl^2 a^2), V_L = n^3: the
+    total density the constraint H = 0 implies along a run (eq. (2.18))."""
+    a = np.asarray(a, dtype=np.float64)
+    hub = -np.asarray(p_a, dtype=np.float64) / (6.0 * float(n) ** 3 * mpl * mpl * a * a)
+    return 3.0 * mpl * mpl * hub * hub
+
+
+def uniform_density_efolds(a, rho, rho_ref):
+    """ln a where rho first falls to rho_ref, interpolating ln a linearly in
+    ln rho between the two recorded steps around the crossing (exact for a
+    power law rho ~ a^-p); NaN if rho stays above rho_ref, ln a[0] if it
+    starts below."""
+    a = np.asarray(a, dtype=np.float64)
+    rho = np.asarray(rho, dtype=np.float64)
+    below = np.nonzero(rho <= rho_ref)[0]
+    if below.size == 0:
+        return float("nan")
+    k = int(below[0])
+    if k == 0:
+        return float(math.log(a[0]))
+    x0, x1 = math.log(rho[k - 1]), math.log(rho[k])
+    y0, y1 = math.log(a[k - 1]), math.log(a[k])
+    t = (math.log(rho_ref) - x0) / (x1 - x0)
+    return float(y0 + t * (y1 - y0))
 
 
 def req_nf(requests, rid):

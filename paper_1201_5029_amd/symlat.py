@@ -35,7 +35,7 @@ EXPORTS = (
     "sl_linear_set_stencil", "sl_linear_set_fields", "sl_linear_evolve",
     "sl_linear_get_fields", "sl_linear_get_background", "sl_linear_classes",
     "sl_linear_synchronize", "sl_linear_set_kernel_timing", "sl_linear_kernel_timing",
-    "sl_batch_autotune", "sl_spectra",
+    "sl_batch_autotune", "sl_spectra", "sl_set_history", "sl_get_history",
 )
 
 #: Members of the cubic stencil family of eq. (2.7): (centre, face, edge,
@@ -129,6 +129,8 @@ def load():
         "sl_linear_kernel_timing": (I32, [P, ctypes.POINTER(I64), dp, dp, dp]),
         "sl_batch_autotune": (I32, [P, I32, dp]),
         "sl_spectra": (I32, [P, I32, I32, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int64), dp]),
+        "sl_set_history": (I32, [P, I64]),
+        "sl_get_history": (I32, [P, dp, dp, dp, I64, ctypes.POINTER(I64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -308,6 +310,21 @@ class Lattice:
                                     c.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                     ctypes.byref(m2)))
         return k, pf, pe, pn, c, m2.value
+
+    def set_history(self, capacity):
+        """Record (eta, a, p_a) at the end of each step, up to capacity."""
+        _check(self._lib.sl_set_history(self._h, int(capacity)))
+
+    def history(self, cap=None):
+        """(eta, a, p_a) arrays of the recorded steps."""
+        n = ctypes.c_int64()
+        _check(self._lib.sl_get_history(self._h, None, None, None, 0, ctypes.byref(n)))
+        m = n.value if cap is None else min(n.value, int(cap))
+        dp = ctypes.POINTER(ctypes.c_double)
+        eta, a, pa = np.zeros(m), np.zeros(m), np.zeros(m)
+        _check(self._lib.sl_get_history(self._h, eta.ctypes.data_as(dp), a.ctypes.data_as(dp),
+                                        pa.ctypes.data_as(dp), m, ctypes.byref(n)))
+        return eta, a, pa
 
     # -- launch shape and timing ---------------------------------------------
     def tile(self):

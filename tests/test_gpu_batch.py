@@ -136,3 +136,41 @@ def test_batch_autotune_keeps_state_and_equals_alone():
     odd.set_tile(16, 1, 0, 1)
     b2.add(odd)
     assert odd.tile()[1] == late.tile()[1] and odd.tile()[4] == late.tile()[4]
+
+
+def test_history_records_every_step_alone_and_batched():
+    """The device history holds (eta, a, p_a) at the end of each step: equal
+    bit for bit to the background read after single-step calls, through the
+    captured chunks of a long call, and for a batch member."""
+    sl.symlat.load().sl_autotune_forget()
+    r = _runs("f64", [32])[0]
+    ref = sl.from_recipe(r)
+    bg = []
+    for _ in range(40):
+        ref.evolve(1, 0.005, 4)
+        bg.append(ref.background())
+    one = sl.from_recipe(r)
+    one.set_history(100)
+    one.evolve(40, 0.005, 4)                      # one captured 32-step chunk + 8 eager
+    eta, a, pa = one.history()
+    assert len(a) == 40
+    assert [tuple(x) for x in zip(eta, a, pa)] == bg
+    one.set_history(5)
+    one.evolve(10, 0.005, 4)
+    assert len(one.history()[0]) == 5             # capacity bound
+    mem = sl.from_recipe(r)
+    mem.set_history(64)
+    b = sl.Batch()
+    b.add(mem)
+    alone = sl.from_recipe(r)
+    tx, vx, _, tz, pf = mem.tile()
+    alone.set_tile(tx, vx, tz, pf)
+    alone.set_history(64)
+    b.step(20, 0.005, 4)
+    alone.evolve(20, 0.005, 4)
+    b.synchronize()
+    hb, ha = mem.history(), alone.history()
+    assert all(np.array_equal(x, y) for x, y in zip(hb, ha)) and len(hb[0]) == 20
+    phi, pi = mem.get_fields()
+    mem.set_fields(phi, pi)                       # a reset restarts the record
+    assert len(mem.history()[0]) == 0

@@ -106,3 +106,22 @@ def test_delta_n_statistics_exact_on_quadratic():
     assert st["f_NL"] == pytest.approx(5.0 / 6.0 * N2 / N1 ** 2, rel=1e-6)
     assert st["sigma_N"] == pytest.approx(float(np.std(N)), rel=1e-12)
     assert st["runs"] == 40
+
+
+def test_uniform_density_efolds_exact_on_power_law():
+    """Radiation-like expansion a = 1 + c eta: H = c / a^2, rho = 3 m^2 H^2
+    ~ a^-4, so ln rho is linear in ln a and the interpolated crossing is
+    exact; p_a follows from H = -p_a / (6 V_L m^2 a^2)."""
+    from paper_1201_5029_amd import serve
+    n, mpl, c = 8, 0.7, 0.3
+    eta = np.arange(1, 200) * 0.05
+    a = 1.0 + c * eta
+    hub = c / a ** 2
+    p_a = -hub * 6.0 * n ** 3 * mpl ** 2 * a ** 2
+    rho = serve.friedmann_density(a, p_a, n, mpl)
+    np.testing.assert_allclose(rho, 3 * mpl ** 2 * hub ** 2, rtol=1e-14)
+    rho_ref = 3 * mpl ** 2 * c ** 2 / 2.345 ** 4      # rho at a = 2.345
+    N = serve.uniform_density_efolds(a, rho, rho_ref)
+    assert N == pytest.approx(math.log(2.345), rel=1e-12)
+    assert math.isnan(serve.uniform_density_efolds(a, rho, rho.min() / 2))
+    assert serve.uniform_density_efolds(a, rho, rho.max() * 2) == pytest.approx(math.log(a[0]))
