@@ -39,6 +39,8 @@ def parse():
     p.add_argument("--no-serve", action="store_true", help="skip the served ensemble")
     p.add_argument("--no-512", action="store_true", help="skip the 512^3 FP32 line")
     p.add_argument("--no-batched", action="store_true", help="skip the batched ensemble line")
+    p.add_argument("--no-configs", action="store_true",
+                   help="skip the 4th-order 256^3, 128^3 preheating and 128^3 oscillon lines")
     p.add_argument("--no-27", action="store_true", help="skip the 27-point stencil line")
     p.add_argument("--no-linear", action="store_true", help="skip the linearized-integrator line")
     p.add_argument("--serve-runs", type=int, default=96)
@@ -264,6 +266,29 @@ def measure_linear(sl, n=256, steps=400, order=6, warmup=20):
             "apply_GBs": n ** 3 * 2 * 2 * nf * 16 / (a_ms * 1e-3) / 1e9 if a_ms > 0 else None}
 
 
+# The paper's own runs of the 256^3 chaotic preheating model (4th order,
+# FP64; seconds per step on the hardware it names), as field-site-updates/s.
+PAPER_256_ORDER4 = {"Tesla C2050": 2 * 256 ** 3 / 0.132, "GTX 470": 2 * 256 ** 3 / 0.152}
+
+
+def measure_config(sl, recipe, steps, warmup=10):
+    """One more workload on the single-lattice path: field-site-updates/s
+    and the pass's HBM roofline (for lattices that fit the 256 MB MALL the
+    bandwidth is effective, not HBM-only)."""
+    wall, passes, pass_ms, e, tile = measure(sl, recipe, steps, warmup)
+    n3 = recipe["n"] ** 3
+    nf = recipe["nfields"]
+    b = 8 if recipe["precision"] == "f64" else 4
+    avg = pass_ms / passes / 1e3
+    state = 4 * b * nf * n3
+    return {"workload": recipe["workload"], "n": recipe["n"], "order": recipe["order"],
+            "dtype": recipe["precision"], "value": n3 * nf * steps / wall,
+            "ms_per_step": wall / steps * 1e3, "pass_ms": avg * 1e3,
+            "achieved_GBs": state / avg / 1e9, "frac": state / avg / 1e9 / HBM_PEAK_GBS,
+            "state_fits_mall": state <= 256e6, "tile": list(tile),
+            "friedmann_residual": e["friedmann_residual"]}
+
+
 def measure_qball512(sl, steps=20, warmup=3):
     """Q-ball configuration at 512^3 (FP32 fields, 6th order): the headline
     roofline point whose working set (4.3 GB) is far beyond the 256 MB MALL."""
@@ -377,6 +402,15 @@ def main():
     if not args.no_512 and args.precision == "f64" and args.n == 256:
         log("512^3 FP32 Q-ball ...")
         out["qball512_fp32"] = measure_qball512(sl)
+    if not args.no_configs and args.precision == "f64" and args.n == 256:
+        log("other configurations ...")
+        o4 = measure_config(sl, synth.preheat(n=256, order=4, dt=0.0025, precision="f64"), 100)
+        o4["paper_context"] = {k: {"value": v, "ratio": o4["value"] / v}
+                               for k, v in PAPER_256_ORDER4.items()}
+        out["preheat256_fp64_order4"] = o4
+        out["preheat128_fp64_order6"] = measure_config(
+            sl, synth.preheat(n=128, order=6, dt=0.0025, precision="f64"), 200)
+        out["oscillon128_fp32_order4"] = measure_config(sl, synth.oscillon(n=128), 200)
     if not args.no_batched and args.precision == "f64" and args.n == 256:
         log("batched ensemble ...")
         out["batched_c4"] = measure_batched(sl)
