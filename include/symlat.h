@@ -275,11 +275,13 @@ sl_status sl_get_tile(sl_lattice* lat, int32_t* tx, int32_t* vx, int32_t* ty, in
                       int32_t* pf);
 sl_status sl_set_tile(sl_lattice* lat, int32_t tx, int32_t vx, int32_t tz, int32_t pf);
 
-/* Autotuner: time the fused pass in candidate shapes (tx in {16, 32, 64},
- * vx in {1, 2, 4} dividing n, pf in {1, 2}, tz in {occupancy choice, n/16,
- * n/8, n/4, n/2}), best of `reps` HIP-event timings of two back-to-back
- * passes each, on the lattice's
- * current state, which the timing passes leave unchanged.  vx_only / pf_only
+/* Autotuner: time candidate shapes (tx in {16, 32, 64}, vx in {1, 2, 4}
+ * dividing n, pf in {1, 2}, tz in {occupancy choice, n/16, n/8, n/4, n/2})
+ * on the lattice's current state: best of `reps` HIP-event timings of two
+ * consecutive stages (fused pass + finalize, each reading what the previous
+ * wrote, as inside sl_evolve) with the drift and kick coefficients frozen at
+ * zero, so the fields keep their values; the scalars are restored after.
+ * best_ms is the time of one stage.  vx_only / pf_only
  * (0 = free) restrict the search, e.g. to the per-lane shape of a batch.
  * The winner is applied and remembered for this process: lattices created
  * later with the same (device, n, fields, precision, potential family) start

@@ -356,3 +356,29 @@ def test_autotune_keeps_state_and_parity():
     g2 = gpu_lattice(48, c["L"], c["potential"], c["params"], phi, pi, mpl=c["mpl"])
     assert g2.tile() == g.tile()
     sl.symlat.autotune_forget()
+
+
+def test_autotune_mid_run_keeps_state_bitwise():
+    """Tuning after some steps (a drift pending, history recording) leaves
+    the state, the pending drift and the record as they were: the tuned run
+    continues bit for bit like a twin given the same shape by hand."""
+    c, phi, pi = _preheat_state(32, seed=49)
+    g = gpu_lattice(32, c["L"], c["potential"], c["params"], phi, pi, mpl=c["mpl"])
+    h = gpu_lattice(32, c["L"], c["potential"], c["params"], phi, pi, mpl=c["mpl"])
+    for lat in (g, h):
+        lat.set_history(64)
+        lat.evolve(7, c["dt"], 4)
+    before = g.get_fields(), g.background()
+    g.autotune(reps=1)
+    tx, vx, _, tz, pf = g.tile()
+    h.set_tile(tx, vx, tz, pf)
+    after = g.get_fields(), g.background()
+    assert all(np.array_equal(x, y) for x, y in zip(before[0], after[0])) and before[1] == after[1]
+    for lat in (g, h):
+        lat.evolve(10, c["dt"], 4)
+    fg, pg = g.get_fields()
+    fh, ph = h.get_fields()
+    assert np.array_equal(fg, fh) and np.array_equal(pg, ph) and g.background() == h.background()
+    assert all(np.array_equal(x, y) for x, y in zip(g.history(), h.history()))
+    assert len(g.history()[0]) == 17
+    sl.symlat.autotune_forget()
