@@ -8,7 +8,7 @@ canonical momentum p_a, fields phi_i with momenta pi_i = a^2 phi_i',
 conformal time eta, reduced Planck mass m_pl.  Arrays are indexed
 [field][z][y][x].
 
-Readings of points the paper leaves open (each is listed in the design doc):
+Readings of points the paper leaves open:
 
 * the Laplacian coefficients c_d of eq. (2.7) are the 7-point member
   (c0 = -6, c1 = 1, c2 = c3 = 0); G of eq. (2.8) uses the same coefficients;
@@ -457,7 +457,8 @@ class Lattice:
                     friedmann_residual=resid, h_total=float(self.hamiltonian()),
                     kin=kin, grad=grad, pot=pot, mean=mean, var=var)
 
-    # --- initial state, Sec. 2.4 (method replaced) ------------
+    # --- initial state, Sec. 2.4 (Gaussian modes in place of the paper's
+    #     convolution method) ------------------------------------------------
     def init_homogeneous(self, phi0, pi0):
         for i in range(self.nf):
             self.phi[i][...] = phi0[i]
@@ -534,7 +535,7 @@ def white_field(n, amp, seed, field):
 
 
 # ---------------------------------------------------------------------------
-# Spectrum (Sec. 2.4 post-processing; binning reading in the design doc)
+# Spectrum (Sec. 2.4 post-processing; |n| rounded half away from zero)
 # ---------------------------------------------------------------------------
 
 def spectrum_bins(n):
@@ -570,8 +571,9 @@ def spectrum(field, L, nbins):
 def mode_spectra(lat, field, nbins):
     """Field, energy-density and number-density spectra of one field
     (the post-processing spectra of Sec. 2.4; the paper refers to the
-    LATTICEEASY definitions without printing them, the reading used here is
-    listed in the design doc).  With F_n = FFT(phi_i)/N^3 and P_n = FFT(pi_i)/N^3,
+    LATTICEEASY definitions without printing them; the forms below are
+    written in the paper's variables).  With F_n = FFT(phi_i)/N^3 and
+    P_n = FFT(pi_i)/N^3,
     k_eff^2(n) of the lattice's stencil and m_eff^2 the lattice mean of
     d^2V/dphi_i^2:
 

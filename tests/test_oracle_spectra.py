@@ -1,5 +1,5 @@
 """Pins of the energy- and number-density spectra (Sec. 2.4 post-processing
-spectra; definitions as read in the design doc) and of the per-site second
+spectra, in the forms of oracle.mode_spectra) and of the per-site second
 derivative of V: Parseval against the independently pinned observables,
 conservation of every mode's energy for a free field in a static
 background (a != 1), closed forms on plane waves, rho = omega n on a shell
