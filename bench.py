@@ -82,7 +82,11 @@ def measured_traffic(workload, precision, tile):
     return None
 
 
-def measure(sl, recipe, steps, warmup, tile=None):
+def measure(sl, recipe, steps, warmup, tile=None, fields=None):
+    """Autotune (or fix) the pass shape, time `steps` steps after a warm-up,
+    then time the fused passes with HIP events over a second region of the
+    same length.  With a dict `fields`, the final (phi, pi) are stored in it
+    as FP64 host arrays."""
     lat = sl.from_recipe(recipe)
     order, dt = recipe["order"], recipe["dt"]
     if tile:
@@ -107,6 +111,8 @@ def measure(sl, recipe, steps, warmup, tile=None):
     lat.set_kernel_timing(False)
     e = lat.energies()
     tile = lat.tile()
+    if fields is not None:
+        fields["phi"], fields["pi"] = lat.get_fields()
     lat.close()
     return wall, passes, pass_ms, e, tile
 
@@ -351,7 +357,9 @@ def main():
     recipe = synth.preheat(n=args.n, order=args.order, dt=0.0025, steps=args.steps,
                            precision=args.precision)
     log("workload", recipe["workload"], args.n, "order", args.order, args.precision)
-    wall, passes, pass_ms, e, tile = measure(sl, recipe, args.steps, args.warmup, args.tile)
+    f64_fields = {}
+    wall, passes, pass_ms, e, tile = measure(sl, recipe, args.steps, args.warmup, args.tile,
+                                             fields=f64_fields if args.precision == "f64" else None)
     nf = recipe["nfields"]
     n3 = args.n ** 3
     b = 8 if args.precision == "f64" else 4
@@ -394,8 +402,18 @@ def main():
     out["roofline"]["frac_of_copy"] = achieved / copy_gbs
     if not args.no_fp32 and args.precision == "f64":
         r32 = dict(recipe, precision="f32")
-        w32, p32, ms32, e32, tile32 = measure(sl, r32, args.steps, args.warmup)
-        out["fp32_storage"] = {
+        f32_fields = {}
+        w32, p32, ms32, e32, tile32 = measure(sl, r32, args.steps, args.warmup, fields=f32_fields)
+        import numpy as np
+
+        def rel_l2(a, b):
+            return max(float(np.linalg.norm(x - y) / np.linalg.norm(y)) for x, y in zip(a, b))
+        err = {"phi_rel_l2": rel_l2(f32_fields["phi"], f64_fields["phi"]),
+               "pi_rel_l2": rel_l2(f32_fields["pi"], f64_fields["pi"]),
+               "steps": 2 * args.steps + max(args.warmup, 33),
+               "against": "the FP64 run of the same workload on the GPU (pinned to the oracle)"}
+        del f32_fields, f64_fields
+        out["fp32_storage"] = {"error_vs_fp64": err,
             "value": n3 * nf * args.steps / w32, "ms_per_step": w32 / args.steps * 1e3,
             "pass_ms": ms32 / p32, "achieved_GBs": 4 * 4 * nf * n3 / (ms32 / p32 / 1e3) / 1e9,
             "friedmann_residual": e32["friedmann_residual"], "tile": list(tile32)}
