@@ -2,6 +2,8 @@
 two-field preheating lattice, 6th order, dt = 0.0025, in the tile shape the
 benchmark uses, one composed step (7 fused passes) against the oracle run on
 the full lattice; plus properties that hold at any size."""
+import math
+
 import numpy as np
 import pytest
 
@@ -108,3 +110,25 @@ def test_qball512_fp32():
     ef, ep = max_rel(gphi, o.phi), max_rel(gpi, o.pi)
     say("qball 32^3 same dx fp64 vs oracle", ef, ep)
     assert max(ef, ep) <= 1e-10
+
+
+def test_largest_side_fp32_white():
+    """n = 1024, the largest side the library accepts (two FP32 fields,
+    4 x 8.6 GB): pass shapes within the grid bounds, two 4th-order steps,
+    the Friedmann residual and the background against the homogeneous
+    expectation (a grows, p_a stays negative)."""
+    n = 1024
+    lat = sl.Lattice(n, 2, 40.0, precision="f32", mpl=synth.PREHEAT_MPL)
+    lat.set_potential("chaotic2", (1.0, 100.0))
+    lat.init_fluctuations([1.0, 0.0], [0.0, 0.0], "white", 1e-6, 20120130)
+    tx, vx, ty, tz, pf = lat.tile()
+    blocks = math.ceil(n / (tx * vx)) * math.ceil(n / ty) * math.ceil(n / tz)
+    say("n=1024 tile", lat.tile(), "blocks", blocks)
+    assert blocks <= 65536
+    eta0, a0, pa0 = lat.background()
+    lat.evolve(2, 0.005, 4)
+    e = lat.energies()
+    say("n=1024 residual", e["friedmann_residual"], "a", e["a"])
+    assert e["friedmann_residual"] < 1e-3
+    assert e["a"] > a0 and e["p_a"] < 0 and e["eta"] == pytest.approx(0.01)
+    lat.close()

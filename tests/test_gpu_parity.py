@@ -382,3 +382,29 @@ def test_autotune_mid_run_keeps_state_bitwise():
     assert all(np.array_equal(x, y) for x, y in zip(g.history(), h.history()))
     assert len(g.history()[0]) == 17
     sl.symlat.autotune_forget()
+
+
+def test_zero_steps_and_empty_batches_are_no_ops():
+    c, phi, pi = _preheat_state(16, seed=50)
+    g = gpu_lattice(16, c["L"], c["potential"], c["params"], phi, pi, mpl=c["mpl"])
+    g.evolve(3, c["dt"], 4)                  # a drift pending
+    f0, p0 = g.get_fields()
+    b0 = g.background()
+    g.evolve(0, c["dt"], 4)
+    with pytest.raises(sl.SymlatError):
+        g.evolve(0, 1e9, 4)                  # arguments are checked for zero steps too
+    f1, p1 = g.get_fields()
+    assert np.array_equal(f0, f1) and np.array_equal(p0, p1) and g.background() == b0
+    b = sl.Batch()
+    b.step(5, c["dt"], 4)                    # no members
+    b.add(g)
+    b.step(0, c["dt"], 4)
+    b.synchronize()
+    assert g.background() == b0
+    lin = sl.Linear(16, 2, c["L"], mpl=c["mpl"])
+    lin.set_potential(c["potential"], c["params"])
+    lin.set_fields(phi, pi)
+    lf0 = lin.get_fields()
+    lin.evolve(0, c["dt"], 4)
+    lf1 = lin.get_fields()
+    assert all(np.array_equal(x, y) for x, y in zip(lf0, lf1))
