@@ -95,7 +95,7 @@ def measure(sl, recipe, steps, warmup, tile=None, fields=None):
         log("pass shape fixed to", lat.tile())
     else:
         shape, best = lat.autotune(reps=5)
-        log("autotuned pass shape (tx, vx, tz, pf) =", shape, "best pass %.4f ms" % best)
+        log("autotuned pass shape (tx, vx, tz, pf) =", shape, "best stage %.4f ms" % best)
     # at least 33 steps, so that the captured 32-step chunk of the evolve
     # graph is built before the timed region
     lat.evolve(max(warmup, 33), dt, order)

@@ -338,8 +338,9 @@ class Lattice:
         _check(self._lib.sl_set_tile(self._h, int(tx), int(vx), int(tz), int(pf)))
 
     def autotune(self, reps=3, vx_only=0, pf_only=0):
-        """Pick the fastest pass shape for this lattice; returns
-        ((tx, vx, tz, pf), best pass ms)."""
+        """Pick the fastest pass shape for this lattice (timed as real
+        stages with frozen coefficients; the state is kept); returns
+        ((tx, vx, tz, pf), best time of one stage in ms)."""
         v = [ctypes.c_int32() for _ in range(4)]
         ms = ctypes.c_double()
         _check(self._lib.sl_autotune(self._h, int(reps), int(vx_only), int(pf_only),
