@@ -282,7 +282,8 @@ sl_status sl_set_tile(sl_lattice* lat, int32_t tx, int32_t vx, int32_t tz, int32
  * wrote, as inside sl_evolve) with the drift and kick coefficients frozen at
  * zero, so the fields keep their values; the scalars are restored after.
  * best_ms is the time of one stage.  vx_only / pf_only
- * (0 = free) restrict the search, e.g. to the per-lane shape of a batch.
+ * (0 = free) restrict the search; a batch member is tuned within its own vx
+ * and pf (the batch is rebuilt at its next step).
  * The winner is applied and remembered for this process: lattices created
  * later with the same (device, n, fields, precision, potential family) start
  * with it.  Outputs may be NULL.  sl_autotune_forget clears that memory and

@@ -921,6 +921,12 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
     return fail(SL_E_INVALID, "vx_only must be 0, 1, 2 or 4");
   if (pf_only != 0 && pf_only != 1 && pf_only != 2) return fail(SL_E_INVALID, "pf_only must be 0, 1 or 2");
   const int n = L->cfg.n;
+  // a batch member keeps its per-lane shape (the batch's kernel is built
+  // for it)
+  if (L->batch) {
+    vx_only = L->v.tile.vx;
+    pf_only = L->v.tile.pf;
+  }
   // more than two fields: one site per lane, pf = 1; the 27-point pass:
   // one or two sites per lane, pf = 1
   const bool many = L->cfg.nfields > 2;
@@ -1018,6 +1024,7 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
     }
   }
   if (!found) tune_cache().push_back({key, {win.tx, win.vx, win.tz, win.pf}});
+  if (L->batch) batch_member_changed(L->batch);
   if (tx_out) *tx_out = win.tx;
   if (vx_out) *vx_out = win.vx;
   if (tz_out) *tz_out = L->v.tile.tz;

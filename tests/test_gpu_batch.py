@@ -174,3 +174,29 @@ def test_history_records_every_step_alone_and_batched():
     phi, pi = mem.get_fields()
     mem.set_fields(phi, pi)                       # a reset restarts the record
     assert len(mem.history()[0]) == 0
+
+
+def test_member_autotune_keeps_the_batch_lane_shape():
+    """Tuning one member alone keeps its per-lane shape (vx, pf), which the
+    batch's kernel is built for; the batch then advances it bit for bit
+    like the same lattice alone with the tuned shape."""
+    sl.symlat.load().sl_autotune_forget()
+    recipes = _runs("f32", [32, 64])
+    mixed = [sl.from_recipe(r) for r in recipes]
+    b = sl.Batch()
+    for m in mixed:
+        b.add(m)
+    alone = sl.from_recipe(recipes[1])
+    tx, vx, _, tz, pf = mixed[1].tile()
+    alone.set_tile(tx, vx, tz, pf)
+    b.step(3, 0.005, 4)
+    alone.evolve(3, 0.005, 4)
+    mixed[1].autotune(reps=1)
+    tx, vx2, _, tz, pf2 = mixed[1].tile()
+    assert (vx2, pf2) == (vx, pf)
+    alone.set_tile(tx, vx, tz, pf)
+    b.step(7, 0.005, 4)
+    alone.evolve(7, 0.005, 4)
+    b.synchronize()
+    assert _same(alone, mixed[1])
+    sl.symlat.load().sl_autotune_forget()
