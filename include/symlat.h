@@ -29,7 +29,9 @@
  *     without waiting; device-side failures (non-finite lattice sums) are
  *     reported by the next synchronising call (sl_energies, sl_get_fields,
  *     sl_get_background, sl_spectrum, sl_synchronize) as SL_E_NONFINITE.
- *   - One handle must not be used from two threads at once.
+ *   - One handle must not be used from two threads at once (a batch and
+ *     its members count as one).  Different handles may be used from
+ *     different threads; the process-wide memory of tuned shapes is locked.
  */
 #ifndef SYMLAT_H
 #define SYMLAT_H

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -204,19 +205,52 @@ size_t partial_doubles() {
   return pass > diag ? pass : diag;
 }
 
-// Process-wide cache of autotuned pass shapes keyed by (device, n, fields,
-// precision, potential family).
+// Process-wide caches of tuned pass shapes, shared by every thread of the
+// process: one mutex each, lookups copy the value out.
+struct TuneVal {
+  int tx, vx, tz, pf;
+};
+template <typename K>
+class ShapeCache {
+ public:
+  bool find(const K& k, TuneVal* v) {
+    std::lock_guard<std::mutex> g(m_);
+    for (const auto& kv : c_)
+      if (kv.first == k) {
+        *v = kv.second;
+        return true;
+      }
+    return false;
+  }
+  void put(const K& k, const TuneVal& v) {
+    std::lock_guard<std::mutex> g(m_);
+    for (auto& kv : c_)
+      if (kv.first == k) {
+        kv.second = v;
+        return;
+      }
+    c_.push_back({k, v});
+  }
+  void clear() {
+    std::lock_guard<std::mutex> g(m_);
+    c_.clear();
+  }
+
+ private:
+  std::mutex m_;
+  std::vector<std::pair<K, TuneVal>> c_;
+};
+
+// Autotuned single-lattice shapes keyed by (device, n, fields, precision,
+// potential family, stencil kind).
 struct TuneKey {
   int dev, n, nf, prec, pot, st;
   bool operator==(const TuneKey& o) const {
     return dev == o.dev && n == o.n && nf == o.nf && prec == o.prec && pot == o.pot && st == o.st;
   }
 };
-struct TuneVal {
-  int tx, vx, tz, pf;
-};
-std::vector<std::pair<TuneKey, TuneVal>>& tune_cache() {
-  static std::vector<std::pair<TuneKey, TuneVal>> c;
+ShapeCache<TuneKey>& tune_cache() {
+  static ShapeCache<TuneKey> c;
   return c;
 }
 
@@ -227,8 +261,8 @@ struct BatchTuneKey {
   int vx, pf;
   bool operator==(const BatchTuneKey& o) const { return k == o.k && vx == o.vx && pf == o.pf; }
 };
-std::vector<std::pair<BatchTuneKey, TuneVal>>& batch_tune_cache() {
-  static std::vector<std::pair<BatchTuneKey, TuneVal>> c;
+ShapeCache<BatchTuneKey>& batch_tune_cache() {
+  static ShapeCache<BatchTuneKey> c;
   return c;
 }
 
@@ -506,12 +540,11 @@ sl_status sl_set_potential(sl_lattice* L, int32_t kind, const double* params, in
   L->pot_set = true;
   refresh_m2max(L);
   const TuneKey key{L->device, L->cfg.n, L->cfg.nfields, L->cfg.precision, kind, L->v.st.kind};
-  for (const auto& kv : tune_cache()) {
-    if (kv.first == key) {
-      L->tz_user = kv.second.tz;
-      retile(L, kv.second.tx, kv.second.vx, kv.second.tz, kv.second.pf);
-      return SL_OK;
-    }
+  TuneVal tv;
+  if (tune_cache().find(key, &tv)) {
+    L->tz_user = tv.tz;
+    retile(L, tv.tx, tv.vx, tv.tz, tv.pf);
+    return SL_OK;
   }
   retile(L, L->v.tile.tx, L->v.tile.vx, L->tz_user, L->v.tile.pf);
   return SL_OK;
@@ -1016,14 +1049,7 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
   L->tz_user = win.tz;
   retile(L, win.tx, win.vx, win.tz, win.pf);
   const TuneKey key{L->device, n, L->cfg.nfields, L->cfg.precision, L->v.pot, L->v.st.kind};
-  bool found = false;
-  for (auto& kv : tune_cache()) {
-    if (kv.first == key) {
-      kv.second = {win.tx, win.vx, win.tz, win.pf};
-      found = true;
-    }
-  }
-  if (!found) tune_cache().push_back({key, {win.tx, win.vx, win.tz, win.pf}});
+  tune_cache().put(key, {win.tx, win.vx, win.tz, win.pf});
   if (L->batch) batch_member_changed(L->batch);
   if (tx_out) *tx_out = win.tx;
   if (vx_out) *vx_out = win.vx;
@@ -1114,13 +1140,12 @@ sl_status sl_set_stencil(sl_lattice* L, const double* c) {
     }
     if (L->pot_set) {
       const TuneKey key{L->device, L->cfg.n, L->cfg.nfields, L->cfg.precision, L->v.pot, kind};
-      for (const auto& kv : tune_cache()) {
-        if (kv.first == key) {
-          tx = kv.second.tx;
-          vx = kv.second.vx;
-          pf = kv.second.pf;
-          L->tz_user = kv.second.tz;
-        }
+      TuneVal tv;
+      if (tune_cache().find(key, &tv)) {
+        tx = tv.tx;
+        vx = tv.vx;
+        pf = tv.pf;
+        L->tz_user = tv.tz;
       }
     }
     retile(L, tx, vx, L->tz_user, pf);
@@ -1314,13 +1339,13 @@ sl_status sl_batch_add(sl_batch* B, sl_lattice* L) {
   int tx = L->v.tile.tx, vx = L->v.tile.vx, tz = L->tz_user, pf = L->v.tile.pf;
   const BatchTuneKey key{{L->device, L->cfg.n, L->cfg.nfields, L->cfg.precision, L->v.pot, L->v.st.kind},
                          0, 0};
-  for (const auto& kv : batch_tune_cache())
-    if (kv.first == key) {
-      tx = kv.second.tx;
-      vx = kv.second.vx;
-      tz = kv.second.tz;
-      pf = kv.second.pf;
-    }
+  TuneVal tv;
+  if (batch_tune_cache().find(key, &tv)) {
+    tx = tv.tx;
+    vx = tv.vx;
+    tz = tv.tz;
+    pf = tv.pf;
+  }
   if (!B->runs.empty() && (vx != B->shape.vx || pf != B->shape.pf)) {
     vx = B->shape.vx;
     pf = B->shape.pf;
@@ -1531,13 +1556,7 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
     const BatchTuneKey key{{R->device, R->cfg.n, R->cfg.nfields, R->cfg.precision, R->v.pot, R->v.st.kind},
                            0, 0};
     const TuneVal val{best_pick[i].tx, best_vx, best_pick[i].tz, best_pf};
-    bool found = false;
-    for (auto& kv : batch_tune_cache())
-      if (kv.first == key) {
-        kv.second = val;
-        found = true;
-      }
-    if (!found) batch_tune_cache().push_back({key, val});
+    batch_tune_cache().put(key, val);
   }
   B->dirty = true;
   ++B->version;
