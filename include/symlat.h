@@ -240,8 +240,14 @@ sl_status sl_get_background(sl_lattice* lat, double* eta, double* a, double* p_a
 /* Wait for the handle's stream; reports sticky device-side errors. */
 sl_status sl_synchronize(sl_lattice* lat);
 
-/* Device bytes a lattice of this configuration allocates (0 if invalid). */
+/* Device bytes a lattice of this configuration holds from creation to
+ * destruction (0 if invalid); sl_set_history adds 24 bytes per record.
+ * sl_transient_bytes: the most any single call on such a lattice allocates
+ * on top while it runs and frees before returning (vacuum or white initial
+ * state, sl_set_fields / sl_get_fields staging, sl_spectrum, sl_spectra);
+ * 0 if invalid.  Admission keeps footprint + transient free. */
 size_t sl_footprint_bytes(const sl_config* cfg);
+size_t sl_transient_bytes(const sl_config* cfg);
 
 /* Thread-local message of the last failing call on this thread. */
 const char* sl_last_error(void);

@@ -426,6 +426,21 @@ size_t sl_footprint_bytes(const sl_config* cfg) {
          sizeof(double) * 3 * kMaxBins;
 }
 
+size_t sl_transient_bytes(const sl_config* cfg) {
+  std::string why;
+  if (!config_ok(cfg, &why)) return 0;
+  const size_t n = size_t(cfg->n), n3 = n * n * n, nf = size_t(cfg->nfields);
+  const size_t fft = 2 * n3 * sizeof(double2) + n * sizeof(double2);
+  const size_t staging = 2 * nf * n3 * sizeof(double);               // set/get fields
+  const size_t white = n3 * sizeof(double) + sizeof(double);         // white initial state
+  const size_t spectrum = fft + size_t(spectrum_blocks(cfg->n)) * 3 * kMaxBins * sizeof(double);
+  const size_t spectra = fft + n3 * sizeof(double2) +
+                         size_t(mode_spectra_blocks(cfg->n)) * 5 * kMaxBins * sizeof(double) +
+                         meff_partial_doubles(cfg->nfields) * sizeof(double) +
+                         (kMaxFields + 5 * kMaxBins) * sizeof(double);
+  return std::max({fft, staging, white, spectrum, spectra});
+}
+
 sl_status sl_lattice_create(const sl_config* cfg, void* hip_stream, sl_lattice** out) {
   if (!out) return fail(SL_E_INVALID, "out is NULL");
   *out = nullptr;

@@ -21,7 +21,7 @@ from collections import deque
 
 import numpy as np
 
-from .symlat import Batch, device_memory, footprint_bytes, from_recipe
+from .symlat import Batch, device_memory, footprint_bytes, from_recipe, transient_bytes
 
 
 # Run kinds the batch tuner has seen in this process; the library gives
@@ -40,8 +40,16 @@ class Request:
         self.recipe = recipe
         self.arrival = float(arrival)
         self.steps = int(steps if steps is not None else recipe["steps"])
-        self.footprint = footprint_bytes(n=recipe["n"], nfields=recipe["nfields"], L=recipe["L"],
-                                         precision=recipe.get("precision", "f64"))
+        cfg = dict(n=recipe["n"], nfields=recipe["nfields"], L=recipe["L"],
+                   precision=recipe.get("precision", "f64"))
+        self.footprint = footprint_bytes(**cfg)
+        self.transient = transient_bytes(**cfg)
+
+
+def _resident_bytes(req, history):
+    """Device bytes a served run holds while resident (with its per-step
+    background record when history is on: 3 doubles per step)."""
+    return req.footprint + (24 * req.steps if history else 0)
 
 
 def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
@@ -81,13 +89,17 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
-            # admission: arrival order, a free slot and the footprint must fit
+            # admission: arrival order, a free slot, and the footprints of the
+            # resident runs plus the largest scratch one call of any of them
+            # allocates (initial state, read-out) must fit
             while waiting and len(active) < max_slots:
                 req = waiting[0]
-                if req.footprint > hbm_budget:
+                need = _resident_bytes(req, history)
+                if need + req.transient > hbm_budget:
                     raise ValueError("request %r needs %d bytes, more than the budget %d"
-                                     % (req.id, req.footprint, hbm_budget))
-                if used + req.footprint > hbm_budget:
+                                     % (req.id, need + req.transient, hbm_budget))
+                reserve = max([req.transient] + [a[0].transient for a in active.values()])
+                if used + need + reserve > hbm_budget:
                     deferred += 1
                     break
                 waiting.popleft()
@@ -95,7 +107,7 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
                 if history:
                     lat.set_history(req.steps)
                 batch.add(lat)
-                used += req.footprint
+                used += need
                 active[req.id] = [req, lat, 0, clock() - t0]
             peak = max(peak, len(active))
             if not active:
@@ -129,7 +141,7 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
                     results.append(res)
                     batch.remove(lat)
                     lat.close()
-                    used -= req.footprint
+                    used -= _resident_bytes(req, history)
                     del active[rid]
     finally:
         for entry in active.values():

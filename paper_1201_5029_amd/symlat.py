@@ -25,7 +25,7 @@ EXPORTS = (
     "sl_lattice_create", "sl_lattice_destroy", "sl_set_potential",
     "sl_init_fluctuations", "sl_evolve", "sl_energies", "sl_spectrum",
     "sl_get_fields", "sl_set_fields", "sl_get_background", "sl_synchronize",
-    "sl_footprint_bytes", "sl_last_error", "sl_composition_weights",
+    "sl_footprint_bytes", "sl_transient_bytes", "sl_last_error", "sl_composition_weights",
     "sl_stability_limit", "sl_set_kernel_timing", "sl_kernel_timing",
     "sl_get_tile", "sl_set_tile", "sl_hbm_copy_bench",
     "sl_batch_create", "sl_batch_destroy", "sl_batch_add", "sl_batch_remove",
@@ -95,6 +95,7 @@ def load():
         "sl_get_background": (I32, [P, dp, dp, dp]),
         "sl_synchronize": (I32, [P]),
         "sl_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(Config)]),
+        "sl_transient_bytes": (ctypes.c_size_t, [ctypes.POINTER(Config)]),
         "sl_last_error": (ctypes.c_char_p, []),
         "sl_composition_weights": (I32, [I32, dp, I32]),
         "sl_stability_limit": (D, [I32]),
@@ -181,7 +182,13 @@ def hbm_copy_bench(nbytes, iters=20):
 
 
 def footprint_bytes(**cfg):
+    """Device bytes a lattice of this configuration holds while it lives."""
     return int(load().sl_footprint_bytes(ctypes.byref(make_config(**cfg))))
+
+
+def transient_bytes(**cfg):
+    """Most device bytes one call on such a lattice allocates while it runs."""
+    return int(load().sl_transient_bytes(ctypes.byref(make_config(**cfg))))
 
 
 def autotune_forget():

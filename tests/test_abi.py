@@ -80,6 +80,19 @@ def test_footprint_counts_both_ping_pong_copies():
     assert f32 >= 4 * state * 4 and f64 - f32 == 4 * state * 4
 
 
+def test_transient_bytes_cover_every_scratch_buffer():
+    """The scratch figure covers the transform buffers (two complex n^3
+    arrays), the FP64 staging of both arrays of every field and the
+    spectra's extra complex copy; it is 0 for an invalid configuration."""
+    for n, nf in [(16, 1), (64, 2), (32, 8)]:
+        t = sl.transient_bytes(n=n, nfields=nf, L=10.0)
+        assert t >= 3 * n ** 3 * 16 and t >= 2 * nf * n ** 3 * 8
+        assert t - max(3 * n ** 3 * 16, 2 * nf * n ** 3 * 8) < 64 << 20
+    assert sl.transient_bytes(n=3, nfields=2, L=10.0) == 0
+    assert sl.transient_bytes(n=64, nfields=2, L=10.0, precision="f32") == \
+        sl.transient_bytes(n=64, nfields=2, L=10.0)
+
+
 def test_null_handles_are_rejected():
     lib = sl.load()
     assert lib.sl_lattice_destroy(None) == binding.SL_OK

@@ -43,7 +43,7 @@ def test_served_results_equal_alone():
 
 def test_admission_by_footprint():
     reqs = _requests([0.0] * 6, [64] * 6, steps=20)
-    budget = 2 * reqs[0].footprint + 1
+    budget = 2 * reqs[0].footprint + reqs[0].transient + 1
     results, stats = serve.serve(reqs, dt=0.005, order=4, max_slots=8, tick_steps=10,
                                  hbm_budget=budget)
     assert stats["runs"] == 6 and stats["peak_resident"] == 2

@@ -88,6 +88,7 @@ def fake(monkeypatch):
     monkeypatch.setattr(serve, "Batch", TimedBatch)
     monkeypatch.setattr(serve, "from_recipe", FakeLattice)
     monkeypatch.setattr(serve, "footprint_bytes", lambda **kw: 100 * kw["n"])
+    monkeypatch.setattr(serve, "transient_bytes", lambda **kw: 10 * kw["n"])
     serve._TUNED.clear()
     return clock
 
@@ -112,13 +113,38 @@ def test_admission_slots_and_ticks(fake):
 
 def test_admission_by_footprint_defers(fake):
     reqs = [_req(i, 64, 0.0, 10) for i in range(4)]
-    budget = 2 * 100 * 64
+    budget = 2 * 100 * 64 + 10 * 64          # two footprints and one call's scratch
     res, st = serve.serve(reqs, 0.005, 4, max_slots=8, tick_steps=10, hbm_budget=budget,
                           clock=fake, sleep=fake.sleep)
     assert st["peak_resident"] == 2 and st["deferred_for_memory"] >= 1 and st["runs"] == 4
     with pytest.raises(ValueError):
         serve.serve([_req(9, 64, 0.0, 10)], 0.005, 4, hbm_budget=100, clock=fake,
                     sleep=fake.sleep)
+
+
+def test_admission_keeps_the_largest_scratch_free(fake):
+    """A resident run whose calls need more scratch than the newcomer's
+    keeps that scratch free: the newcomer waits although its own footprint
+    and scratch would fit."""
+    big, small = _req(0, 128, 0.0, 30), _req(1, 16, 0.0, 10)
+    budget = 100 * 128 + 100 * 16 + 10 * 128 - 1
+    assert 100 * 128 + 100 * 16 + 10 * 16 <= budget   # the newcomer's own needs fit
+    res, st = serve.serve([big, small], 0.005, 4, max_slots=4, tick_steps=10,
+                          hbm_budget=budget, clock=fake, sleep=fake.sleep)
+    assert st["deferred_for_memory"] >= 1 and st["peak_resident"] == 1
+    budget += 1                              # room for the larger scratch: both resident
+    res, st = serve.serve([_req(0, 128, 0.0, 30), _req(1, 16, 0.0, 10)], 0.005, 4,
+                          max_slots=4, tick_steps=10, hbm_budget=budget, clock=fake,
+                          sleep=fake.sleep)
+    assert st["peak_resident"] == 2
+
+
+def test_history_counts_in_the_footprint(fake):
+    reqs = [_req(i, 32, 0.0, 100) for i in range(2)]
+    budget = 2 * 100 * 32 + 10 * 32          # fits two runs without their records
+    res, st = serve.serve(reqs, 0.005, 4, max_slots=4, tick_steps=50, hbm_budget=budget,
+                          history=True, clock=fake, sleep=fake.sleep)
+    assert st["peak_resident"] == 1 and st["runs"] == 2
 
 
 def test_late_arrivals_join_and_latency(fake):
