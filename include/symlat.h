@@ -132,6 +132,22 @@ typedef struct {
  * not > 0, or a NULL argument. */
 sl_status sl_lattice_create(const sl_config* cfg, void* hip_stream, sl_lattice** out);
 
+/* As sl_lattice_create, but the handle adopts the caller's four field
+ * arrays instead of allocating them: phi0, pi0 (buffer 0) and phi1, pi1
+ * (buffer 1), each nfields * n^3 elements of the storage precision in the
+ * [field][z][y][x] layout, in device memory of the current device (hipMalloc
+ * or a pool carved from it), 16-byte aligned and not overlapping.  The
+ * handle zero-fills them at creation, uses them until sl_lattice_destroy and
+ * never frees them; the caller keeps them alive that long and touches them
+ * only between synchronising calls.  Which buffer holds the state alternates
+ * with the stages: read it with sl_get_fields.  The small buffers (partial
+ * sums, scalars) are still the handle's.  SL_E_INVALID if an array is NULL,
+ * misaligned, not device memory of this device, shorter than needed inside
+ * its allocation, or overlaps another.  sl_footprint_bytes still counts the
+ * four arrays. */
+sl_status sl_lattice_create_with_buffers(const sl_config* cfg, void* hip_stream, void* phi0,
+                                         void* pi0, void* phi1, void* pi1, sl_lattice** out);
+
 /* Release all device memory of the handle; NULL is a no-op. */
 sl_status sl_lattice_destroy(sl_lattice* lat);
 

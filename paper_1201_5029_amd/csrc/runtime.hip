@@ -272,6 +272,7 @@ struct sl_lattice {
   sl_config cfg{};
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  bool own_fields = true;  // false: the four field arrays belong to the caller
   int device = 0;
   LatView v{};
   size_t n3 = 0;
@@ -353,7 +354,7 @@ void drop_graph(sl_lattice* L) {
 
 void free_all(sl_lattice* L) {
   drop_graph(L);
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 2 && L->own_fields; ++k) {
     if (L->v.phi[k]) (void)hipFree(L->v.phi[k]);
     if (L->v.pi[k]) (void)hipFree(L->v.pi[k]);
   }
@@ -441,7 +442,50 @@ size_t sl_transient_bytes(const sl_config* cfg) {
   return std::max({fft, staging, white, spectrum, spectra});
 }
 
+namespace {
+
+// A caller's field array: device memory of the current device, 16-byte
+// aligned (vector loads), with `bytes` bytes inside one allocation.
+sl_status check_user_array(void* p, size_t bytes, int device, const char* name) {
+  if (!p) return fail(SL_E_INVALID, "%s is NULL", name);
+  if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return fail(SL_E_INVALID, "%s is not 16-byte aligned", name);
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+      attr.device != device) {
+    (void)hipGetLastError();
+    return fail(SL_E_INVALID, "%s is not device memory of device %d", name, device);
+  }
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SL_E_INVALID, "%s: cannot find its allocation", name);
+  }
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base), q = reinterpret_cast<uintptr_t>(p);
+  if (q < b || q - b > size || size - (q - b) < bytes)
+    return fail(SL_E_INVALID, "%s holds fewer than the %zu bytes the lattice needs", name, bytes);
+  return SL_OK;
+}
+
+sl_status create_impl(const sl_config* cfg, void* hip_stream, void* const* user, sl_lattice** out);
+
+}  // namespace
+
 sl_status sl_lattice_create(const sl_config* cfg, void* hip_stream, sl_lattice** out) {
+  return create_impl(cfg, hip_stream, nullptr, out);
+}
+
+sl_status sl_lattice_create_with_buffers(const sl_config* cfg, void* hip_stream, void* phi0, void* pi0,
+                                         void* phi1, void* pi1, sl_lattice** out) {
+  void* const user[4] = {phi0, pi0, phi1, pi1};
+  return create_impl(cfg, hip_stream, user, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+sl_status create_impl(const sl_config* cfg, void* hip_stream, void* const* user, sl_lattice** out) {
   if (!out) return fail(SL_E_INVALID, "out is NULL");
   *out = nullptr;
   std::string why;
@@ -454,6 +498,25 @@ sl_status sl_lattice_create(const sl_config* cfg, void* hip_stream, sl_lattice**
   if (hipGetDevice(&L->device) != hipSuccess) {
     delete L;
     return fail(SL_E_DEVICE, "no HIP device");
+  }
+  const size_t fbytes = L->n3 * cfg->nfields * L->elem;
+  if (user) {
+    static const char* names[4] = {"phi0", "pi0", "phi1", "pi1"};
+    for (int k = 0; k < 4; ++k) {
+      const sl_status st = check_user_array(user[k], fbytes, L->device, names[k]);
+      if (st != SL_OK) {
+        delete L;
+        return st;
+      }
+      for (int j = 0; j < k; ++j) {
+        const uintptr_t a = reinterpret_cast<uintptr_t>(user[j]), b = reinterpret_cast<uintptr_t>(user[k]);
+        if ((a < b ? b - a : a - b) < fbytes) {
+          delete L;
+          return fail(SL_E_INVALID, "%s and %s overlap", names[j], names[k]);
+        }
+      }
+    }
+    L->own_fields = false;
   }
   if (hip_stream) {
     L->stream = static_cast<hipStream_t>(hip_stream);
@@ -489,9 +552,14 @@ sl_status sl_lattice_create(const sl_config* cfg, void* hip_stream, sl_lattice**
   L->partials_n = partial_doubles();
   L->a_host = cfg->a0;
 
-  const size_t fbytes = L->n3 * cfg->nfields * L->elem;
   bool ok = true;
-  for (int k = 0; k < 2 && ok; ++k) {
+  if (user) {
+    v.phi[0] = user[0];
+    v.pi[0] = user[1];
+    v.phi[1] = user[2];
+    v.pi[1] = user[3];
+  }
+  for (int k = 0; k < 2 && ok && !user; ++k) {
     ok = ok && hipMalloc(&v.phi[k], fbytes) == hipSuccess;
     ok = ok && hipMalloc(&v.pi[k], fbytes) == hipSuccess;
   }
@@ -520,6 +588,10 @@ sl_status sl_lattice_create(const sl_config* cfg, void* hip_stream, sl_lattice**
   *out = L;
   return SL_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 sl_status sl_lattice_destroy(sl_lattice* L) {
   if (!L) return SL_OK;

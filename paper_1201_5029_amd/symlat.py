@@ -22,7 +22,7 @@ FLUCT = {"none": 0, "vacuum": 1, "white": 2}
 
 #: every symbol the header declares (checked by the CPU test suite)
 EXPORTS = (
-    "sl_lattice_create", "sl_lattice_destroy", "sl_set_potential",
+    "sl_lattice_create", "sl_lattice_create_with_buffers", "sl_lattice_destroy", "sl_set_potential",
     "sl_init_fluctuations", "sl_evolve", "sl_energies", "sl_spectrum",
     "sl_get_fields", "sl_set_fields", "sl_get_background", "sl_synchronize",
     "sl_footprint_bytes", "sl_transient_bytes", "sl_last_error", "sl_composition_weights",
@@ -84,6 +84,8 @@ def load():
     dp = ctypes.POINTER(ctypes.c_double)
     sig = {
         "sl_lattice_create": (I32, [ctypes.POINTER(Config), P, ctypes.POINTER(P)]),
+        "sl_lattice_create_with_buffers": (I32, [ctypes.POINTER(Config), P, P, P, P, P,
+                                                 ctypes.POINTER(P)]),
         "sl_lattice_destroy": (I32, [P]),
         "sl_set_potential": (I32, [P, I32, dp, I32]),
         "sl_init_fluctuations": (I32, [P, dp, dp, I32, D, U64]),
@@ -203,17 +205,27 @@ def device_memory():
 
 
 class Lattice:
-    """One lattice handle.  ``stream`` is an optional hipStream_t (int)."""
+    """One lattice handle.  ``stream`` is an optional hipStream_t (int);
+    ``buffers`` optional device addresses (ints) of the caller's four field
+    arrays (phi0, pi0, phi1, pi1), which the handle then uses without owning
+    them (sl_lattice_create_with_buffers)."""
 
     def __init__(self, n, nfields, L, precision="f64", expand=True, mpl=1.0, a0=1.0,
-                 rho_rad0=0.0, rho_mat0=0.0, stream=None):
+                 rho_rad0=0.0, rho_mat0=0.0, stream=None, buffers=None):
         self._lib = load()
         self.n, self.nfields, self.L = int(n), int(nfields), float(L)
         self.precision = precision
         self.cfg = make_config(n, nfields, L, precision, expand, mpl, a0, rho_rad0, rho_mat0)
         h = ctypes.c_void_p()
-        _check(self._lib.sl_lattice_create(ctypes.byref(self.cfg),
-                                           ctypes.c_void_p(stream or 0), ctypes.byref(h)))
+        if buffers is None:
+            _check(self._lib.sl_lattice_create(ctypes.byref(self.cfg),
+                                               ctypes.c_void_p(stream or 0), ctypes.byref(h)))
+        else:
+            b = [ctypes.c_void_p(int(x) if x else 0) for x in buffers]
+            if len(b) != 4:
+                raise ValueError("buffers: four device addresses (phi0, pi0, phi1, pi1)")
+            _check(self._lib.sl_lattice_create_with_buffers(
+                ctypes.byref(self.cfg), ctypes.c_void_p(stream or 0), *b, ctypes.byref(h)))
         self._h = h
 
     # -- lifetime ---------------------------------------------------------
