@@ -345,12 +345,67 @@ def cpu_baseline(recipe):
                          recipe["workload"], t)}
 
 
+def _oracle_runs(job):
+    """Worker of the ensemble comparator: the oracle on one ensemble run,
+    `steps` composed steps timed after its initial state is built."""
+    recipe, steps = job
+    import oracle
+    pot = oracle.Potential(recipe["potential"], recipe["params"])
+    o = oracle.Lattice(recipe["n"], recipe["L"], pot, mpl=recipe["mpl"])
+    o.init_fluctuations(recipe["phi0"], recipe["pi0"], recipe["fluct"], recipe["amplitude"],
+                        recipe["seed"])
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        o.step(recipe["dt"], recipe["order"])
+    return recipe["n"] ** 3 * recipe["nfields"] * steps, time.perf_counter() - t0
+
+
+def cpu_ensemble_baseline(steps=4):
+    """CPU comparator of the served ensemble: P = (usable host CPUs, at most
+    16) oracle processes, each advancing one run of the Delta-N scan (the
+    scan's first P runs, FP64) `steps` steps at once; aggregate
+    field-site-updates/s = total work / longest worker time.  Forked before
+    this process touches the GPU."""
+    import multiprocessing as mp
+    import synth
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    procs = max(1, min(16, ncpu))
+    runs = synth.delta_n_scan()[:procs]
+    with mp.get_context("fork").Pool(procs) as pool:
+        res = pool.map(_oracle_runs, [(r, steps) for r in runs])
+    work = sum(w for w, _ in res)
+    longest = max(t for _, t in res)
+    return {"value": work / longest, "unit": "field-site-updates/s", "cores": procs,
+            "kind": "oracle", "sample": "%d processes, one Delta-N scan run each (n in %s), "
+            "%d steps of order 4, numpy FP64, longest worker %.2f s"
+            % (procs, sorted({r["n"] for r in runs}), steps, longest)}
+
+
+def cpu_parity_config():
+    """The oracle on the 32^3 parity configuration in full (200 steps of
+    order 4), one core."""
+    import synth
+    r = synth.preheat(n=32)
+    work, t = _oracle_runs((r, 200))
+    return {"value": work / t, "unit": "field-site-updates/s", "cores": 1, "seconds": t,
+            "sample": "32^3 preheat, 200 steps of order 4, numpy FP64"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the method's multi-GPU forms are not built "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    cpu_pre = {}
+    if not args.no_cpu_baseline:
+        # host-only legs first: the worker processes are forked before any GPU use
+        log("cpu baselines (oracle: ensemble processes, parity configuration) ...")
+        cpu_pre["ensemble"] = cpu_ensemble_baseline()
+        cpu_pre["parity_32"] = cpu_parity_config()
     import paper_1201_5029_amd as sl
     import synth
 
@@ -444,6 +499,9 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, 1 step) ...")
         out["cpu_baseline"] = cpu_baseline(recipe)
+        out["cpu_baseline"]["parity_32"] = cpu_pre["parity_32"]
+        if "served" in out:
+            out["served"]["cpu_ensemble_baseline"] = cpu_pre["ensemble"]
     print(json.dumps(out), flush=True)
 
 
