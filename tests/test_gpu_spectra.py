@@ -67,3 +67,24 @@ def test_spectra_fp32_storage():
     o.phi[...] = phi
     o.pi[...] = pi
     _check(o, g, 0, 16, 1e-9)
+
+
+def test_spectra_bin_count_edges_and_errors():
+    """One bin (it would hold only the excluded zero mode, so it is empty;
+    modes beyond the last bin are dropped, as in the oracle), the largest bin
+    count, and refused arguments: field out of range, nbins outside
+    [1, 2048], no initial state."""
+    import paper_1201_5029_amd as sl
+    c = synth.preheat(n=10)
+    o, g = _pair(10, c["potential"], c["params"], c["phi0"], [0.0, 0.0], 1e-2, c["L"],
+                 mpl=c["mpl"])
+    _check(o, g, 0, 1, 1e-9)
+    _check(o, g, 1, 2048, 1e-9)
+    for field, nb in [(2, 8), (-1, 8), (0, 0), (0, 2049)]:
+        with pytest.raises(sl.SymlatError) as e:
+            g.spectra(field, nb)
+        assert e.value.status == 1
+    bare = sl.Lattice(8, 2, 10.0)
+    with pytest.raises(sl.SymlatError) as e:
+        bare.spectra(0, 4)
+    assert e.value.status == 4
