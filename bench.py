@@ -360,7 +360,7 @@ def _oracle_runs(job):
     return recipe["n"] ** 3 * recipe["nfields"] * steps, time.perf_counter() - t0
 
 
-def cpu_ensemble_baseline(steps=4):
+def cpu_ensemble_baseline(steps=16):
     """CPU comparator of the served ensemble: P = (usable host CPUs, at most
     16) oracle processes, each advancing one run of the Delta-N scan (the
     scan's first P runs, FP64) `steps` steps at once; aggregate
