@@ -4,6 +4,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "timing.h"
 
 namespace symlat {
 namespace {
@@ -38,8 +39,8 @@ extern "C" sl_status sl_hbm_copy_bench(size_t bytes, int32_t iters, double* gbs)
     (void)hipFree(b);
     return SL_E_DEVICE;
   }
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
+  (void)timing_event_create(&e0);
+  (void)timing_event_create(&e1);
   const size_t count = bytes / 16;
   const unsigned grid = unsigned((count + kBlock - 1) / kBlock);
   (void)hipMemsetAsync(a, 0, bytes, s);

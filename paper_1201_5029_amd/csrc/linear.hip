@@ -35,6 +35,7 @@
 #include <vector>
 
 #include "device.h"
+#include "timing.h"
 
 namespace symlat {
 
@@ -496,7 +497,7 @@ sl_status new_rec(sl_linear* L, int kind, size_t* index) {
   sl_linear::Rec r{{nullptr, nullptr, nullptr, nullptr}, kind};
   const int ne = kind == 0 ? 4 : 2;
   for (int i = 0; i < ne; ++i) {
-    if (hipEventCreate(&r.e[i]) != hipSuccess) {
+    if (timing_event_create(&r.e[i]) != hipSuccess) {
       for (int j = 0; j < i; ++j) (void)hipEventDestroy(r.e[j]);
       return fail(SL_E_DEVICE, "cannot create a timing event");
     }
@@ -796,8 +797,8 @@ sl_status sl_linear_evolve(sl_linear* L, int64_t steps, double dt, int32_t order
       // identity, so repeating it leaves the same M (every variant applies
       // the same operations to a column)
       hipEvent_t t0, t1;
-      HIP_TRY(hipEventCreate(&t0));
-      HIP_TRY(hipEventCreate(&t1));
+      HIP_TRY(timing_event_create(&t0));
+      HIP_TRY(timing_event_create(&t1));
       float best = 1e30f;
       int win = 1;
       hipError_t err = hipSuccess;

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "timing.h"
 
 using namespace symlat;
 
@@ -759,8 +760,8 @@ sl_status sl_evolve(sl_lattice* L, int64_t steps, double dt, int32_t order) {
         const double wn = last_stage ? w[0] : w[j + 1];
         if (L->timing) {
           hipEvent_t e0, e1;
-          HIP_TRY(hipEventCreate(&e0));
-          HIP_TRY(hipEventCreate(&e1));
+          HIP_TRY(timing_event_create(&e0));
+          HIP_TRY(timing_event_create(&e1));
           HIP_TRY(hipEventRecord(e0, L->stream));
           HIP_TRY(launch_pass(L->v, L->stream));
           HIP_TRY(hipEventRecord(e1, L->stream));
@@ -1092,8 +1093,8 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
   frozen.hist = nullptr;  // tuning stages are not recorded
   HIP_TRY(hipMemcpy(L->v.sc, &frozen, sizeof frozen, hipMemcpyHostToDevice));
   hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(timing_event_create(&e0));
+  HIP_TRY(timing_event_create(&e1));
   auto stage = [&]() -> hipError_t {
     hipError_t e = launch_pass(L->v, L->stream);
     if (e == hipSuccess) e = launch_stage_finalize(L->v, 1.0, 1.0, 0.0, 1, 0, L->stream);
@@ -1498,8 +1499,8 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
     return a.first > b.first;
   });
   hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(timing_event_create(&e0));
+  HIP_TRY(timing_event_create(&e1));
   // time the batched pass alone: without its finalize it leaves every
   // member's state as it was (reads the current buffer, writes the spare
   // buffer and the partials)
