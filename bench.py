@@ -187,7 +187,7 @@ def measure_batched(sl, nruns=96, steps=100):
         b.add(lat)
     pass_ms = b.autotune(reps=5)
     shapes = sorted(set((r["n"],) + tuple(lat.tile()) for r, lat in zip(recipes, lats)))
-    b.step(10, dt, order)
+    b.step(10, dt, order)          # captures the batch's chunk graph before the timed region
     b.synchronize()
     t0 = time.perf_counter()
     b.step(steps, dt, order)

@@ -325,8 +325,9 @@ sl_status sl_autotune_forget(void);
  * or set from the batch tuner's record for its size).  Each
  * stage is one fused pass over the concatenated tiles of all members (each
  * XCD strides through a contiguous range of them) and one finalize with a
- * workgroup per member; an evolve call is captured as a HIP graph and
- * replayed while (steps, dt, order, membership) are unchanged.  A member's
+ * workgroup per member; interior chunks of 8 steps of a call replay one
+ * captured HIP graph (kept while dt, order and membership are unchanged,
+ * whatever the step count), the last 1 .. 8 steps launch eagerly.  A member's
  * result is bit-identical to evolving it alone with the same tile shape.
  * The batch does not own its members: destroying a lattice removes it.
  * hip_stream: caller-owned hipStream_t or NULL (own stream).  The batch

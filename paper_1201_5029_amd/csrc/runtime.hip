@@ -144,6 +144,7 @@ namespace {
 
 constexpr long kMaxPassBlocks = 65536;  // bound of the per-block partial-sum buffer
 constexpr int64_t kEvolveChunk = 32;     // steps per captured evolve graph
+constexpr int64_t kBatchChunk = 8;       // steps per captured batch graph
 
 // Tile geometry for lanes tx (16/32/64), vx sites per lane, tz planes and
 // prefetch depth pf.
@@ -1274,7 +1275,6 @@ struct sl_batch {
   hipEvent_t ev = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  int64_t g_steps = -1;
   double g_dt = 0.0;
   int g_order = 0;
   uint64_t g_version = ~0ull;
@@ -1352,14 +1352,16 @@ sl_status batch_upload(sl_batch* B) {
 }
 
 // Enqueue one batched evolve call on the batch stream.
-sl_status batch_enqueue(sl_batch* B, int64_t steps, double dt, const std::vector<double>& w) {
+// `steps` steps of every member; has_next = 0 only for the last stage of the
+// call's last chunk, whose drift then stays pending.
+sl_status batch_enqueue(sl_batch* B, int64_t steps, double dt, const std::vector<double>& w,
+                        bool last_chunk) {
   const int R = int(B->runs.size());
   const int s = int(w.size());
-  HIP_TRY(launch_batched_begin(B->run_dev, R, w[0], dt, B->stream));
   for (int64_t step = 0; step < steps; ++step) {
     for (int j = 0; j < s; ++j) {
       const bool last_stage = j == s - 1;
-      const int has_next = !(last_stage && step == steps - 1);
+      const int has_next = !(last_stage && last_chunk && step == steps - 1);
       const double wn = last_stage ? w[0] : w[j + 1];
       HIP_TRY(launch_batched_pass(B->prec, B->pot, B->nf, B->shape, B->st_kind, B->lds, B->pass_dev,
                                   B->start_dev, R, B->grid, B->stream));
@@ -1679,27 +1681,35 @@ sl_status sl_batch_step(sl_batch* B, int64_t steps, double dt, int32_t order) {
     HIP_TRY(hipEventRecord(B->ev, L->stream));
     HIP_TRY(hipStreamWaitEvent(B->stream, B->ev, 0));
   }
-  // one captured graph per (steps, dt, order, membership); replayed when unchanged
-  if (!(B->gexec && B->g_steps == steps && B->g_dt == dt && B->g_order == order &&
-        B->g_version == B->version)) {
-    batch_drop_graph(B);
-    HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
-    sl_status st = batch_enqueue(B, steps, dt, w);
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(B->stream, &g);
-    if (st != SL_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return st;
+  HIP_TRY(launch_batched_begin(B->run_dev, int(B->runs.size()), w[0], dt, B->stream));
+  // Interior chunks of kBatchChunk steps replay one captured graph (kept
+  // while dt, order and membership are unchanged, whatever the step count
+  // of the call); the last 1 .. kBatchChunk steps launch eagerly.
+  const int64_t chunks = (steps - 1) / kBatchChunk;
+  if (chunks > 0) {
+    if (!(B->gexec && B->g_dt == dt && B->g_order == order && B->g_version == B->version)) {
+      batch_drop_graph(B);
+      HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+      sl_status st = batch_enqueue(B, kBatchChunk, dt, w, false);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(B->stream, &g);
+      if (st != SL_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return fail(SL_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+      B->graph = g;
+      HIP_TRY(hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
+      B->g_dt = dt;
+      B->g_order = order;
+      B->g_version = B->version;
     }
-    if (e != hipSuccess) return fail(SL_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
-    B->graph = g;
-    HIP_TRY(hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
-    B->g_steps = steps;
-    B->g_dt = dt;
-    B->g_order = order;
-    B->g_version = B->version;
+    for (int64_t c = 0; c < chunks; ++c) HIP_TRY(hipGraphLaunch(B->gexec, B->stream));
   }
-  HIP_TRY(hipGraphLaunch(B->gexec, B->stream));
+  {
+    const sl_status st = batch_enqueue(B, steps - chunks * kBatchChunk, dt, w, true);
+    if (st != SL_OK) return st;
+  }
   // members' later work waits for the batch
   HIP_TRY(hipEventRecord(B->ev, B->stream));
   for (sl_lattice* L : B->runs) {
