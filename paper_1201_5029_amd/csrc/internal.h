@@ -186,6 +186,9 @@ hipError_t launch_export(const LatView& v, double* phi_out, double* pi_out, hipS
 hipError_t launch_import(const LatView& v, const double* phi_in, const double* pi_in, double a,
                          double p_a, hipStream_t s);
 hipError_t launch_reset_scalars(const LatView& v, double a, double p_a, hipStream_t s);
+// Copy the scalars of the nruns runs of a batch table into out_dev[0 .. nruns).
+hipError_t launch_gather_scalars(const BatchRun* runs_dev, int nruns, DevScalars* out_dev,
+                                 hipStream_t s);
 
 // ---- initial state and spectrum (kernels_init.hip) ------------------------
 hipError_t launch_fill_homogeneous(const LatView& v, const double* phi0, const double* pi0,

@@ -326,6 +326,13 @@ __global__ void import_kernel(void* phi0, void* pi0, size_t count, const double*
   }
 }
 
+// One record per batch member, in table order, for a single read-back.
+__global__ void gather_scalars_kernel(const BatchRun* __restrict__ runs, int nruns,
+                                      DevScalars* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nruns) out[r] = *runs[r].sc;
+}
+
 __global__ void reset_scalars_kernel(DevScalars* sc, double a, double p_a) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     DevScalars S = *sc;  // keeps the history buffer; a reset restarts it
@@ -401,6 +408,14 @@ hipError_t launch_import(const LatView& v, const double* phi_in, const double* p
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(reset_scalars_kernel, dim3(1), dim3(64), 0, s, v.sc, a, p_a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_scalars(const BatchRun* runs_dev, int nruns, DevScalars* out_dev,
+                                 hipStream_t s) {
+  if (nruns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_scalars_kernel, dim3((nruns + 255) / 256), dim3(256), 0, s, runs_dev,
+                     nruns, out_dev);
   return hipGetLastError();
 }
 

@@ -309,13 +309,19 @@ void batch_member_changed(sl_batch* B);
 
 namespace {
 
+// Host bookkeeping of a scalar record read back from the device: the last
+// finite a, and the sticky non-finite flag as SL_E_NONFINITE.
+sl_status apply_scalars(sl_lattice* L, const DevScalars& S) {
+  if (std::isfinite(S.a)) L->a_host = S.a;
+  if (S.status & kStatusNonFinite)
+    return fail(SL_E_NONFINITE, "a lattice sum or the background became non-finite");
+  return SL_OK;
+}
+
 sl_status read_scalars(sl_lattice* L, DevScalars* S) {
   HIP_TRY(hipMemcpyAsync(S, L->v.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, L->stream));
   HIP_TRY(hipStreamSynchronize(L->stream));
-  if (std::isfinite(S->a)) L->a_host = S->a;
-  if (S->status & kStatusNonFinite)
-    return fail(SL_E_NONFINITE, "a lattice sum or the background became non-finite");
-  return SL_OK;
+  return apply_scalars(L, *S);
 }
 
 sl_status require_state(sl_lattice* L) {
@@ -1266,6 +1272,8 @@ struct sl_batch {
   PassParams* pass_dev = nullptr;
   BatchRun* run_dev = nullptr;
   int* start_dev = nullptr;
+  DevScalars* sc_dev = nullptr;        // members' scalars gathered for one read-back
+  std::vector<DevScalars> sc_host;
   int cap = 0;
   bool dirty = true;
   int total_tiles = 0;
@@ -1308,14 +1316,17 @@ sl_status batch_upload(sl_batch* B) {
     if (B->pass_dev) (void)hipFree(B->pass_dev);
     if (B->run_dev) (void)hipFree(B->run_dev);
     if (B->start_dev) (void)hipFree(B->start_dev);
+    if (B->sc_dev) (void)hipFree(B->sc_dev);
     B->pass_dev = nullptr;
     B->run_dev = nullptr;
     B->start_dev = nullptr;
+    B->sc_dev = nullptr;
     int cap = B->cap ? B->cap : 16;
     while (cap < R) cap *= 2;
     if (hipMalloc(&B->pass_dev, sizeof(PassParams) * cap) != hipSuccess ||
         hipMalloc(&B->run_dev, sizeof(BatchRun) * cap) != hipSuccess ||
-        hipMalloc(&B->start_dev, sizeof(int) * (cap + 1)) != hipSuccess) {
+        hipMalloc(&B->start_dev, sizeof(int) * (cap + 1)) != hipSuccess ||
+        hipMalloc(&B->sc_dev, sizeof(DevScalars) * cap) != hipSuccess) {
       B->cap = 0;
       return fail(SL_E_NOMEM, "cannot allocate the batch run table");
     }
@@ -1407,6 +1418,7 @@ sl_status sl_batch_destroy(sl_batch* B) {
   if (B->pass_dev) (void)hipFree(B->pass_dev);
   if (B->run_dev) (void)hipFree(B->run_dev);
   if (B->start_dev) (void)hipFree(B->start_dev);
+  if (B->sc_dev) (void)hipFree(B->sc_dev);
   if (B->ev) (void)hipEventDestroy(B->ev);
   if (B->own_stream) (void)hipStreamDestroy(B->stream);
   delete B;
@@ -1722,12 +1734,26 @@ sl_status sl_batch_step(sl_batch* B, int64_t steps, double dt, int32_t order) {
 sl_status sl_batch_synchronize(sl_batch* B) {
   if (!B) return fail(SL_E_INVALID, "batch handle is NULL");
   HIP_TRY(hipStreamSynchronize(B->stream));
-  for (sl_lattice* L : B->runs) {
-    DevScalars S;
-    sl_status st = read_scalars(L, &S);
+  for (sl_lattice* L : B->runs)
+    if (L->stream != B->stream) HIP_TRY(hipStreamSynchronize(L->stream));
+  if (B->runs.empty()) return SL_OK;
+  if (B->dirty) {
+    const sl_status st = batch_upload(B);
     if (st != SL_OK) return st;
   }
-  return SL_OK;
+  // every member's scalars in one gather and one read-back
+  const int R = int(B->runs.size());
+  B->sc_host.resize(size_t(R));
+  HIP_TRY(launch_gather_scalars(B->run_dev, R, B->sc_dev, B->stream));
+  HIP_TRY(hipMemcpyAsync(B->sc_host.data(), B->sc_dev, sizeof(DevScalars) * R, hipMemcpyDeviceToHost,
+                         B->stream));
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  sl_status first = SL_OK;
+  for (int r = 0; r < R; ++r) {
+    const sl_status st = apply_scalars(B->runs[r], B->sc_host[r]);
+    if (st != SL_OK && first == SL_OK) first = st;
+  }
+  return first;
 }
 
 sl_status sl_device_memory(size_t* free_bytes, size_t* total_bytes) {

@@ -200,3 +200,28 @@ def test_member_autotune_keeps_the_batch_lane_shape():
     b.synchronize()
     assert _same(alone, mixed[1])
     sl.symlat.load().sl_autotune_forget()
+
+
+def test_batch_synchronize_reports_a_nonfinite_member():
+    """A NaN planted in one member's state surfaces as SL_E_NONFINITE at the
+    batch's next synchronisation (one gathered read-back of every member's
+    scalars), while the finite members keep stepping and report their a."""
+    sl.symlat.load().sl_autotune_forget()
+    recipes = _runs("f64", [16, 24, 16])
+    mixed = [sl.from_recipe(r) for r in recipes]
+    phi, pi = mixed[1].get_fields()
+    phi[0, 3, 4, 5] = np.nan
+    eta, a, p_a = mixed[1].background()
+    mixed[1].set_fields(phi, pi, a, p_a)       # explicit p_a: no constraint solve
+    b = sl.Batch()
+    for m in mixed:
+        b.add(m)
+    b.step(3, 0.005, 4)
+    with pytest.raises(sl.SymlatError) as e:
+        b.synchronize()
+    assert e.value.status == 5
+    for j in (0, 2):
+        assert mixed[j].background()[1] > 1.0
+    b.remove(mixed[1])
+    b.step(2, 0.005, 4)
+    b.synchronize()                            # the finite members alone: no error
