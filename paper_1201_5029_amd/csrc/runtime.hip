@@ -207,6 +207,30 @@ size_t partial_doubles() {
   return pass > diag ? pass : diag;
 }
 
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+// A lattice's device memory is two allocations: the four field arrays (each
+// starting on a 256-byte boundary) and the small buffers below, at these
+// offsets inside one block.
+struct AuxLayout {
+  size_t sc, partials, sink, sums, energies, spec, total;
+  AuxLayout() {
+    size_t o = 0;
+    auto take = [&o](size_t bytes) {
+      const size_t at = o;
+      o += round256(bytes);
+      return at;
+    };
+    sc = take(sizeof(DevScalars));
+    partials = take(partial_doubles() * sizeof(double));
+    sink = take(kSinkBytes);
+    sums = take(sizeof(double) * (5 * kMaxFields + 1));
+    energies = take(sizeof(sl_energies_t));
+    spec = take(sizeof(double) * 3 * kMaxBins);
+    total = o;
+  }
+};
+
 // Process-wide caches of tuned pass shapes, shared by every thread of the
 // process: one mutex each, lookups copy the value out.
 struct TuneVal {
@@ -292,6 +316,8 @@ struct sl_lattice {
   sl_energies_t* energies_dev = nullptr;
   double* spec_dev = nullptr;
   double* hist_dev = nullptr;  // per-step background record (sl_set_history)
+  void* fields_mem = nullptr;  // the four field arrays (when the handle owns them)
+  void* aux_mem = nullptr;     // scalars, partial sums, sink, observable buffers
   bool timing = false;
   sl_batch* batch = nullptr;  // batch this lattice belongs to, if any
   int tz_user = 0;  // 0: z-chunk chosen from the occupancy of the pass kernel
@@ -306,6 +332,7 @@ struct sl_lattice {
 };
 
 void batch_member_changed(sl_batch* B);
+hipStream_t batch_stream(const sl_batch* B);
 
 namespace {
 
@@ -362,16 +389,8 @@ void drop_graph(sl_lattice* L) {
 
 void free_all(sl_lattice* L) {
   drop_graph(L);
-  for (int k = 0; k < 2 && L->own_fields; ++k) {
-    if (L->v.phi[k]) (void)hipFree(L->v.phi[k]);
-    if (L->v.pi[k]) (void)hipFree(L->v.pi[k]);
-  }
-  if (L->v.sc) (void)hipFree(L->v.sc);
-  if (L->v.partials) (void)hipFree(L->v.partials);
-  if (L->v.sink) (void)hipFree(L->v.sink);
-  if (L->sums_dev) (void)hipFree(L->sums_dev);
-  if (L->energies_dev) (void)hipFree(L->energies_dev);
-  if (L->spec_dev) (void)hipFree(L->spec_dev);
+  if (L->fields_mem) (void)hipFree(L->fields_mem);
+  if (L->aux_mem) (void)hipFree(L->aux_mem);
   if (L->hist_dev) (void)hipFree(L->hist_dev);
   for (auto& e : L->events) {
     (void)hipEventDestroy(e.first);
@@ -430,9 +449,7 @@ size_t sl_footprint_bytes(const sl_config* cfg) {
   if (!config_ok(cfg, &why)) return 0;
   const size_t n3 = size_t(cfg->n) * cfg->n * cfg->n;
   const size_t elem = cfg->precision == SL_FP32 ? 4 : 8;
-  return 4 * n3 * cfg->nfields * elem + partial_doubles() * sizeof(double) + kSinkBytes + sizeof(DevScalars) +
-         sizeof(double) * (5 * kMaxFields + 1) + sizeof(sl_energies_t) +
-         sizeof(double) * 3 * kMaxBins;
+  return 4 * round256(n3 * cfg->nfields * elem) + AuxLayout().total;
 }
 
 size_t sl_transient_bytes(const sl_config* cfg) {
@@ -567,16 +584,28 @@ sl_status create_impl(const sl_config* cfg, void* hip_stream, void* const* user,
     v.phi[1] = user[2];
     v.pi[1] = user[3];
   }
-  for (int k = 0; k < 2 && ok && !user; ++k) {
-    ok = ok && hipMalloc(&v.phi[k], fbytes) == hipSuccess;
-    ok = ok && hipMalloc(&v.pi[k], fbytes) == hipSuccess;
+  if (!user) {
+    const size_t stride = round256(fbytes);
+    ok = hipMalloc(&L->fields_mem, 4 * stride) == hipSuccess;
+    if (ok) {
+      char* base = static_cast<char*>(L->fields_mem);
+      v.phi[0] = base;
+      v.pi[0] = base + stride;
+      v.phi[1] = base + 2 * stride;
+      v.pi[1] = base + 3 * stride;
+    }
   }
-  ok = ok && hipMalloc(reinterpret_cast<void**>(&v.sc), sizeof(DevScalars)) == hipSuccess;
-  ok = ok && hipMalloc(reinterpret_cast<void**>(&v.partials), L->partials_n * sizeof(double)) == hipSuccess;
-  ok = ok && hipMalloc(&v.sink, kSinkBytes) == hipSuccess;
-  ok = ok && hipMalloc(reinterpret_cast<void**>(&L->sums_dev), sizeof(double) * (5 * kMaxFields + 1)) == hipSuccess;
-  ok = ok && hipMalloc(reinterpret_cast<void**>(&L->energies_dev), sizeof(sl_energies_t)) == hipSuccess;
-  ok = ok && hipMalloc(reinterpret_cast<void**>(&L->spec_dev), sizeof(double) * 3 * kMaxBins) == hipSuccess;
+  const AuxLayout aux;
+  ok = ok && hipMalloc(&L->aux_mem, aux.total) == hipSuccess;
+  if (ok) {
+    char* base = static_cast<char*>(L->aux_mem);
+    v.sc = reinterpret_cast<DevScalars*>(base + aux.sc);
+    v.partials = reinterpret_cast<double*>(base + aux.partials);
+    v.sink = base + aux.sink;
+    L->sums_dev = reinterpret_cast<double*>(base + aux.sums);
+    L->energies_dev = reinterpret_cast<sl_energies_t*>(base + aux.energies);
+    L->spec_dev = reinterpret_cast<double*>(base + aux.spec);
+  }
   if (!ok) {
     free_all(L);
     delete L;
@@ -815,7 +844,8 @@ sl_status sl_set_history(sl_lattice* L, int64_t capacity) {
   if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
   if (capacity < 0 || capacity > (int64_t(1) << 31)) return fail(SL_E_INVALID, "capacity must be in [0, 2^31]");
   // the lattice's stream and, if it is a batch member, the batch's stream
-  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  if (L->batch) HIP_TRY(hipStreamSynchronize(batch_stream(L->batch)));
   DevScalars S;
   HIP_TRY(hipMemcpy(&S, L->v.sc, sizeof S, hipMemcpyDeviceToHost));
   if (L->hist_dev) {
@@ -1294,6 +1324,8 @@ namespace {
 
 // A member's tile or stencil changed: re-upload the run table and capture
 // a new graph at the next step.
+hipStream_t batch_stream(const sl_batch* B) { return B->stream; }
+
 void batch_member_changed(sl_batch* B) {
   B->dirty = true;
   ++B->version;
