@@ -848,6 +848,11 @@ sl_status sl_set_history(sl_lattice* L, int64_t capacity) {
   if (L->batch) HIP_TRY(hipStreamSynchronize(batch_stream(L->batch)));
   DevScalars S;
   HIP_TRY(hipMemcpy(&S, L->v.sc, sizeof S, hipMemcpyDeviceToHost));
+  if (capacity > 0 && L->hist_dev && S.hist == L->hist_dev && S.hist_cap == capacity) {
+    S.hist_n = 0;  // same capacity: restart the record in the same buffer
+    HIP_TRY(hipMemcpy(L->v.sc, &S, sizeof S, hipMemcpyHostToDevice));
+    return SL_OK;
+  }
   if (L->hist_dev) {
     (void)hipFree(L->hist_dev);
     L->hist_dev = nullptr;

@@ -21,12 +21,21 @@ from collections import deque
 
 import numpy as np
 
-from .symlat import Batch, device_memory, footprint_bytes, from_recipe, transient_bytes
+from .symlat import (Batch, device_memory, footprint_bytes, from_recipe, reset_from_recipe,
+                     transient_bytes)
 
 
 # Run kinds the batch tuner has seen in this process; the library gives
 # later lattices of these kinds their tuned shapes when they join a batch.
 _TUNED = set()
+
+
+def _config(recipe):
+    """What a lattice handle is made for: a retired run's handle serves a
+    later request with the same configuration (re-initialised in place)."""
+    return (recipe["n"], recipe["nfields"], recipe["L"], recipe.get("precision", "f64"),
+            recipe.get("expand", True), recipe.get("mpl", 1.0), recipe.get("a0", 1.0),
+            str(recipe.get("stencil")))
 
 
 def _kind(recipe):
@@ -65,12 +74,18 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
     in this process (a run is never retiled once it has stepped; later runs
     of a tuned size start with the tuned shape).
 
+    Handles of retired runs are kept and re-initialised for later requests
+    with the same configuration (no device allocation or release on that
+    path); kept handles count against the memory budget and are released
+    when an admission needs their memory, and all at the end.
+
     results: one dict per request with id, n, arrival, admitted, completed,
     latency (s, completion - arrival), eta, a, p_a, efolds = ln a, the pass
     shape it ran with (tile) and the final fields when keep_fields.  stats:
-    p50/p99 latency, makespan, field site-updates, aggregate
-    field-site-updates/s, admissions deferred for memory, peak resident
-    runs."""
+    p50/p99 latency, makespan (loop start to the last completion), wall_s
+    (the whole call, releases included), field site-updates, aggregate
+    field-site-updates/s over the makespan, admissions deferred for memory,
+    peak resident runs, handles reused."""
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     waiting = deque()
     active = {}  # id -> [request, lattice, steps_done, admitted_at]
@@ -78,9 +93,13 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
     if hbm_budget is None:
         free, _ = device_memory()
         hbm_budget = int(0.9 * free)
-    used = 0
+    used = 0        # resident runs
     deferred = 0
     peak = 0
+    reused = 0
+    pool = {}       # configuration -> [(lattice, bytes)] of retired runs
+    pooled = 0      # bytes held by kept handles
+    last_done = 0.0
     batch = Batch()
     tuned = not tune
     t0 = clock()
@@ -99,11 +118,27 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
                     raise ValueError("request %r needs %d bytes, more than the budget %d"
                                      % (req.id, need + req.transient, hbm_budget))
                 reserve = max([req.transient] + [a[0].transient for a in active.values()])
-                if used + need + reserve > hbm_budget:
-                    deferred += 1
-                    break
+                spare = pool.get(_config(req.recipe))
+                if spare:
+                    if used + pooled - spare[-1][1] + need + reserve > hbm_budget:
+                        deferred += 1
+                        break
+                    lat, b = spare.pop()
+                    pooled -= b
+                    reset_from_recipe(lat, req.recipe)
+                    reused += 1
+                else:
+                    # release kept handles of other configurations while short of memory
+                    while used + pooled + need + reserve > hbm_budget and pooled > 0:
+                        key = max((k for k in pool if pool[k]), key=lambda k: pool[k][-1][1])
+                        old, b = pool[key].pop()
+                        old.close()
+                        pooled -= b
+                    if used + pooled + need + reserve > hbm_budget:
+                        deferred += 1
+                        break
+                    lat = from_recipe(req.recipe)
                 waiting.popleft()
-                lat = from_recipe(req.recipe)
                 if history:
                     lat.set_history(req.steps)
                 batch.add(lat)
@@ -139,21 +174,29 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
                     if history:
                         res["history"] = lat.history()
                     results.append(res)
+                    last_done = done_at
                     batch.remove(lat)
-                    lat.close()
-                    used -= _resident_bytes(req, history)
+                    b = _resident_bytes(req, history)
+                    pool.setdefault(_config(req.recipe), []).append((lat, b))
+                    used -= b
+                    pooled += b
                     del active[rid]
     finally:
         for entry in active.values():
             entry[1].close()
+        for kept in pool.values():
+            for lat, _ in kept:
+                lat.close()
         batch.close()
-    makespan = clock() - t0
+    wall = clock() - t0
+    makespan = last_done if results else wall
     lat_s = np.array([r["latency"] for r in results]) if results else np.zeros(1)
     sups = sum(r["n"] ** 3 * req_nf(requests, r["id"]) * r["steps"] for r in results)
     stats = dict(p50_s=float(np.percentile(lat_s, 50)), p99_s=float(np.percentile(lat_s, 99)),
-                 makespan_s=makespan, field_site_updates=sups,
+                 makespan_s=makespan, wall_s=wall, field_site_updates=sups,
                  field_site_updates_per_s=sups / makespan if makespan > 0 else float("nan"),
-                 deferred_for_memory=deferred, peak_resident=peak, runs=len(results))
+                 deferred_for_memory=deferred, peak_resident=peak, runs=len(results),
+                 reused=reused)
     return sorted(results, key=lambda r: r["id"]), stats
 
 

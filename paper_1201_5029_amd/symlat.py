@@ -503,6 +503,16 @@ class Linear:
             pass
 
 
+def reset_from_recipe(lat, r):
+    """Re-initialise a lattice made for the recipe's configuration (size,
+    fields, box, precision, expansion, m_pl, a0, stencil) for a new run of
+    it: the potential and the initial state exactly as from_recipe sets
+    them, the pass shape kept."""
+    lat.set_potential(r["potential"], r["params"])
+    lat.init_fluctuations(r["phi0"], r["pi0"], r["fluct"], r["amplitude"], r["seed"])
+    return lat
+
+
 def from_recipe(r, stream=None):
     """Lattice with potential set and initial state drawn from a workload
     recipe dict (see the synth module)."""

@@ -9,10 +9,21 @@ from paper_1201_5029_amd import serve
 
 
 class FakeLattice:
+    made = []
+
     def __init__(self, recipe):
         self.recipe = recipe
         self.steps = 0
         self.closed = False
+        self.inits = 1
+        FakeLattice.made.append(self)
+
+    def reset(self, recipe):
+        assert not self.closed
+        self.recipe = recipe
+        self.steps = 0
+        self.inits += 1
+        return self
 
     def background(self):
         return 0.01 * self.steps, 1.0 + 0.001 * self.steps, -1.0
@@ -87,6 +98,8 @@ def fake(monkeypatch):
 
     monkeypatch.setattr(serve, "Batch", TimedBatch)
     monkeypatch.setattr(serve, "from_recipe", FakeLattice)
+    monkeypatch.setattr(serve, "reset_from_recipe", lambda lat, r: lat.reset(r))
+    FakeLattice.made = []
     monkeypatch.setattr(serve, "footprint_bytes", lambda **kw: 100 * kw["n"])
     monkeypatch.setattr(serve, "transient_bytes", lambda **kw: 10 * kw["n"])
     serve._TUNED.clear()
@@ -145,6 +158,38 @@ def test_history_counts_in_the_footprint(fake):
     res, st = serve.serve(reqs, 0.005, 4, max_slots=4, tick_steps=50, hbm_budget=budget,
                           history=True, clock=fake, sleep=fake.sleep)
     assert st["peak_resident"] == 1 and st["runs"] == 2
+
+
+def test_retired_handles_serve_later_requests(fake):
+    """With two slots, five requests of one configuration need only two
+    handles: retired ones are re-initialised for the next request; every
+    handle is released by the end; the makespan ends at the last completion."""
+    reqs = [_req(i, 32, 0.0, 20) for i in range(5)]
+    res, st = serve.serve(reqs, 0.005, 4, max_slots=2, tick_steps=20, hbm_budget=10 ** 9,
+                          clock=fake, sleep=fake.sleep)
+    assert st["runs"] == 5 and st["reused"] == 3 and len(FakeLattice.made) == 2
+    assert sum(m.inits for m in FakeLattice.made) == 5
+    assert all(m.closed for m in FakeLattice.made)
+    assert all(r["efolds"] == pytest.approx(math.log(1.0 + 0.001 * 20)) for r in res)
+    assert st["makespan_s"] == max(r["completed"] for r in res) <= st["wall_s"]
+
+
+def test_kept_handles_are_released_for_memory(fake):
+    """A kept handle of another configuration is released when a new
+    request needs its memory; one of the same configuration is reused."""
+    big, small = _req(0, 128, 0.0, 10), _req(1, 16, 0.0, 10)
+    budget = 100 * 128 + 10 * 128                  # one big run, or one small one
+    res, st = serve.serve([big, small], 0.005, 4, max_slots=4, tick_steps=10,
+                          hbm_budget=budget, clock=fake, sleep=fake.sleep)
+    assert st["runs"] == 2 and st["reused"] == 0 and st["peak_resident"] == 1
+    first = FakeLattice.made[0]
+    assert first.recipe["n"] == 128 and first.closed
+    # same configuration again: the kept handle serves it
+    FakeLattice.made = []
+    res, st = serve.serve([_req(0, 16, 0.0, 10), _req(1, 16, 0.05, 10)], 0.005, 4,
+                          max_slots=4, tick_steps=10, hbm_budget=budget, clock=fake,
+                          sleep=fake.sleep)
+    assert st["reused"] == 1 and len(FakeLattice.made) == 1
 
 
 def test_late_arrivals_join_and_latency(fake):
