@@ -146,3 +146,36 @@ def test_largest_side_fp32_white():
     assert e["friedmann_residual"] < 1e-3
     assert e["a"] > a0 and e["p_a"] < 0 and e["eta"] == pytest.approx(0.01)
     lat.close()
+
+
+def test_deltan96_batch_fullsize_sampled():
+    """The Delta-N ensemble at its full size (96 runs, n in {32, 64, 96},
+    FP32, 4th order) as one batch in the shapes the batch tuner picks, as
+    the benchmark runs it: sampled members equal the same runs advanced
+    alone with the recorded shape, bit for bit, and the background of every
+    member grows."""
+    recipes = synth.delta_n_scan(nruns=96, steps=30)
+    lats = [sl.from_recipe(r) for r in recipes]
+    b = sl.Batch()
+    for lat in lats:
+        b.add(lat)
+    b.autotune(reps=2)
+    a0 = [lat.background()[1] for lat in lats]
+    b.step(30, recipes[0]["dt"], recipes[0]["order"])
+    b.synchronize()
+    assert all(lat.background()[1] > a for lat, a in zip(lats, a0))
+    for j in (0, 17, 41, 64, 80, 95):          # every size is among them
+        r = recipes[j]
+        alone = sl.from_recipe(r)
+        tx, vx, _, tz, pf = lats[j].tile()
+        alone.set_tile(tx, vx, tz, pf)
+        alone.evolve(30, r["dt"], r["order"])
+        fa, pa = alone.get_fields()
+        fb, pb = lats[j].get_fields()
+        say("delta-N member", j, r["n"], lats[j].tile())
+        assert np.array_equal(fa, fb) and np.array_equal(pa, pb), j
+        assert alone.background() == lats[j].background()
+        alone.close()
+    b.close()
+    for lat in lats:
+        lat.close()
