@@ -150,6 +150,11 @@ def _check(status):
 
 
 def _dvec(values, n):
+    """n doubles for the C side; a length other than n is refused here, since
+    the library reads exactly n values."""
+    values = list(values)
+    if len(values) != n:
+        raise ValueError("expected %d values, got %d" % (n, len(values)))
     arr = (ctypes.c_double * max(n, 1))()
     for i, v in enumerate(values):
         arr[i] = float(v)

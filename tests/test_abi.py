@@ -103,3 +103,13 @@ def test_null_handles_are_rejected():
     assert b"NULL" in lib.sl_last_error()
     out = ctypes.c_void_p()
     assert lib.sl_lattice_create(None, None, ctypes.byref(out)) == binding.SL_E_INVALID
+
+
+def test_vectors_of_the_wrong_length_are_refused_before_the_call():
+    """The library reads exactly nfields (or nparams, or 4) doubles: the
+    binding refuses other lengths instead of padding or truncating."""
+    with pytest.raises(ValueError):
+        binding._dvec([1.0], 2)
+    with pytest.raises(ValueError):
+        binding._dvec([1.0, 2.0, 3.0], 2)
+    assert list(binding._dvec([1.0, 2.0], 2)) == [1.0, 2.0]
