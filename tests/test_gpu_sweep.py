@@ -64,3 +64,27 @@ def test_sweep(case):
     say("  errors", ef, ep, ea, epa)
     assert max(ef, ep, ea, epa) <= FP64_TOL
     g.close()
+
+
+@pytest.mark.parametrize("case", range(0, len(CASES), 3))
+def test_sweep_fp32_storage(case):
+    """Every third case with FP32 field storage: relative L2 error of the
+    fields and momenta within the FP32 gate (1e-4)."""
+    from gpu_util import rel_l2
+    kind, params, base, mpl, n, stencil, tile = CASES[case]
+    nf = len(base)
+    L = 0.5 * n
+    scale = max(abs(b) for b in base)
+    phi, pi = synth.gaussian_state(n, nf, 9000 + case, phi_base=list(base),
+                                   phi_amp=1e-3 * scale, pi_amp=1e-3 * scale)
+    o = oracle_lattice(n, L, kind, params, phi, pi, mpl=mpl,
+                       stencil=oracle.STENCIL_27 if stencil else None)
+    g = gpu_lattice(n, L, kind, params, phi, pi, precision="f32", mpl=mpl, tile=tile,
+                    stencil=stencil)
+    g.evolve(5, 0.005, 4)
+    o.evolve(5, 0.005, 4)
+    gphi, gpi = g.get_fields()
+    e1, e2 = rel_l2(gphi, o.phi), rel_l2(gpi, o.pi)
+    say("sweep fp32 case", case, kind, n, stencil or "7", g.tile(), e1, e2)
+    assert max(e1, e2) <= 1e-4
+    g.close()
