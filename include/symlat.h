@@ -135,7 +135,9 @@ sl_status sl_lattice_create(const sl_config* cfg, void* hip_stream, sl_lattice**
 /* As sl_lattice_create, but the handle adopts the caller's four field
  * arrays instead of allocating them: phi0, pi0 (buffer 0) and phi1, pi1
  * (buffer 1), each nfields * n^3 elements of the storage precision in the
- * [field][z][y][x] layout, in device memory of the current device (hipMalloc
+ * device layout [z][field][y][x] (the fields of each z-plane one after the
+ * other: element (i, z, y, x) at ((z*nfields + i)*n + y)*n + x; host arrays
+ * keep [field][z][y][x]), in device memory of the current device (hipMalloc
  * or a pool carved from it), 16-byte aligned and not overlapping.  The
  * handle zero-fills them at creation, uses them until sl_lattice_destroy and
  * never frees them; the caller keeps them alive that long and touches them

@@ -56,6 +56,13 @@ __device__ __forceinline__ KSum wave_reduce(KSum v) {
   return v;
 }
 
+// Field arrays hold the fields of each z-plane one after the other
+// ([z][field][y][x], x fastest): site e = (z n + y) n + x of field i of nf.
+__device__ __forceinline__ size_t field_site(int i, size_t e, int nf, size_t n2) {
+  const size_t z = e / n2;
+  return (z * size_t(nf) + size_t(i)) * n2 + (e - z * n2);
+}
+
 // Reduce NV pairs over a 256-thread workgroup; thread 0 gets the result.
 // scratch: 4 * NV KSum of LDS.  Contains barriers: all threads must call.
 template <int NV>

@@ -32,8 +32,8 @@ constexpr int nsums() { return 5 * NF + 1; }
 // stencil: the 26 neighbours weighted by class (face, edge, corner).
 template <typename T>
 __device__ void stencil27_at(const T* __restrict__ phi, const T* __restrict__ pi, double c,
-                             size_t o, int n, int x, int y, int z, double f, const Stencil& st,
-                             double& D, double& G) {
+                             int i, int nf, int n, int x, int y, int z, double f,
+                             const Stencil& st, double& D, double& G) {
   const size_t n2 = size_t(n) * n;
   double acc[4] = {0.0, 0.0, 0.0, 0.0}, g[4] = {0.0, 0.0, 0.0, 0.0};
   for (int dz = -1; dz <= 1; ++dz) {
@@ -44,7 +44,7 @@ __device__ void stencil27_at(const T* __restrict__ phi, const T* __restrict__ pi
         const int cls = (dz != 0) + (dy != 0) + (dx != 0);
         if (cls == 0) continue;
         const int xx = x + dx < 0 ? n - 1 : (x + dx >= n ? 0 : x + dx);
-        const size_t e = o + size_t(zz) * n2 + size_t(yy) * n + xx;
+        const size_t e = (size_t(zz) * nf + i) * n2 + size_t(yy) * n + xx;
         const double v = fma(c, double(pi[e]), double(phi[e]));
         acc[cls] += v;
         const double d = v - f;
@@ -71,9 +71,10 @@ __global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScala
   for (int i = 0; i < kMaxFields; ++i) pot.p[i] = prm.p[i];
   const size_t n2 = size_t(n) * n, n3 = n2 * n;
 
+  // arrays are [z][field][y][x]: field i of plane z starts at (z NF + i) n^2
   double shift[NF];
 #pragma unroll
-  for (int i = 0; i < NF; ++i) shift[i] = fma(c, double(pi[i * n3]), double(phi[i * n3]));
+  for (int i = 0; i < NF; ++i) shift[i] = fma(c, double(pi[i * n2]), double(phi[i * n2]));
 
   KSum acc[NV];
 #pragma unroll
@@ -84,24 +85,28 @@ __global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScala
     const int x = int(e % n);
     const int y = int((e / n) % n);
     const int z = int(e / n2);
-    const size_t xm = e - x + (x == 0 ? n - 1 : x - 1), xp = e - x + (x == n - 1 ? 0 : x + 1);
-    const size_t ym = e + (size_t((y == 0 ? n - 1 : y - 1)) - y) * n;
-    const size_t yp = e + (size_t((y == n - 1 ? 0 : y + 1)) - y) * n;
-    const size_t zm = e + (size_t((z == 0 ? n - 1 : z - 1)) - z) * n2;
-    const size_t zp = e + (size_t((z == n - 1 ? 0 : z + 1)) - z) * n2;
+    const size_t r = e - size_t(z) * n2;  // y n + x
+    const size_t zm = size_t(z == 0 ? n - 1 : z - 1), zp = size_t(z == n - 1 ? 0 : z + 1);
+    // neighbours as (plane, in-plane index)
+    const size_t nz[6] = {size_t(z), size_t(z), size_t(z), size_t(z), zm, zp};
+    const size_t nr[6] = {r - x + (x == 0 ? n - 1 : x - 1), r - x + (x == n - 1 ? 0 : x + 1),
+                          r + (size_t((y == 0 ? n - 1 : y - 1)) - y) * n,
+                          r + (size_t((y == n - 1 ? 0 : y + 1)) - y) * n, r, r};
     double f[NF];
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      const size_t o = i * n3;
-      const double pc = double(pi[o + e]);
-      const double fcv = fma(c, pc, double(phi[o + e]));
+      const size_t o = (size_t(z) * NF + i) * n2 + r;
+      const double pc = double(pi[o]);
+      const double fcv = fma(c, pc, double(phi[o]));
       f[i] = fcv;
       double D, G;
       if (st.kind == 0) {
         double nb[6];
-        const size_t idx[6] = {xm, xp, ym, yp, zm, zp};
 #pragma unroll
-        for (int q = 0; q < 6; ++q) nb[q] = fma(c, double(pi[o + idx[q]]), double(phi[o + idx[q]]));
+        for (int q = 0; q < 6; ++q) {
+          const size_t on = (nz[q] * NF + i) * n2 + nr[q];
+          nb[q] = fma(c, double(pi[on]), double(phi[on]));
+        }
         D = -6.0 * fcv;
         G = 0.0;
 #pragma unroll
@@ -112,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScala
         }
         G = 0.5 * G;
       } else {
-        stencil27_at<T>(phi, pi, c, o, n, x, y, z, fcv, st, D, G);
+        stencil27_at<T>(phi, pi, c, i, NF, n, x, y, z, fcv, st, D, G);
       }
       kadd(acc[5 * i + 0], pc * pc);
       kadd(acc[5 * i + 1], G);
@@ -161,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void energies_finalize(const double* partia
     s[k] = v[k].s + v[k].c;
     sums_out[k] = s[k];
   }
-  const size_t n3 = size_t(n) * n * n;
+  const size_t n2 = size_t(n) * n;
   const double VL = K.VL;
   const double a = S.a;
   const double a2 = a * a, a4 = a2 * a2, a6 = a4 * a2;
@@ -175,11 +180,11 @@ __global__ __launch_bounds__(kBlock) void energies_finalize(const double* partia
     if (prec == SL_FP32) {
       const float* ph = static_cast<const float*>(B.phi[par]);
       const float* pp = static_cast<const float*>(B.pi[par]);
-      sh = fma(S.c_pend, double(pp[i * n3]), double(ph[i * n3]));
+      sh = fma(S.c_pend, double(pp[i * n2]), double(ph[i * n2]));
     } else {
       const double* ph = static_cast<const double*>(B.phi[par]);
       const double* pp = static_cast<const double*>(B.pi[par]);
-      sh = fma(S.c_pend, pp[i * n3], ph[i * n3]);
+      sh = fma(S.c_pend, pp[i * n2], ph[i * n2]);
     }
     E.kin[i] = (s[5 * i] / VL) / (2.0 * a6);
     E.grad[i] = (s[5 * i + 1] / VL) / (2.0 * a2 * K.dx2);
@@ -299,30 +304,42 @@ __global__ __launch_bounds__(kBlock) void sum_pi2_finalize(const double* partial
   }
 }
 
+// Device index of host element e: the host arrays are [field][z][y][x], the
+// device arrays [z][field][y][x].
+__device__ __forceinline__ size_t device_index(size_t e, int nf, size_t n2, size_t n3) {
+  const size_t i = e / n3, s = e - i * n3;
+  const size_t z = s / n2;
+  return (z * nf + i) * n2 + (s - z * n2);
+}
+
 template <typename T>
-__global__ void export_kernel(Bufs B, const DevScalars* sc, size_t count, double* phi_out,
-                              double* pi_out) {
+__global__ void export_kernel(Bufs B, const DevScalars* sc, size_t count, int nf, size_t n2,
+                              double* phi_out, double* pi_out) {
   const int par = sc->parity;
   const T* __restrict__ phi = static_cast<const T*>(B.phi[par]);
   const T* __restrict__ pi = static_cast<const T*>(B.pi[par]);
   const double c = sc->c_pend;
+  const size_t n3 = count / nf;
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += stride) {
-    const double p = double(pi[e]);
-    if (phi_out) phi_out[e] = fma(c, p, double(phi[e]));
+    const size_t d = device_index(e, nf, n2, n3);
+    const double p = double(pi[d]);
+    if (phi_out) phi_out[e] = fma(c, p, double(phi[d]));
     if (pi_out) pi_out[e] = p;
   }
 }
 
 template <typename T>
-__global__ void import_kernel(void* phi0, void* pi0, size_t count, const double* phi_in,
-                              const double* pi_in) {
+__global__ void import_kernel(void* phi0, void* pi0, size_t count, int nf, size_t n2,
+                              const double* phi_in, const double* pi_in) {
   T* __restrict__ phi = static_cast<T*>(phi0);
   T* __restrict__ pi = static_cast<T*>(pi0);
+  const size_t n3 = count / nf;
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += stride) {
-    phi[e] = static_cast<T>(phi_in[e]);
-    pi[e] = static_cast<T>(pi_in[e]);
+    const size_t d = device_index(e, nf, n2, n3);
+    phi[d] = static_cast<T>(phi_in[e]);
+    pi[d] = static_cast<T>(pi_in[e]);
   }
 }
 
@@ -389,10 +406,10 @@ hipError_t launch_export(const LatView& v, double* phi_out, double* pi_out, hipS
   const Bufs B = bufs_of(v);
   if (v.prec == SL_FP32)
     hipLaunchKernelGGL(export_kernel<float>, dim3(grid_for(count)), dim3(kBlock), 0, s, B, v.sc,
-                       count, phi_out, pi_out);
+                       count, v.nf, size_t(v.n) * v.n, phi_out, pi_out);
   else
     hipLaunchKernelGGL(export_kernel<double>, dim3(grid_for(count)), dim3(kBlock), 0, s, B, v.sc,
-                       count, phi_out, pi_out);
+                       count, v.nf, size_t(v.n) * v.n, phi_out, pi_out);
   return hipGetLastError();
 }
 
@@ -401,10 +418,10 @@ hipError_t launch_import(const LatView& v, const double* phi_in, const double* p
   const size_t count = size_t(v.nf) * v.n * v.n * v.n;
   if (v.prec == SL_FP32)
     hipLaunchKernelGGL(import_kernel<float>, dim3(grid_for(count)), dim3(kBlock), 0, s, v.phi[0],
-                       v.pi[0], count, phi_in, pi_in);
+                       v.pi[0], count, v.nf, size_t(v.n) * v.n, phi_in, pi_in);
   else
     hipLaunchKernelGGL(import_kernel<double>, dim3(grid_for(count)), dim3(kBlock), 0, s, v.phi[0],
-                       v.pi[0], count, phi_in, pi_in);
+                       v.pi[0], count, v.nf, size_t(v.n) * v.n, phi_in, pi_in);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(reset_scalars_kernel, dim3(1), dim3(64), 0, s, v.sc, a, p_a);

@@ -17,9 +17,10 @@
 // sum pi'^2 (for the H2 kicks of p_a).  The global sums make every stage a
 // grid-wide dependency, so a stage is one pass plus one small finalize.
 //
-// Data layout: phi and pi are [field][z][y][x] (x fastest) in two ping-pong
-// buffers; the pass reads buffer `parity` and writes the other one, so no
-// tile ever reads a value another tile has already advanced.
+// Data layout: phi and pi are [z][field][y][x] (x fastest; the fields of one
+// plane one after the other) in two ping-pong buffers; the pass reads buffer
+// `parity` and writes the other one, so no tile ever reads a value another
+// tile has already advanced.
 //
 // Tiling: a 256-thread workgroup owns a TX x TY column tile (TX lanes of a
 // wavefront along x, coalesced) and marches up TZ planes in z.  Each thread
@@ -115,7 +116,6 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
 
   const int n = P.n;
   const size_t n2 = size_t(n) * n;
-  const size_t n3 = n2 * n;
 
   // tile of this workgroup (x tiles fastest, then y, then z chunks)
   int b = tile_id;
@@ -174,7 +174,7 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
   auto load_own = [&](int zz) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      const size_t o = i * n3 + size_t(zz) * n2 + col;
+      const size_t o = (size_t(zz) * NF + i) * n2 + col;
       const Vec<T, VX> u = ldv<T, VX>(phi_in + o), w = ldv<T, VX>(pi_in + o);
 #pragma unroll
       for (int v = 0; v < VX; ++v) {
@@ -186,7 +186,7 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
   auto load_halo = [&](int zz) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      const size_t o = i * n3 + size_t(zz) * n2 + hcol;
+      const size_t o = (size_t(zz) * NF + i) * n2 + hcol;
       const Vec<T, VX> u = ldv<T, VX>(phi_in + o), w = ldv<T, VX>(pi_in + o);
 #pragma unroll
       for (int v = 0; v < VX; ++v) {
@@ -295,11 +295,11 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
         }
         vs += double(V);
       }
-      const size_t oc = size_t(z) * n2 + col;
 #pragma unroll
       for (int i = 0; i < NF; ++i) {
-        T* po = active ? phi_out + i * n3 + oc : sink + (2 * i) * VX;
-        T* qo = active ? pi_out + i * n3 + oc : sink + (2 * i + 1) * VX;
+        const size_t oc = (size_t(z) * NF + i) * n2 + col;
+        T* po = active ? phi_out + oc : sink + (2 * i) * VX;
+        T* qo = active ? pi_out + oc : sink + (2 * i + 1) * VX;
         stv<T, VX>(po, fc[i]);
         stv<T, VX>(qo, pn[i]);
       }
@@ -365,7 +365,6 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T*
 
   const int n = P.n;
   const size_t n2 = size_t(n) * n;
-  const size_t n3 = n2 * n;
 
   int b = tile_id;
   const int xt = b % P.ntx;
@@ -432,7 +431,7 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T*
   auto load_plane = [&](int zz) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      const size_t o = i * n3 + size_t(zz) * n2;
+      const size_t o = (size_t(zz) * NF + i) * n2;
       const Vec<T, VX> u = ldv<T, VX>(phi_in + o + col), w = ldv<T, VX>(pi_in + o + col);
       const Vec<T, VX> hu = ldv<T, VX>(phi_in + o + hcol), hw = ldv<T, VX>(pi_in + o + hcol);
 #pragma unroll
@@ -513,11 +512,12 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T*
         }
         vs += double(V);
       }
-      const size_t oc = size_t(wrapz(p - 1)) * n2 + col;
+      const size_t zo = size_t(wrapz(p - 1));
 #pragma unroll
       for (int i = 0; i < NF; ++i) {
-        T* po = out ? phi_out + i * n3 + oc : sink + (2 * i) * VX;
-        T* qo = out ? pi_out + i * n3 + oc : sink + (2 * i + 1) * VX;
+        const size_t oc = (zo * NF + i) * n2 + col;
+        T* po = out ? phi_out + oc : sink + (2 * i) * VX;
+        T* qo = out ? pi_out + oc : sink + (2 * i + 1) * VX;
         stv<T, VX>(po, fB[i]);
         stv<T, VX>(qo, pn[i]);
       }

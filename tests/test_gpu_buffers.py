@@ -61,7 +61,8 @@ def test_caller_buffers_equal_owned(precision):
         pis = []
         for k in (1, 3):
             assert hip.hipMemcpy(host.ctypes.data, bufs[k], nbytes, 2) == 0
-            pis.append(host.copy().reshape(pe.shape))
+            # device layout [z][field][y][x] -> [field][z][y][x]
+            pis.append(host.copy().reshape(n, nf, n, n).transpose(1, 0, 2, 3))
         assert any(np.array_equal(x.astype(np.float64), pe) for x in pis)
         ext.close()
         own.close()
