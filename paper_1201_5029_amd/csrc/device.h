@@ -56,11 +56,12 @@ __device__ __forceinline__ KSum wave_reduce(KSum v) {
   return v;
 }
 
-// Field arrays hold the fields of each z-plane one after the other
-// ([z][field][y][x], x fastest): site e = (z n + y) n + x of field i of nf.
-__device__ __forceinline__ size_t field_site(int i, size_t e, int nf, size_t n2) {
+// Offset of site e = (z n + y) n + x of field i in a field array whose
+// planes are zs n^2 elements apart (the fields of a plane one after the
+// other, x fastest).
+__device__ __forceinline__ size_t field_site(int i, size_t e, int zs, size_t n2) {
   const size_t z = e / n2;
-  return (z * size_t(nf) + size_t(i)) * n2 + (e - z * n2);
+  return (z * size_t(zs) + size_t(i)) * n2 + (e - z * n2);
 }
 
 // Reduce NV pairs over a 256-thread workgroup; thread 0 gets the result.

@@ -119,6 +119,7 @@ struct PassParams {
   int n;
   int tx, logtx, ty, tz;  // lanes in x, log2(lanes), rows, planes per chunk
   int ntx, nty, ntz;
+  int zs;  // plane stride of the field arrays, in planes (LatView::zs)
 };
 
 // One run of a batch for the finalize / begin kernels.
@@ -138,6 +139,11 @@ struct LatView {
   double* partials;      // per-block (sum, compensation) pairs
   void* sink;            // kSinkBytes of store slots for idle lanes of the pass
   int n, nf, prec, pot;  // prec: sl_precision, pot: sl_potential
+  // Field layout: element (field i, plane z, in-plane r = y n + x) of a phi or
+  // pi array is at (z zs + i) n^2 + r.  zs = nf: the fields of a plane one
+  // after the other; zs = 2 nf: phi and pi of one parity share a block, the
+  // pi planes of z following its phi planes (pi[k] = phi[k] + nf n^2).
+  int zs;
   PotArgs prm;
   BgConsts bg;
   Tile tile;

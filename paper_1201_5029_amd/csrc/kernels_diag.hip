@@ -32,7 +32,7 @@ constexpr int nsums() { return 5 * NF + 1; }
 // stencil: the 26 neighbours weighted by class (face, edge, corner).
 template <typename T>
 __device__ void stencil27_at(const T* __restrict__ phi, const T* __restrict__ pi, double c,
-                             int i, int nf, int n, int x, int y, int z, double f,
+                             int i, int zs, int n, int x, int y, int z, double f,
                              const Stencil& st, double& D, double& G) {
   const size_t n2 = size_t(n) * n;
   double acc[4] = {0.0, 0.0, 0.0, 0.0}, g[4] = {0.0, 0.0, 0.0, 0.0};
@@ -44,7 +44,7 @@ __device__ void stencil27_at(const T* __restrict__ phi, const T* __restrict__ pi
         const int cls = (dz != 0) + (dy != 0) + (dx != 0);
         if (cls == 0) continue;
         const int xx = x + dx < 0 ? n - 1 : (x + dx >= n ? 0 : x + dx);
-        const size_t e = (size_t(zz) * nf + i) * n2 + size_t(yy) * n + xx;
+        const size_t e = (size_t(zz) * zs + i) * n2 + size_t(yy) * n + xx;
         const double v = fma(c, double(pi[e]), double(phi[e]));
         acc[cls] += v;
         const double d = v - f;
@@ -58,7 +58,7 @@ __device__ void stencil27_at(const T* __restrict__ phi, const T* __restrict__ pi
 
 template <typename T, int NF, int KIND>
 __global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScalars* sc,
-                                                         PotArgs prm, int n, Stencil st,
+                                                         PotArgs prm, int n, int zs, Stencil st,
                                                          double* partials) {
   constexpr int NV = nsums<NF>();
   __shared__ KSum scratch[4 * NV];
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScala
   for (int i = 0; i < kMaxFields; ++i) pot.p[i] = prm.p[i];
   const size_t n2 = size_t(n) * n, n3 = n2 * n;
 
-  // arrays are [z][field][y][x]: field i of plane z starts at (z NF + i) n^2
+  // field i of plane z starts at (z zs + i) n^2
   double shift[NF];
 #pragma unroll
   for (int i = 0; i < NF; ++i) shift[i] = fma(c, double(pi[i * n2]), double(phi[i * n2]));
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScala
     double f[NF];
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      const size_t o = (size_t(z) * NF + i) * n2 + r;
+      const size_t o = (size_t(z) * zs + i) * n2 + r;
       const double pc = double(pi[o]);
       const double fcv = fma(c, pc, double(phi[o]));
       f[i] = fcv;
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScala
         double nb[6];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-          const size_t on = (nz[q] * NF + i) * n2 + nr[q];
+          const size_t on = (nz[q] * zs + i) * n2 + nr[q];
           nb[q] = fma(c, double(pi[on]), double(phi[on]));
         }
         D = -6.0 * fcv;
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScala
         }
         G = 0.5 * G;
       } else {
-        stencil27_at<T>(phi, pi, c, i, NF, n, x, y, z, fcv, st, D, G);
+        stencil27_at<T>(phi, pi, c, i, zs, n, x, y, z, fcv, st, D, G);
       }
       kadd(acc[5 * i + 0], pc * pc);
       kadd(acc[5 * i + 1], G);
@@ -242,7 +242,7 @@ hipError_t energies_t(const LatView& v, double* sums, sl_energies_t* out, int mo
   int nb = int((n3 + kBlock - 1) / kBlock);
   if (nb > kDiagBlocksMax) nb = kDiagBlocksMax;
   hipLaunchKernelGGL((energies_kernel<T, NF, KIND>), dim3(nb), dim3(kBlock), 0, s, B, v.sc,
-                     v.prm, v.n, v.st, v.partials);
+                     v.prm, v.n, v.zs, v.st, v.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((energies_finalize<NF>), dim3(1), dim3(kBlock), 0, s, v.partials, nb, v.sc,
@@ -274,13 +274,15 @@ hipError_t energies_dispatch(const LatView& v, double* sums, sl_energies_t* out,
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void sum_pi2_kernel(Bufs B, const DevScalars* sc,
-                                                        size_t count, double* partials) {
+                                                        size_t count, size_t n3, size_t n2, int zs,
+                                                        double* partials) {
   __shared__ KSum scratch[4];
   const T* __restrict__ pi = static_cast<const T*>(B.pi[sc->parity]);
   KSum acc[1] = {{0.0, 0.0}};
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += stride) {
-    const double p = double(pi[e]);
+    const size_t i = e / n3;  // field i, site e - i n^3
+    const double p = double(pi[field_site(int(i), e - i * n3, zs, n2)]);
     kadd(acc[0], p * p);
   }
   block_reduce<1>(acc, scratch);
@@ -304,17 +306,15 @@ __global__ __launch_bounds__(kBlock) void sum_pi2_finalize(const double* partial
   }
 }
 
-// Device index of host element e: the host arrays are [field][z][y][x], the
-// device arrays [z][field][y][x].
-__device__ __forceinline__ size_t device_index(size_t e, int nf, size_t n2, size_t n3) {
-  const size_t i = e / n3, s = e - i * n3;
-  const size_t z = s / n2;
-  return (z * nf + i) * n2 + (s - z * n2);
+// Device offset of host element e: the host arrays are [field][z][y][x].
+__device__ __forceinline__ size_t device_index(size_t e, int zs, size_t n2, size_t n3) {
+  const size_t i = e / n3;
+  return field_site(int(i), e - i * n3, zs, n2);
 }
 
 template <typename T>
-__global__ void export_kernel(Bufs B, const DevScalars* sc, size_t count, int nf, size_t n2,
-                              double* phi_out, double* pi_out) {
+__global__ void export_kernel(Bufs B, const DevScalars* sc, size_t count, int nf, int zs,
+                              size_t n2, double* phi_out, double* pi_out) {
   const int par = sc->parity;
   const T* __restrict__ phi = static_cast<const T*>(B.phi[par]);
   const T* __restrict__ pi = static_cast<const T*>(B.pi[par]);
@@ -322,7 +322,7 @@ __global__ void export_kernel(Bufs B, const DevScalars* sc, size_t count, int nf
   const size_t n3 = count / nf;
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += stride) {
-    const size_t d = device_index(e, nf, n2, n3);
+    const size_t d = device_index(e, zs, n2, n3);
     const double p = double(pi[d]);
     if (phi_out) phi_out[e] = fma(c, p, double(phi[d]));
     if (pi_out) pi_out[e] = p;
@@ -330,14 +330,14 @@ __global__ void export_kernel(Bufs B, const DevScalars* sc, size_t count, int nf
 }
 
 template <typename T>
-__global__ void import_kernel(void* phi0, void* pi0, size_t count, int nf, size_t n2,
+__global__ void import_kernel(void* phi0, void* pi0, size_t count, int nf, int zs, size_t n2,
                               const double* phi_in, const double* pi_in) {
   T* __restrict__ phi = static_cast<T*>(phi0);
   T* __restrict__ pi = static_cast<T*>(pi0);
   const size_t n3 = count / nf;
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += stride) {
-    const size_t d = device_index(e, nf, n2, n3);
+    const size_t d = device_index(e, zs, n2, n3);
     phi[d] = static_cast<T>(phi_in[e]);
     pi[d] = static_cast<T>(pi_in[e]);
   }
@@ -391,10 +391,10 @@ hipError_t launch_sum_pi2(const LatView& v, hipStream_t s) {
   const Bufs B = bufs_of(v);
   if (v.prec == SL_FP32)
     hipLaunchKernelGGL(sum_pi2_kernel<float>, dim3(nb), dim3(kBlock), 0, s, B, v.sc, count,
-                       v.partials);
+                       count / v.nf, size_t(v.n) * v.n, v.zs, v.partials);
   else
     hipLaunchKernelGGL(sum_pi2_kernel<double>, dim3(nb), dim3(kBlock), 0, s, B, v.sc, count,
-                       v.partials);
+                       count / v.nf, size_t(v.n) * v.n, v.zs, v.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sum_pi2_finalize, dim3(1), dim3(kBlock), 0, s, v.partials, nb, v.sc);
@@ -406,10 +406,10 @@ hipError_t launch_export(const LatView& v, double* phi_out, double* pi_out, hipS
   const Bufs B = bufs_of(v);
   if (v.prec == SL_FP32)
     hipLaunchKernelGGL(export_kernel<float>, dim3(grid_for(count)), dim3(kBlock), 0, s, B, v.sc,
-                       count, v.nf, size_t(v.n) * v.n, phi_out, pi_out);
+                       count, v.nf, v.zs, size_t(v.n) * v.n, phi_out, pi_out);
   else
     hipLaunchKernelGGL(export_kernel<double>, dim3(grid_for(count)), dim3(kBlock), 0, s, B, v.sc,
-                       count, v.nf, size_t(v.n) * v.n, phi_out, pi_out);
+                       count, v.nf, v.zs, size_t(v.n) * v.n, phi_out, pi_out);
   return hipGetLastError();
 }
 
@@ -418,10 +418,10 @@ hipError_t launch_import(const LatView& v, const double* phi_in, const double* p
   const size_t count = size_t(v.nf) * v.n * v.n * v.n;
   if (v.prec == SL_FP32)
     hipLaunchKernelGGL(import_kernel<float>, dim3(grid_for(count)), dim3(kBlock), 0, s, v.phi[0],
-                       v.pi[0], count, v.nf, size_t(v.n) * v.n, phi_in, pi_in);
+                       v.pi[0], count, v.nf, v.zs, size_t(v.n) * v.n, phi_in, pi_in);
   else
     hipLaunchKernelGGL(import_kernel<double>, dim3(grid_for(count)), dim3(kBlock), 0, s, v.phi[0],
-                       v.pi[0], count, v.nf, size_t(v.n) * v.n, phi_in, pi_in);
+                       v.pi[0], count, v.nf, v.zs, size_t(v.n) * v.n, phi_in, pi_in);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(reset_scalars_kernel, dim3(1), dim3(64), 0, s, v.sc, a, p_a);

@@ -37,13 +37,14 @@ __device__ __forceinline__ double normal(uint64_t seed, uint64_t field, uint64_t
 }
 
 template <typename T>
-__global__ void fill_homogeneous_kernel(void* phi0, void* pi0, int nf, size_t n2, size_t n3,
-                                        PotArgs v0, PotArgs p0) {
+__global__ void fill_homogeneous_kernel(void* phi0, void* pi0, int nf, int zs, size_t n2,
+                                        size_t n3, PotArgs v0, PotArgs p0) {
   T* phi = static_cast<T*>(phi0);
   T* pi = static_cast<T*>(pi0);
   const size_t stride = size_t(gridDim.x) * blockDim.x;
-  for (size_t d = size_t(blockIdx.x) * blockDim.x + threadIdx.x; d < n3 * nf; d += stride) {
-    const int i = int((d / n2) % size_t(nf));  // field of device element d
+  for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n3 * nf; e += stride) {
+    const int i = int(e / n3);  // field i, site e - i n^3
+    const size_t d = field_site(i, e - size_t(i) * n3, zs, n2);
     phi[d] = static_cast<T>(v0.p[i]);
     pi[d] = static_cast<T>(p0.p[i]);
   }
@@ -128,12 +129,12 @@ __global__ __launch_bounds__(kBlock) void dft_axis_kernel(int n, const double2* 
 }
 
 template <typename T>
-__global__ void add_real_kernel(void* phi0, const double2* F, size_t n3, size_t n2, int nf,
+__global__ void add_real_kernel(void* phi0, const double2* F, size_t n3, size_t n2, int zs,
                                 int field, double base, double scale) {
   T* phi = static_cast<T*>(phi0);
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n3; e += stride)
-    phi[field_site(field, e, nf, n2)] = static_cast<T>(base + scale * F[e].x);
+    phi[field_site(field, e, zs, n2)] = static_cast<T>(base + scale * F[e].x);
 }
 
 __global__ __launch_bounds__(kBlock) void white_kernel(double* g, size_t n3, int field,
@@ -165,18 +166,18 @@ __global__ __launch_bounds__(kBlock) void mean_finalize_kernel(const double* par
 
 template <typename T>
 __global__ void white_store_kernel(void* phi0, const double* g, const double* mean, size_t n3,
-                                   size_t n2, int nf, int field, double base, double amp) {
+                                   size_t n2, int zs, int field, double base, double amp) {
   T* phi = static_cast<T*>(phi0);
   const double mu = *mean;
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n3; e += stride)
-    phi[field_site(field, e, nf, n2)] = static_cast<T>(base + amp * (g[e] - mu));
+    phi[field_site(field, e, zs, n2)] = static_cast<T>(base + amp * (g[e] - mu));
 }
 
 template <typename T>
 __global__ void field_to_complex_kernel(const void* const phi_b0, const void* const phi_b1,
                                         const void* const pi_b0, const void* const pi_b1,
-                                        const DevScalars* sc, size_t n3, size_t n2, int nf,
+                                        const DevScalars* sc, size_t n3, size_t n2, int zs,
                                         int field, double2* F) {
   const int par = sc->parity;
   const T* phi = static_cast<const T*>(par ? phi_b1 : phi_b0);
@@ -184,7 +185,7 @@ __global__ void field_to_complex_kernel(const void* const phi_b0, const void* co
   const double c = sc->c_pend;
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n3; e += stride) {
-    const size_t d = field_site(field, e, nf, n2);
+    const size_t d = field_site(field, e, zs, n2);
     F[e] = make_double2(fma(c, double(pi[d]), double(phi[d])), 0.0);
   }
 }
@@ -262,10 +263,10 @@ hipError_t launch_fill_homogeneous(const LatView& v, const double* phi0, const d
   const int nb = grid_for(n3 * v.nf);
   if (v.prec == SL_FP32)
     hipLaunchKernelGGL(fill_homogeneous_kernel<float>, dim3(nb), dim3(kBlock), 0, s, v.phi[0],
-                       v.pi[0], v.nf, size_t(v.n) * v.n, n3, a, b);
+                       v.pi[0], v.nf, v.zs, size_t(v.n) * v.n, n3, a, b);
   else
     hipLaunchKernelGGL(fill_homogeneous_kernel<double>, dim3(nb), dim3(kBlock), 0, s, v.phi[0],
-                       v.pi[0], v.nf, size_t(v.n) * v.n, n3, a, b);
+                       v.pi[0], v.nf, v.zs, size_t(v.n) * v.n, n3, a, b);
   return hipGetLastError();
 }
 
@@ -296,10 +297,10 @@ hipError_t launch_add_real(const LatView& v, const double2* cbuf, int field, dou
   const size_t n3 = size_t(v.n) * v.n * v.n;
   if (v.prec == SL_FP32)
     hipLaunchKernelGGL(add_real_kernel<float>, dim3(grid_for(n3)), dim3(kBlock), 0, s, v.phi[0],
-                       cbuf, n3, size_t(v.n) * v.n, v.nf, field, base, scale);
+                       cbuf, n3, size_t(v.n) * v.n, v.zs, field, base, scale);
   else
     hipLaunchKernelGGL(add_real_kernel<double>, dim3(grid_for(n3)), dim3(kBlock), 0, s, v.phi[0],
-                       cbuf, n3, size_t(v.n) * v.n, v.nf, field, base, scale);
+                       cbuf, n3, size_t(v.n) * v.n, v.zs, field, base, scale);
   return hipGetLastError();
 }
 
@@ -317,10 +318,10 @@ hipError_t launch_white(const LatView& v, double* gbuf, double* mean_dev, int fi
   if (e != hipSuccess) return e;
   if (v.prec == SL_FP32)
     hipLaunchKernelGGL(white_store_kernel<float>, dim3(grid_for(n3)), dim3(kBlock), 0, s,
-                       v.phi[0], gbuf, mean_dev, n3, size_t(v.n) * v.n, v.nf, field, base, amp);
+                       v.phi[0], gbuf, mean_dev, n3, size_t(v.n) * v.n, v.zs, field, base, amp);
   else
     hipLaunchKernelGGL(white_store_kernel<double>, dim3(grid_for(n3)), dim3(kBlock), 0, s,
-                       v.phi[0], gbuf, mean_dev, n3, size_t(v.n) * v.n, v.nf, field, base, amp);
+                       v.phi[0], gbuf, mean_dev, n3, size_t(v.n) * v.n, v.zs, field, base, amp);
   return hipGetLastError();
 }
 
@@ -328,11 +329,11 @@ hipError_t launch_field_to_complex(const LatView& v, int field, double2* cbuf, h
   const size_t n3 = size_t(v.n) * v.n * v.n;
   if (v.prec == SL_FP32)
     hipLaunchKernelGGL(field_to_complex_kernel<float>, dim3(grid_for(n3)), dim3(kBlock), 0, s,
-                       v.phi[0], v.phi[1], v.pi[0], v.pi[1], v.sc, n3, size_t(v.n) * v.n, v.nf,
+                       v.phi[0], v.phi[1], v.pi[0], v.pi[1], v.sc, n3, size_t(v.n) * v.n, v.zs,
                        field, cbuf);
   else
     hipLaunchKernelGGL(field_to_complex_kernel<double>, dim3(grid_for(n3)), dim3(kBlock), 0, s,
-                       v.phi[0], v.phi[1], v.pi[0], v.pi[1], v.sc, n3, size_t(v.n) * v.n, v.nf,
+                       v.phi[0], v.phi[1], v.pi[0], v.pi[1], v.sc, n3, size_t(v.n) * v.n, v.zs,
                        field, cbuf);
   return hipGetLastError();
 }

@@ -17,10 +17,11 @@
 // sum pi'^2 (for the H2 kicks of p_a).  The global sums make every stage a
 // grid-wide dependency, so a stage is one pass plus one small finalize.
 //
-// Data layout: phi and pi are [z][field][y][x] (x fastest; the fields of one
-// plane one after the other) in two ping-pong buffers; the pass reads buffer
-// `parity` and writes the other one, so no tile ever reads a value another
-// tile has already advanced.
+// Data layout: in phi and pi the fields of each z-plane follow one another
+// (x fastest), planes P.zs n^2 elements apart (zs = nf, or 2 nf when phi and
+// pi of a parity share one block, interleaved by plane); two ping-pong
+// buffers: the pass reads buffer `parity` and writes the other one, so no
+// tile ever reads a value another tile has already advanced.
 //
 // Tiling: a 256-thread workgroup owns a TX x TY column tile (TX lanes of a
 // wavefront along x, coalesced) and marches up TZ planes in z.  Each thread
@@ -174,7 +175,7 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
   auto load_own = [&](int zz) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      const size_t o = (size_t(zz) * NF + i) * n2 + col;
+      const size_t o = (size_t(zz) * P.zs + i) * n2 + col;
       const Vec<T, VX> u = ldv<T, VX>(phi_in + o), w = ldv<T, VX>(pi_in + o);
 #pragma unroll
       for (int v = 0; v < VX; ++v) {
@@ -186,7 +187,7 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
   auto load_halo = [&](int zz) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      const size_t o = (size_t(zz) * NF + i) * n2 + hcol;
+      const size_t o = (size_t(zz) * P.zs + i) * n2 + hcol;
       const Vec<T, VX> u = ldv<T, VX>(phi_in + o), w = ldv<T, VX>(pi_in + o);
 #pragma unroll
       for (int v = 0; v < VX; ++v) {
@@ -297,7 +298,7 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
       }
 #pragma unroll
       for (int i = 0; i < NF; ++i) {
-        const size_t oc = (size_t(z) * NF + i) * n2 + col;
+        const size_t oc = (size_t(z) * P.zs + i) * n2 + col;
         T* po = active ? phi_out + oc : sink + (2 * i) * VX;
         T* qo = active ? pi_out + oc : sink + (2 * i + 1) * VX;
         stv<T, VX>(po, fc[i]);
@@ -431,7 +432,7 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T*
   auto load_plane = [&](int zz) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      const size_t o = (size_t(zz) * NF + i) * n2;
+      const size_t o = (size_t(zz) * P.zs + i) * n2;
       const Vec<T, VX> u = ldv<T, VX>(phi_in + o + col), w = ldv<T, VX>(pi_in + o + col);
       const Vec<T, VX> hu = ldv<T, VX>(phi_in + o + hcol), hw = ldv<T, VX>(pi_in + o + hcol);
 #pragma unroll
@@ -515,7 +516,7 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T*
       const size_t zo = size_t(wrapz(p - 1));
 #pragma unroll
       for (int i = 0; i < NF; ++i) {
-        const size_t oc = (zo * NF + i) * n2 + col;
+        const size_t oc = (zo * P.zs + i) * n2 + col;
         T* po = out ? phi_out + oc : sink + (2 * i) * VX;
         T* qo = out ? pi_out + oc : sink + (2 * i + 1) * VX;
         stv<T, VX>(po, fB[i]);
@@ -730,6 +731,7 @@ PassParams make_params(const LatView& v) {
   P.ntx = v.tile.ntx;
   P.nty = v.tile.nty;
   P.ntz = v.tile.ntz;
+  P.zs = v.zs;
   return P;
 }
 

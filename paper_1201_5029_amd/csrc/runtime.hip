@@ -584,15 +584,29 @@ sl_status create_impl(const sl_config* cfg, void* hip_stream, void* const* user,
     v.phi[1] = user[2];
     v.pi[1] = user[3];
   }
+  // The fields of a plane follow one another in every array (zs = nf).  With
+  // FP64 storage of up to two fields, phi and pi of one parity also share a
+  // block, interleaved by plane (zs = 2 nf, pi[k] = phi[k] + nf n^2): the
+  // FP64 pass measured 2-3 % faster so, FP32 1 % slower.
+  v.zs = cfg->nfields;
   if (!user) {
     const size_t stride = round256(fbytes);
     ok = hipMalloc(&L->fields_mem, 4 * stride) == hipSuccess;
     if (ok) {
       char* base = static_cast<char*>(L->fields_mem);
-      v.phi[0] = base;
-      v.pi[0] = base + stride;
-      v.phi[1] = base + 2 * stride;
-      v.pi[1] = base + 3 * stride;
+      if (cfg->precision == SL_FP64 && cfg->nfields <= 2) {
+        const size_t plane = size_t(cfg->n) * cfg->n * cfg->nfields * L->elem;
+        v.zs = 2 * cfg->nfields;
+        v.phi[0] = base;
+        v.pi[0] = base + plane;
+        v.phi[1] = base + 2 * stride;
+        v.pi[1] = base + 2 * stride + plane;
+      } else {
+        v.phi[0] = base;
+        v.pi[0] = base + stride;
+        v.phi[1] = base + 2 * stride;
+        v.pi[1] = base + 3 * stride;
+      }
     }
   }
   const AuxLayout aux;
@@ -611,9 +625,13 @@ sl_status create_impl(const sl_config* cfg, void* hip_stream, void* const* user,
     delete L;
     return fail(SL_E_NOMEM, "device allocation of %zu bytes failed", sl_footprint_bytes(cfg));
   }
-  for (int k = 0; k < 2; ++k) {
-    (void)hipMemsetAsync(v.phi[k], 0, fbytes, L->stream);
-    (void)hipMemsetAsync(v.pi[k], 0, fbytes, L->stream);
+  if (L->fields_mem) {
+    (void)hipMemsetAsync(L->fields_mem, 0, 4 * round256(fbytes), L->stream);
+  } else {
+    for (int k = 0; k < 2; ++k) {
+      (void)hipMemsetAsync(v.phi[k], 0, fbytes, L->stream);
+      (void)hipMemsetAsync(v.pi[k], 0, fbytes, L->stream);
+    }
   }
   (void)hipMemsetAsync(v.sc, 0, sizeof(DevScalars), L->stream);
   if (launch_reset_scalars(v, cfg->a0, 0.0, L->stream) != hipSuccess ||

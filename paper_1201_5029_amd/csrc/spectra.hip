@@ -52,7 +52,8 @@ struct Bufs4 {
 // Per-block compensated sums of d^2V/dphi_i^2 at the synchronised fields.
 template <typename T, int NF, int KIND>
 __global__ __launch_bounds__(kBlock) void meff_kernel(Bufs4 B, const DevScalars* sc, PotArgs prm,
-                                                     size_t n3, size_t n2, double* part) {
+                                                     size_t n3, size_t n2, int zs,
+                                                     double* part) {
   __shared__ KSum scratch[4 * NF];
   const int par = sc->parity;
   const T* phi = static_cast<const T*>(B.phi[par]);
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void meff_kernel(Bufs4 B, const DevScalars*
     double f[NF], d[NF];
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      const size_t o = field_site(i, e, NF, n2);
+      const size_t o = field_site(i, e, zs, n2);
       f[i] = fma(c, double(pi[o]), double(phi[o]));
     }
     d2v_diag<KIND, NF, double>(f, pot, d);
@@ -98,11 +99,11 @@ __global__ void meff_finalize_kernel(const double* part, int nblocks, int nf, do
 
 template <typename T>
 __global__ void momentum_to_complex_kernel(Bufs4 B, const DevScalars* sc, size_t n3, size_t n2,
-                                           int nf, int field, double2* F) {
+                                           int zs, int field, double2* F) {
   const T* pi = static_cast<const T*>(B.pi[sc->parity]);
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n3; e += stride)
-    F[e] = make_double2(double(pi[field_site(field, e, nf, n2)]), 0.0);
+    F[e] = make_double2(double(pi[field_site(field, e, zs, n2)]), 0.0);
 }
 
 __device__ __forceinline__ int shell_index(long long m) {
@@ -200,7 +201,7 @@ hipError_t meff_t(const LatView& v, double* part, double* m2, hipStream_t s) {
   const size_t n3 = size_t(v.n) * v.n * v.n;
   const int nb = spec_grid(n3);
   hipLaunchKernelGGL((meff_kernel<T, NF, KIND>), dim3(nb), dim3(kBlock), 0, s, bufs4(v), v.sc, v.prm,
-                     n3, size_t(v.n) * v.n, part);
+                     n3, size_t(v.n) * v.n, v.zs, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(meff_finalize_kernel, dim3(1), dim3(64), 0, s, part, nb, NF, 1.0 / double(n3), m2);
@@ -240,10 +241,10 @@ hipError_t launch_momentum_to_complex(const LatView& v, int field, double2* cbuf
   const int nb = int((n3 + kBlock - 1) / kBlock < 65536 ? (n3 + kBlock - 1) / kBlock : 65536);
   if (v.prec == SL_FP32)
     hipLaunchKernelGGL(momentum_to_complex_kernel<float>, dim3(nb), dim3(kBlock), 0, s, bufs4(v), v.sc,
-                       n3, size_t(v.n) * v.n, v.nf, field, cbuf);
+                       n3, size_t(v.n) * v.n, v.zs, field, cbuf);
   else
     hipLaunchKernelGGL(momentum_to_complex_kernel<double>, dim3(nb), dim3(kBlock), 0, s, bufs4(v), v.sc,
-                       n3, size_t(v.n) * v.n, v.nf, field, cbuf);
+                       n3, size_t(v.n) * v.n, v.zs, field, cbuf);
   return hipGetLastError();
 }
 
