@@ -285,9 +285,10 @@ double sl_stability_limit(int32_t order);
 sl_status sl_set_kernel_timing(sl_lattice* lat, int32_t enable);
 sl_status sl_kernel_timing(sl_lattice* lat, int64_t* passes, double* total_ms);
 
-/* Launch shape of the fused pass: tx lanes along x (16, 32 or 64), each
+/* Launch shape of the fused pass: tx lanes along x (8 .. 64), each
  * holding vx consecutive x-sites (1, 2 or 4; n must be divisible by vx),
- * ty = 256/tx rows, tz z-planes per workgroup, and the prefetch depth pf of
+ * ty = floor(256/tx) rows (the remaining 256 - tx*ty lanes of the workgroup
+ * idle), tz z-planes per workgroup, and the prefetch depth pf of
  * the z-march (1: next plane loaded each iteration; 2: own column two
  * planes and halo one plane ahead).  Lattices with more than two fields run
  * with vx = 1, pf = 1; any stencil other than the 7-point one runs with
@@ -301,8 +302,10 @@ sl_status sl_get_tile(sl_lattice* lat, int32_t* tx, int32_t* vx, int32_t* ty, in
                       int32_t* pf);
 sl_status sl_set_tile(sl_lattice* lat, int32_t tx, int32_t vx, int32_t tz, int32_t pf);
 
-/* Autotuner: time candidate shapes (tx in {16, 32, 64}, vx in {1, 2, 4}
- * dividing n, pf in {1, 2}, tz in {occupancy choice, n/16, n/8, n/4, n/2})
+/* Autotuner: time candidate shapes (tx in {16, 32, 64}, 8 with vx = 4, and
+ * n/vx when that is in [8, 64] and not a power of two, i.e. a whole row per
+ * tile; vx in {1, 2, 4} dividing n; pf in {1, 2}; tz in {occupancy choice,
+ * n/16, n/8, n/4, n/2})
  * on the lattice's current state: best of `reps` HIP-event timings of two
  * consecutive stages (fused pass + finalize, each reading what the previous
  * wrote, as inside sl_evolve) with the drift and kick coefficients frozen at
@@ -345,7 +348,8 @@ sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order
 /* Batch autotuner: every per-lane shape (vx in {1, 2, 4} dividing all
  * member sizes, pf in {1, 2}, as the field count and stencil allow) is timed
  * at starting shapes; for the two fastest, per member size (largest share
- * of sites first, two rounds of coordinate descent) tx in {16, 32, 64} and
+ * of sites first, two rounds of coordinate descent) the same tx candidates
+ * as sl_autotune and
  * z-chunks n/{1, 2, 4, 8} are tried for all members of that size, timing
  * the batched pass alone (best of `reps`
  * HIP-event timings of two passes; the members' states are left

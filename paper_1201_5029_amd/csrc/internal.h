@@ -95,11 +95,11 @@ struct Stencil {
   int32_t pad;
 };
 
-// Launch shape of the tiled passes: TX lanes in x (power of two) each
-// holding VX consecutive sites (tile width TX*VX), TY = 256/TX rows in y,
-// TZ planes per z-chunk.
+// Launch shape of the tiled passes: TX lanes in x (8 .. 64) each holding VX
+// consecutive sites (tile width TX*VX), TY = floor(256/TX) rows in y (the
+// last 256 - TX*TY lanes of the workgroup idle), TZ planes per z-chunk.
 struct Tile {
-  int tx, logtx, ty, tz, vx;
+  int tx, ty, tz, vx;
   int pf;  // prefetch depth of the z-march (1 or 2 planes)
   int ntx, nty, ntz;
   int nblocks() const { return ntx * nty * ntz; }
@@ -117,7 +117,7 @@ struct PassParams {
   PotArgs prm;
   double stc[4];  // stencil weights (27-point pass only)
   int n;
-  int tx, logtx, ty, tz;  // lanes in x, log2(lanes), rows, planes per chunk
+  int tx, ty, tz;  // lanes in x, rows, planes per chunk
   int ntx, nty, ntz;
   int zs;  // plane stride of the field arrays, in planes (LatView::zs)
 };

@@ -130,12 +130,13 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
   const int zend = z0 + zc;  // exclusive; plane zend (mod n) is the upper halo
 
   const int tid = threadIdx.x;
-  const int tx = tid & (P.tx - 1);
-  const int ty = tid >> P.logtx;
+  const int ty = tid / P.tx;  // lanes past TX*TY (ty = TY) are idle
+  const int tx = tid - ty * P.tx;
   const bool active = (tx * VX < wx) && (ty < wy);
   const int LX = TW + 2;
   const int plane = LX * (P.ty + 2);
-  const int own = (ty + 1) * LX + 1 + tx * VX;  // LDS index of the first own site
+  // LDS index of the first own site (idle lanes: a row inside the tile)
+  const int own = (min(ty, P.ty - 1) + 1) * LX + 1 + tx * VX;
   // own column; idle lanes read the tile's first column (in range, unused)
   const size_t col = active ? size_t(y0 + ty) * n + (x0 + tx * VX) : size_t(y0) * n + x0;
 
@@ -378,12 +379,12 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T*
   const int zend = z0 + zc;
 
   const int tid = threadIdx.x;
-  const int tx = tid & (P.tx - 1);
-  const int ty = tid >> P.logtx;
+  const int ty = tid / P.tx;  // lanes past TX*TY (ty = TY) are idle
+  const int tx = tid - ty * P.tx;
   const bool active = (tx * VX < wx) && (ty < wy);
   const int LX = TW + 2;
   const int plane = LX * (P.ty + 2);
-  const int own = (ty + 1) * LX + 1 + tx * VX;
+  const int own = (min(ty, P.ty - 1) + 1) * LX + 1 + tx * VX;
   const size_t col = active ? size_t(y0 + ty) * n + (x0 + tx * VX) : size_t(y0) * n + x0;
 
   // halo job: 1 = VX-wide row segment above/below, 2 = the cell at element
@@ -725,7 +726,6 @@ PassParams make_params(const LatView& v) {
   for (int k = 0; k < 4; ++k) P.stc[k] = v.st.c[k];
   P.n = v.n;
   P.tx = v.tile.tx;
-  P.logtx = v.tile.logtx;
   P.ty = v.tile.ty;
   P.tz = v.tile.tz;
   P.ntx = v.tile.ntx;

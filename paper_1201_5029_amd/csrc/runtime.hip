@@ -146,20 +146,35 @@ constexpr long kMaxPassBlocks = 65536;  // bound of the per-block partial-sum bu
 constexpr int64_t kEvolveChunk = 32;     // steps per captured evolve graph
 constexpr int64_t kBatchChunk = 8;       // steps per captured batch graph
 
-// Tile geometry for lanes tx (16/32/64), vx sites per lane, tz planes and
+// Tile geometry for lanes tx (8 .. 64), vx sites per lane, tz planes and
 // prefetch depth pf.
 Tile tile_geometry(int n, int tx, int vx, int tz, int pf) {
   Tile t;
   t.tx = tx;
   t.vx = vx;
   t.pf = pf;
-  t.logtx = tx == 64 ? 6 : (tx == 32 ? 5 : 4);
   t.ty = kBlock / tx;
   t.ntx = (n + tx * vx - 1) / (tx * vx);
   t.nty = (n + t.ty - 1) / t.ty;
   t.tz = tz > n ? n : tz;
   t.ntz = (n + t.tz - 1) / t.tz;
   return t;
+}
+
+// Lane counts along x the tuners try for vx sites per lane: powers of two
+// (8 only with 4 sites per lane, and none far wider than the lattice) and,
+// when it is not one of them, the width of a whole row, so that sizes such
+// as 96 run without idle columns.
+std::vector<int> tx_candidates(int n, int vx) {
+  std::vector<int> v;
+  for (int tx : {8, 16, 32, 64}) {
+    if (tx == 8 && vx != 4) continue;
+    if (tx * vx > 2 * n && tx > 16) continue;
+    v.push_back(tx);
+  }
+  const int row = n / vx;
+  if (row >= 8 && row <= 64 && (row & (row - 1)) != 0) v.push_back(row);
+  return v;
 }
 
 // z-chunk length for a shape: the grid should fill the resident capacity
@@ -1118,8 +1133,7 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
   std::vector<Cand> cands;
   for (int vx : {1, 2, 4}) {
     if (n % vx != 0 || (many && vx != 1) || (st27 && vx > 2) || (vx_only && vx != vx_only)) continue;
-    for (int tx : {16, 32, 64}) {
-      if (tx * vx > 2 * n && tx != 16) continue;  // tile far wider than the lattice
+    for (int tx : tx_candidates(n, vx)) {
       for (int pf : {1, 2}) {
         if (((many || st27) && pf != 1) || (pf_only && pf != pf_only)) continue;
         std::vector<int> tzs = {0};
@@ -1226,7 +1240,7 @@ sl_status sl_get_tile(sl_lattice* L, int32_t* tx, int32_t* vx, int32_t* ty, int3
 
 sl_status sl_set_tile(sl_lattice* L, int32_t tx, int32_t vx, int32_t tz, int32_t pf) {
   if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
-  if (tx != 16 && tx != 32 && tx != 64) return fail(SL_E_INVALID, "tx must be 16, 32 or 64");
+  if (tx < 8 || tx > 64) return fail(SL_E_INVALID, "tx must be in [8, 64]");
   if (vx != 1 && vx != 2 && vx != 4) return fail(SL_E_INVALID, "vx must be 1, 2 or 4");
   if (L->cfg.n % vx != 0) return fail(SL_E_INVALID, "vx = %d needs n divisible by %d", vx, vx);
   if (pf != 1 && pf != 2) return fail(SL_E_INVALID, "pf must be 1 or 2");
@@ -1667,8 +1681,7 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
         int ref_tx = 0, ref_tz = 0;
         cur_shape(n, &ref_tx, &ref_tz);
         int btx = ref_tx, btz = ref_tz;
-        for (int tx : {16, 32, 64}) {
-          if (tx * vx > 2 * n && tx != 16) continue;
+        for (int tx : tx_candidates(n, vx)) {
           if (B->st_kind != 0 && 2 * tx + 2 * (kBlock / tx) + 4 > kBlock) continue;
           for (int d : {1, 2, 4, 8}) {
             const int tz = n / d;

@@ -46,13 +46,37 @@ def _cases(count=24, seed=20120299):
 CASES = _cases()
 
 
-@pytest.mark.parametrize("case", range(len(CASES)))
-def test_sweep(case):
-    kind, params, base, mpl, n, stencil, tile = CASES[case]
+def _cases_lanes(count=16, seed=20120298):
+    """Cases for the lane count along x: 8 lanes (32 rows of the workgroup),
+    a whole row per tile (n / vx lanes, often not a power of two, with the
+    last 256 mod tx lanes idle) or any count in [8, 64]; half of the sizes
+    multiples of 4, with 4 sites per lane where the case allows it."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        kind, params, base, mpl = MODELS[int(rng.integers(len(MODELS)))]
+        nf = len(base)
+        n = int(4 * rng.integers(1, 11)) if rng.random() < 0.5 else int(rng.integers(4, 41))
+        st27 = bool(rng.random() < 0.3)
+        vxs = [1] if nf > 2 else [v for v in (1, 2, 4) if n % v == 0 and not (st27 and v == 4)]
+        vx = 4 if 4 in vxs else int(rng.choice(vxs))
+        pf = 1 if (nf > 2 or st27) else int(rng.choice([1, 2]))
+        tz = int(rng.integers(0, n + 1))
+        row = n // vx
+        tx = [8, row if 8 <= row <= 64 else 8, int(rng.integers(8, 65))][k % 3]
+        out.append((kind, params, base, mpl, n, "27" if st27 else None, (tx, vx, tz, pf)))
+    return out
+
+
+CASES_LANES = _cases_lanes()
+
+
+def _run_case(case, spec, seed):
+    kind, params, base, mpl, n, stencil, tile = spec
     nf = len(base)
     L = 0.5 * n                                    # dx = 0.5
     scale = max(abs(b) for b in base)
-    phi, pi = synth.gaussian_state(n, nf, 9000 + case, phi_base=list(base),
+    phi, pi = synth.gaussian_state(n, nf, seed, phi_base=list(base),
                                    phi_amp=1e-3 * scale, pi_amp=1e-3 * scale)
     o = oracle_lattice(n, L, kind, params, phi, pi, mpl=mpl,
                        stencil=oracle.STENCIL_27 if stencil else None)
@@ -64,6 +88,16 @@ def test_sweep(case):
     say("  errors", ef, ep, ea, epa)
     assert max(ef, ep, ea, epa) <= FP64_TOL
     g.close()
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_sweep(case):
+    _run_case(case, CASES[case], 9000 + case)
+
+
+@pytest.mark.parametrize("case", range(len(CASES_LANES)))
+def test_sweep_lanes(case):
+    _run_case(case, CASES_LANES[case], 9100 + case)
 
 
 @pytest.mark.parametrize("case", range(0, len(CASES), 3))
