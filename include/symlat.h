@@ -347,7 +347,8 @@ sl_status sl_batch_count(const sl_batch* batch, int32_t* count);
 sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order);
 /* Batch autotuner: every per-lane shape (vx in {1, 2, 4} dividing all
  * member sizes, pf in {1, 2}, as the field count and stencil allow) is timed
- * at starting shapes; for the two fastest, per member size (largest share
+ * at starting shapes (a whole row per tile, at most 64 lanes, quarter-lattice
+ * z-chunks); for the three fastest, per member size (largest share
  * of sites first, two rounds of coordinate descent) the same tx candidates
  * as sl_autotune and
  * z-chunks n/{1, 2, 4, 8} are tried for all members of that size, timing

@@ -569,9 +569,10 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(PassParams P) {
 // Batched form: the tiles of many lattices (same precision, potential family
 // and per-lane shape; any sizes) in one launch.  Global tile g belongs to run
 // r with start[r] <= g < start[r+1].  Each XCD takes a contiguous range of
-// global tiles and its workgroups stride through it, so one launch of about
-// the resident capacity covers any mix of lattice sizes.  A run's tiles and
-// partial sums are exactly those of the same lattice advanced alone.
+// global tiles and its workgroups stride through it (the runtime launches
+// one workgroup per tile, so a workgroup takes one tile, at most two when
+// the ranges are uneven).  A run's tiles and partial sums are exactly those
+// of the same lattice advanced alone.
 template <typename T, int NF, int KIND, int VX, int PF, int ST>
 __global__ __launch_bounds__(kBlock) void batched_pass_kernel(const PassParams* __restrict__ runs,
                                                              const int* __restrict__ start,
@@ -831,14 +832,6 @@ hipError_t launch_batched_pass(int prec, int pot, int nf, const Tile& shape, int
   const PassKernel k = pick(prec, pot, nf, shape, stencil_kind);
   hipLaunchKernelGGL(k.bfn, dim3(grid), dim3(kBlock), lds, s, runs_dev, start_dev, nruns);
   return hipGetLastError();
-}
-
-int batched_blocks_per_cu(int prec, int pot, int nf, const Tile& shape, int stencil_kind,
-                          size_t lds) {
-  const PassKernel k = pick(prec, pot, nf, shape, stencil_kind);
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k.bfn, kBlock, lds) != hipSuccess) return 1;
-  return nb > 0 ? nb : 1;
 }
 
 size_t pass_lds_bytes(int prec, int nf, const Tile& t) {

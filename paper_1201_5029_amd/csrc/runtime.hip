@@ -1423,10 +1423,11 @@ sl_status batch_upload(sl_batch* B) {
   HIP_TRY(hipStreamSynchronize(B->stream));
   B->total_tiles = start[R];
   B->lds = lds;
-  const long resident =
-      long(batched_blocks_per_cu(B->prec, B->pot, B->nf, B->shape, B->st_kind, lds)) * device_cus();
-  B->grid = int(B->total_tiles < resident ? B->total_tiles : resident);
-  if (B->grid < 1) B->grid = 1;
+  // one workgroup per tile: the dispatcher hands the next tile to whichever
+  // CU frees a slot first, which evens out tiles of different sizes (a grid
+  // of the resident capacity with a static tile stride was 4 % slower on
+  // the 96-run ensemble)
+  B->grid = B->total_tiles > 0 ? B->total_tiles : 1;
   B->dirty = false;
   return SL_OK;
 }
@@ -1641,7 +1642,8 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
   double best_all = 1e300;
   sl_status st = SL_OK;
   // set every size to a lane shape: the members' current shapes for the
-  // batch's own lane shape, else the width rule with a quarter-lattice chunk
+  // batch's own lane shape, else a whole row per tile (at most 64 lanes, at
+  // least 8) with a quarter-lattice chunk
   auto start_shape = [&](int vx, int pf) {
     for (const auto& sz : sizes) {
       const int n = sz.second;
@@ -1649,14 +1651,14 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
       cur_shape(n, &tx, &tz);
       if (vx != B->shape.vx || pf != B->shape.pf) {
         const int width = n / vx;
-        tx = width >= 64 ? 64 : (width >= 32 ? 32 : 16);
+        tx = width > 64 ? 64 : (width < 8 ? 8 : width);
         tz = n / 4 >= 4 ? n / 4 : n;
       }
       apply(n, tx, vx, tz, pf);
     }
   };
   // phase 1: every lane shape at its starting shapes; phase 2 refines the
-  // two best
+  // three best
   const int orig_vx = B->shape.vx, orig_pf = B->shape.pf;
   std::vector<std::pair<double, int>> ranked;
   for (size_t q = 0; q < lane_shapes.size() && st == SL_OK; ++q) {
@@ -1668,7 +1670,7 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
     ranked.push_back({ms, int(q)});
   }
   std::sort(ranked.begin(), ranked.end());
-  for (size_t r = 0; r < ranked.size() && r < 2 && st == SL_OK; ++r) {
+  for (size_t r = 0; r < ranked.size() && r < 3 && st == SL_OK; ++r) {
     const int vx = lane_shapes[ranked[r].second].first, pf = lane_shapes[ranked[r].second].second;
     B->shape.vx = orig_vx;
     B->shape.pf = orig_pf;
