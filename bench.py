@@ -193,6 +193,7 @@ def measure_batched(sl, nruns=96, steps=100):
     for lat in lats:
         b.add(lat)
     pass_ms = b.autotune(reps=5)
+    grid = b.grid()
     shapes = sorted(set((r["n"],) + tuple(lat.tile()) for r, lat in zip(recipes, lats)))
     b.step(10, dt, order)          # captures the batch's chunk graph before the timed region
     b.synchronize()
@@ -213,7 +214,9 @@ def measure_batched(sl, nruns=96, steps=100):
             "effective_GBs": bytes_pass * stages * steps / wall / 1e9,
             "pass_ms": pass_ms, "pass_achieved_GBs": bytes_pass / (pass_ms * 1e-3) / 1e9,
             "pass_frac": bytes_pass / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "bytes_per_pass": bytes_pass, "shapes_n_tx_vx_ty_tz_pf": shapes}
+            "bytes_per_pass": bytes_pass, "shapes_n_tx_vx_ty_tz_pf": shapes,
+            "workgroups": {"launched": grid[1],
+                           "form": "persistent" if grid[0] > 0 else "one per tile"}}
 
 
 def measure_stencil27(sl, steps=50, warmup=5):

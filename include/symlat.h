@@ -343,6 +343,16 @@ sl_status sl_batch_destroy(sl_batch* batch);
 sl_status sl_batch_add(sl_batch* batch, sl_lattice* lat);
 sl_status sl_batch_remove(sl_batch* batch, sl_lattice* lat);
 sl_status sl_batch_count(const sl_batch* batch, int32_t* count);
+/* Workgroups of the batched pass.  0 (the default) launches one per tile,
+ * and the dispatcher balances tiles of different sizes over the CUs;
+ * w > 0 launches min(w, tiles) workgroups that stay resident and stride
+ * through the concatenated tile list, each XCD through a contiguous range
+ * (the persistent form).  Results are the same bit for bit either way.
+ * sl_batch_autotune sets it.  sl_batch_get_grid reports the request and the
+ * workgroup count the next step launches (0 for an empty batch); outputs
+ * may be NULL.  SL_E_INVALID for w < 0 or w > 2^24. */
+sl_status sl_batch_set_grid(sl_batch* batch, int32_t workgroups);
+sl_status sl_batch_get_grid(const sl_batch* batch, int32_t* requested, int32_t* launched);
 /* Advance every member `steps` steps (same dt and order for all). */
 sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order);
 /* Batch autotuner: every per-lane shape (vx in {1, 2, 4} dividing all
@@ -354,8 +364,10 @@ sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order
  * z-chunks n/{1, 2, 4, 8} are tried for all members of that size, timing
  * the batched pass alone (best of `reps`
  * HIP-event timings of two passes; the members' states are left
- * unchanged), and keep a shape only if it is at least 0.5 % faster.  The
- * chosen shapes are applied to the members
+ * unchanged), and keep a shape only if it is at least 0.5 % faster; last,
+ * with the chosen shapes, the persistent grid of the resident capacity is
+ * timed against one workgroup per tile and kept only if 0.5 % faster (see
+ * sl_batch_set_grid).  The chosen shapes are applied to the members
  * (also for their own sl_evolve calls) and remembered for this process:
  * lattices of a tuned size that join a batch later are given that shape.
  * best_ms (may be NULL) receives the final pass time.  SL_E_STATE for an

@@ -162,6 +162,8 @@ size_t pass_lds_bytes(int prec, int nf, const Tile& t);
 hipError_t launch_batched_pass(int prec, int pot, int nf, const Tile& shape, int stencil_kind,
                                size_t lds, const PassParams* runs_dev, const int* start_dev,
                                int nruns, int grid, hipStream_t s);
+int batched_blocks_per_cu(int prec, int pot, int nf, const Tile& shape, int stencil_kind,
+                          size_t lds);
 hipError_t launch_batched_finalize(const BatchRun* runs_dev, int nruns, double w, double w_next,
                                    double h, int has_next, int end_of_step, hipStream_t s);
 hipError_t launch_batched_begin(const BatchRun* runs_dev, int nruns, double w, double h,

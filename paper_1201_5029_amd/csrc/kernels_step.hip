@@ -569,23 +569,27 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(PassParams P) {
 // Batched form: the tiles of many lattices (same precision, potential family
 // and per-lane shape; any sizes) in one launch.  Global tile g belongs to run
 // r with start[r] <= g < start[r+1].  Each XCD takes a contiguous range of
-// global tiles and its workgroups stride through it (the runtime launches
-// one workgroup per tile, so a workgroup takes one tile, at most two when
-// the ranges are uneven).  A run's tiles and partial sums are exactly those
-// of the same lattice advanced alone.
+// global tiles and its workgroups stride through it: with one workgroup per
+// tile (the default launch) a workgroup takes one tile, at most two when
+// the ranges are uneven; with a smaller, persistent grid each workgroup
+// works through many.  A run's tiles and partial sums are exactly those of
+// the same lattice advanced alone, whatever the grid.
 template <typename T, int NF, int KIND, int VX, int PF, int ST>
 __global__ __launch_bounds__(kBlock) void batched_pass_kernel(const PassParams* __restrict__ runs,
                                                              const int* __restrict__ start,
                                                              int nruns) {
   extern __shared__ unsigned char smem_raw[];
   __shared__ KSum red_scratch[4 * 3];
+  // workgroups are dealt to the 8 XCDs round-robin; a grid of fewer than 8
+  // spreads the tile list over the XCDs it has
   constexpr int kXcd = 8;
   const int total = start[nruns];
   const int G = gridDim.x, b = blockIdx.x;
-  const int xcd = b % kXcd, i = b / kXcd;
-  const int nbx = (G - xcd + kXcd - 1) / kXcd;  // workgroups on this XCD
-  const int t0 = int((long long)total * xcd / kXcd);
-  const int t1 = int((long long)total * (xcd + 1) / kXcd);
+  const int nx = G < kXcd ? G : kXcd;
+  const int xcd = b % nx, i = b / nx;
+  const int nbx = (G - xcd + nx - 1) / nx;  // workgroups on this XCD
+  const int t0 = int((long long)total * xcd / nx);
+  const int t1 = int((long long)total * (xcd + 1) / nx);
   for (int g = t0 + i; g < t1; g += nbx) {
     int lo = 0, hi = nruns - 1;  // run with start[r] <= g < start[r + 1]
     while (lo < hi) {
@@ -832,6 +836,14 @@ hipError_t launch_batched_pass(int prec, int pot, int nf, const Tile& shape, int
   const PassKernel k = pick(prec, pot, nf, shape, stencil_kind);
   hipLaunchKernelGGL(k.bfn, dim3(grid), dim3(kBlock), lds, s, runs_dev, start_dev, nruns);
   return hipGetLastError();
+}
+
+int batched_blocks_per_cu(int prec, int pot, int nf, const Tile& shape, int stencil_kind,
+                          size_t lds) {
+  const PassKernel k = pick(prec, pot, nf, shape, stencil_kind);
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k.bfn, kBlock, lds) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
 }
 
 size_t pass_lds_bytes(int prec, int nf, const Tile& t) {

@@ -1345,7 +1345,8 @@ struct sl_batch {
   bool dirty = true;
   int total_tiles = 0;
   size_t lds = 0;
-  int grid = 0;
+  int grid_req = 0;  // 0: one workgroup per tile; > 0: that many workgroups stride through them
+  int grid = 0;      // workgroups of the batched pass as last uploaded
   uint64_t version = 0;
   hipEvent_t ev = nullptr;
   hipGraph_t graph = nullptr;
@@ -1369,6 +1370,15 @@ void batch_member_changed(sl_batch* B) {
 }
 
 namespace {
+
+// Workgroups of the batched pass.  By default one per tile: the dispatcher
+// hands the next tile to whichever CU frees a slot first, which evens out
+// tiles of different sizes.  A requested count (the persistent form) makes
+// each XCD's workgroups stride through its contiguous range of tiles.
+int batch_grid(int requested, int total_tiles) {
+  const int total = total_tiles > 0 ? total_tiles : 1;
+  return requested > 0 && requested < total ? requested : total;
+}
 
 void batch_drop_graph(sl_batch* B) {
   if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
@@ -1423,11 +1433,7 @@ sl_status batch_upload(sl_batch* B) {
   HIP_TRY(hipStreamSynchronize(B->stream));
   B->total_tiles = start[R];
   B->lds = lds;
-  // one workgroup per tile: the dispatcher hands the next tile to whichever
-  // CU frees a slot first, which evens out tiles of different sizes (a grid
-  // of the resident capacity with a static tile stride was 4 % slower on
-  // the 96-run ensemble)
-  B->grid = B->total_tiles > 0 ? B->total_tiles : 1;
+  B->grid = batch_grid(B->grid_req, B->total_tiles);
   B->dirty = false;
   return SL_OK;
 }
@@ -1634,6 +1640,10 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
       if (ok && !((B->nf > 2 || B->st_kind != 0) && pf != 1)) lane_shapes.push_back({vx, pf});
   }
   batch_drop_graph(B);
+  // shapes are tuned with one workgroup per tile; phase 3 picks the grid
+  const int saved_grid = B->grid_req;
+  B->grid_req = 0;
+  B->dirty = true;
   struct Pick {
     int tx, tz;
   };
@@ -1715,11 +1725,38 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
       for (size_t i = 0; i < sizes.size(); ++i) cur_shape(sizes[i].second, &best_pick[i].tx, &best_pick[i].tz);
     }
   }
+  if (st == SL_OK) {
+    for (size_t i = 0; i < sizes.size(); ++i)
+      apply(sizes[i].second, best_pick[i].tx, best_vx, best_pick[i].tz, best_pf);
+    // phase 3: one workgroup per tile against the persistent form with a
+    // grid of the resident capacity; the persistent form only if 0.5 %
+    // faster
+    double t_tile = 0.0, t_pers = 0.0;
+    st = time_now(&t_tile);
+    const long resident = long(batched_blocks_per_cu(B->prec, B->pot, B->nf, B->shape, B->st_kind,
+                                                     B->lds)) * device_cus();
+    if (st == SL_OK && resident < B->total_tiles) {
+      B->grid_req = int(resident);
+      B->dirty = true;
+      st = time_now(&t_pers);
+    }
+    if (st == SL_OK) {
+      if (t_pers > 0.0 && t_pers < 0.995 * t_tile) {
+        best_all = t_pers;
+      } else {
+        B->grid_req = 0;
+        best_all = t_tile;
+      }
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (st != SL_OK) return st;
-  for (size_t i = 0; i < sizes.size(); ++i)
-    apply(sizes[i].second, best_pick[i].tx, best_vx, best_pick[i].tz, best_pf);
+  if (st != SL_OK) {
+    B->grid_req = saved_grid;
+    B->dirty = true;
+    ++B->version;
+    return st;
+  }
   // remember the shapes for members added later (this batch or another)
   for (size_t i = 0; i < sizes.size(); ++i) {
     const sl_lattice* R = nullptr;
@@ -1739,6 +1776,26 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
 sl_status sl_batch_count(const sl_batch* B, int32_t* count) {
   if (!B || !count) return fail(SL_E_INVALID, "batch handle or count is NULL");
   *count = int32_t(B->runs.size());
+  return SL_OK;
+}
+
+sl_status sl_batch_set_grid(sl_batch* B, int32_t workgroups) {
+  if (!B) return fail(SL_E_INVALID, "batch handle is NULL");
+  if (workgroups < 0 || workgroups > (1 << 24))
+    return fail(SL_E_INVALID, "workgroups must be in [0, 2^24] (0: one per tile)");
+  if (workgroups == B->grid_req) return SL_OK;
+  B->grid_req = workgroups;
+  B->dirty = true;
+  ++B->version;
+  return SL_OK;
+}
+
+sl_status sl_batch_get_grid(const sl_batch* B, int32_t* requested, int32_t* launched) {
+  if (!B) return fail(SL_E_INVALID, "batch handle is NULL");
+  long total = 0;
+  for (const sl_lattice* L : B->runs) total += L->v.tile.nblocks();
+  if (requested) *requested = B->grid_req;
+  if (launched) *launched = B->runs.empty() ? 0 : batch_grid(B->grid_req, int(total));
   return SL_OK;
 }
 

@@ -36,6 +36,7 @@ EXPORTS = (
     "sl_linear_get_fields", "sl_linear_get_background", "sl_linear_classes",
     "sl_linear_synchronize", "sl_linear_set_kernel_timing", "sl_linear_kernel_timing",
     "sl_batch_autotune", "sl_spectra", "sl_set_history", "sl_get_history",
+    "sl_batch_set_grid", "sl_batch_get_grid",
 )
 
 #: Members of the cubic stencil family of eq. (2.7): (centre, face, edge,
@@ -111,6 +112,8 @@ def load():
         "sl_batch_add": (I32, [P, P]),
         "sl_batch_remove": (I32, [P, P]),
         "sl_batch_count": (I32, [P, ctypes.POINTER(I32)]),
+        "sl_batch_set_grid": (I32, [P, I32]),
+        "sl_batch_get_grid": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "sl_batch_step": (I32, [P, I64, D, I32]),
         "sl_batch_synchronize": (I32, [P]),
         "sl_device_memory": (I32, [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
@@ -405,6 +408,17 @@ class Batch:
 
     def step(self, steps, dt, order=4):
         _check(self._lib.sl_batch_step(self._h, int(steps), float(dt), int(order)))
+
+    def set_grid(self, workgroups):
+        """0: one workgroup per tile; w > 0: the persistent form with
+        min(w, tiles) workgroups striding through the tiles."""
+        _check(self._lib.sl_batch_set_grid(self._h, int(workgroups)))
+
+    def grid(self):
+        """(requested, launched) workgroups of the batched pass."""
+        r, l = ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.sl_batch_get_grid(self._h, ctypes.byref(r), ctypes.byref(l)))
+        return r.value, l.value
 
     def synchronize(self):
         _check(self._lib.sl_batch_synchronize(self._h))

@@ -225,3 +225,66 @@ def test_batch_synchronize_reports_a_nonfinite_member():
     b.remove(mixed[1])
     b.step(2, 0.005, 4)
     b.synchronize()                            # the finite members alone: no error
+
+
+@pytest.mark.parametrize("grid", [0, 1, 3, 7, 8, 13, 64, 1 << 20])
+def test_grid_forms_equal_alone(grid):
+    """One workgroup per tile (grid 0) and the persistent form with any
+    number of workgroups (fewer than the 8 XCDs, a few per XCD, more than the
+    tiles) give the members' alone results bit for bit, over graph replays."""
+    sl.symlat.load().sl_autotune_forget()
+    recipes = _runs("f32", [32, 64, 48, 96])
+    alone = [sl.from_recipe(r) for r in recipes]
+    mixed = [sl.from_recipe(r) for r in recipes]
+    b = sl.Batch()
+    for m in mixed:
+        b.add(m)
+    b.set_grid(grid)
+    tiles = sum(_tiles(m) for m in mixed)
+    req, launched = b.grid()
+    say("grid", grid, "tiles", tiles, "->", (req, launched))
+    assert req == grid and launched == (min(grid, tiles) if grid > 0 else tiles)
+    for rep in range(3):            # 10 steps: one captured 8-step chunk + 2 eager
+        b.step(10, 0.005, 4)
+        for a in alone:
+            a.evolve(10, 0.005, 4)
+        b.synchronize()
+        for j, (a, m) in enumerate(zip(alone, mixed)):
+            assert _same(a, m), (grid, rep, j)
+
+
+def _tiles(lat):
+    """Tiles of a lattice's fused pass from its shape (tx, vx, ty, tz, pf)."""
+    tx, vx, ty, tz, _ = lat.tile()
+    n = lat.n
+    return (-(-n // (tx * vx))) * (-(-n // ty)) * (-(-n // tz))
+
+
+def test_batch_with_fewer_tiles_than_xcds():
+    """Batches whose whole tile list is shorter than the number of XCDs
+    (one 8^3 lattice in one tile; two 6^3 lattices) advance every tile:
+    bit-identical to the lattices alone."""
+    sl.symlat.load().sl_autotune_forget()
+    for sizes in ([8], [6, 6], [4, 8, 4]):
+        recipes = _runs("f64", sizes, base_seed=20120600)
+        alone = [sl.from_recipe(r) for r in recipes]
+        mixed = [sl.from_recipe(r) for r in recipes]
+        b = sl.Batch()
+        for m in mixed:
+            b.add(m)
+        for a, m in zip(alone, mixed):
+            _, vx, _, _, pf = m.tile()
+            for lat in (m, a):
+                lat.set_tile(16, vx, lat.n, pf)   # the whole lattice in one tile
+        start = [m.get_fields()[0] for m in mixed]
+        tiles = sum(_tiles(m) for m in mixed)
+        say("sizes", sizes, "tiles", tiles, "grid", b.grid())
+        assert tiles == len(sizes) and b.grid() == (0, tiles)
+        b.step(5, 0.005, 4)
+        for a in alone:
+            a.evolve(5, 0.005, 4)
+        b.synchronize()
+        for a, m, f0 in zip(alone, mixed, start):
+            assert _same(a, m), sizes
+            assert not np.array_equal(f0, m.get_fields()[0])   # every lattice moved
+        b.close()
