@@ -55,6 +55,50 @@ class Request:
         self.transient = transient_bytes(**cfg)
 
 
+class HandlePool:
+    """Lattice handles of retired runs, kept for later requests with the
+    same configuration (re-initialised in place, no device allocation).
+    serve() makes one for the call and releases it at the end; a caller
+    that passes its own keeps the handles between calls, as a server does
+    between bursts of requests, and releases them with close()."""
+
+    def __init__(self):
+        self.kept = {}   # configuration -> [(lattice, bytes)]
+        self.bytes = 0   # device bytes the kept handles hold
+
+    def __len__(self):
+        return sum(len(v) for v in self.kept.values())
+
+    def spare_bytes(self, config):
+        """Bytes of the handle take(config) would return, or None."""
+        v = self.kept.get(config)
+        return v[-1][1] if v else None
+
+    def take(self, config):
+        lat, b = self.kept[config].pop()
+        self.bytes -= b
+        return lat
+
+    def put(self, config, lat, nbytes):
+        self.kept.setdefault(config, []).append((lat, nbytes))
+        self.bytes += nbytes
+
+    def release_largest(self):
+        """Release one kept handle of the configuration whose handles are
+        largest (to make room for a request of another configuration)."""
+        key = max((k for k in self.kept if self.kept[k]), key=lambda k: self.kept[k][-1][1])
+        lat, b = self.kept[key].pop()
+        lat.close()
+        self.bytes -= b
+
+    def close(self):
+        for v in self.kept.values():
+            for lat, _ in v:
+                lat.close()
+        self.kept = {}
+        self.bytes = 0
+
+
 def _resident_bytes(req, history):
     """Device bytes a served run holds while resident (with its per-step
     background record when history is on: 3 doubles per step)."""
@@ -62,7 +106,7 @@ def _resident_bytes(req, history):
 
 
 def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
-          keep_fields=False, tune=True, history=False, clock=time.perf_counter,
+          keep_fields=False, tune=True, history=False, pool=None, clock=time.perf_counter,
           sleep=time.sleep):
     """Run the request loop to completion.  Returns (results, stats).
 
@@ -77,7 +121,9 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
     Handles of retired runs are kept and re-initialised for later requests
     with the same configuration (no device allocation or release on that
     path); kept handles count against the memory budget and are released
-    when an admission needs their memory, and all at the end.
+    when an admission needs their memory.  pool: a HandlePool that supplies
+    and keeps the handles beyond this call (released by its owner); without
+    one, the call's own pool is released at the end.
 
     results: one dict per request with id, n, arrival, admitted, completed,
     latency (s, completion - arrival), eta, a, p_a, efolds = ln a, the pass
@@ -90,15 +136,16 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
     waiting = deque()
     active = {}  # id -> [request, lattice, steps_done, admitted_at]
     results = []
+    own_pool = pool is None
+    if own_pool:
+        pool = HandlePool()
     if hbm_budget is None:
         free, _ = device_memory()
-        hbm_budget = int(0.9 * free)
+        hbm_budget = int(0.9 * (free + pool.bytes))   # kept handles are counted below
     used = 0        # resident runs
     deferred = 0
     peak = 0
     reused = 0
-    pool = {}       # configuration -> [(lattice, bytes)] of retired runs
-    pooled = 0      # bytes held by kept handles
     last_done = 0.0
     batch = Batch()
     tuned = not tune
@@ -118,23 +165,22 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
                     raise ValueError("request %r needs %d bytes, more than the budget %d"
                                      % (req.id, need + req.transient, hbm_budget))
                 reserve = max([req.transient] + [a[0].transient for a in active.values()])
-                spare = pool.get(_config(req.recipe))
-                if spare:
-                    if used + pooled - spare[-1][1] + need + reserve > hbm_budget:
+                cfg = _config(req.recipe)
+                spare = pool.spare_bytes(cfg)
+                if spare is not None:
+                    if used + pool.bytes - spare + need + reserve > hbm_budget:
                         deferred += 1
                         break
-                    lat, b = spare.pop()
-                    pooled -= b
+                    lat = pool.take(cfg)
                     reset_from_recipe(lat, req.recipe)
+                    if not history:
+                        lat.set_history(0)   # a kept handle may still hold a record
                     reused += 1
                 else:
                     # release kept handles of other configurations while short of memory
-                    while used + pooled + need + reserve > hbm_budget and pooled > 0:
-                        key = max((k for k in pool if pool[k]), key=lambda k: pool[k][-1][1])
-                        old, b = pool[key].pop()
-                        old.close()
-                        pooled -= b
-                    if used + pooled + need + reserve > hbm_budget:
+                    while used + pool.bytes + need + reserve > hbm_budget and pool.bytes > 0:
+                        pool.release_largest()
+                    if used + pool.bytes + need + reserve > hbm_budget:
                         deferred += 1
                         break
                     lat = from_recipe(req.recipe)
@@ -177,16 +223,14 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
                     last_done = done_at
                     batch.remove(lat)
                     b = _resident_bytes(req, history)
-                    pool.setdefault(_config(req.recipe), []).append((lat, b))
+                    pool.put(_config(req.recipe), lat, b)
                     used -= b
-                    pooled += b
                     del active[rid]
     finally:
         for entry in active.values():
             entry[1].close()
-        for kept in pool.values():
-            for lat, _ in kept:
-                lat.close()
+        if own_pool:
+            pool.close()
         batch.close()
     wall = clock() - t0
     makespan = last_done if results else wall

@@ -213,3 +213,28 @@ def test_tuning_once_per_run_kind(fake):
     serve.serve([_req(1, 32, 0.0, 10)], 0.005, 4, hbm_budget=10 ** 9, clock=fake,
                 sleep=fake.sleep)
     assert serve._TUNED == before
+
+
+def test_a_caller_pool_keeps_handles_between_calls(fake):
+    """A HandlePool passed by the caller supplies and keeps the handles: a
+    second call with the same configurations creates none (every request
+    re-initialises a kept handle, and one kept from a run with a record
+    drops it when the new run keeps none), and nothing is released until
+    the pool is closed."""
+    pool = serve.HandlePool()
+    res, st = serve.serve([_req(i, 32, 0.0, 20) for i in range(3)], 0.005, 4, max_slots=4,
+                          tick_steps=20, hbm_budget=10 ** 9, history=True, pool=pool,
+                          clock=fake, sleep=fake.sleep)
+    assert st["reused"] == 0 and len(FakeLattice.made) == 3 and len(pool) == 3
+    assert not any(m.closed for m in FakeLattice.made)
+    assert all(m.cap == 20 for m in FakeLattice.made)
+    assert pool.bytes == 3 * (100 * 32 + 24 * 20)
+    res, st = serve.serve([_req(i, 32, 0.0, 20) for i in range(3)], 0.005, 4, max_slots=4,
+                          tick_steps=20, hbm_budget=10 ** 9, pool=pool, clock=fake,
+                          sleep=fake.sleep)
+    assert st["reused"] == 3 and st["runs"] == 3 and len(FakeLattice.made) == 3
+    assert all(m.inits == 2 and m.cap == 0 for m in FakeLattice.made)
+    assert len(pool) == 3 and pool.bytes == 3 * 100 * 32
+    assert not any(m.closed for m in FakeLattice.made)
+    pool.close()
+    assert all(m.closed for m in FakeLattice.made) and len(pool) == 0 and pool.bytes == 0
