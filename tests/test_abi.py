@@ -103,6 +103,9 @@ def test_null_handles_are_rejected():
     assert b"NULL" in lib.sl_last_error()
     out = ctypes.c_void_p()
     assert lib.sl_lattice_create(None, None, ctypes.byref(out)) == binding.SL_E_INVALID
+    assert lib.sl_batch_set_grid(None, 0) == binding.SL_E_INVALID
+    assert lib.sl_batch_get_grid(None, None, None) == binding.SL_E_INVALID
+    assert lib.sl_set_tile(None, 8, 1, 0, 1) == binding.SL_E_INVALID
 
 
 def test_vectors_of_the_wrong_length_are_refused_before_the_call():

@@ -97,6 +97,13 @@ def test_batch_rejects_mismatched_members():
     osc = sl.from_recipe(synth.oscillon(n=32))
     with pytest.raises(sl.SymlatError):
         b.add(osc)                   # different potential family
+    for bad in (-1, (1 << 24) + 1):
+        with pytest.raises(sl.SymlatError):
+            b.set_grid(bad)
+    assert b.grid() == (0, sum(_tiles(m) for m in b.members))
+    for tx in (7, 65):
+        with pytest.raises(sl.SymlatError):
+            a.set_tile(tx, 1, 0, a.tile()[4])
 
 
 def test_batch_autotune_keeps_state_and_equals_alone():
