@@ -82,12 +82,17 @@ def measured_traffic(workload, precision, tile):
     return None
 
 
-def measure(sl, recipe, steps, warmup, tile=None, fields=None):
+def measure(sl, recipe, steps, warmup, tile=None, fields=None, diag=None):
     """Autotune (or fix) the pass shape, time `steps` steps after a warm-up,
     then time the fused passes with HIP events over a second region of the
     same length.  With a dict `fields`, the final (phi, pi) are stored in it
-    as FP64 host arrays."""
+    as FP64 host arrays; with a dict `diag`, the wall time of creating the
+    lattice with its initial state and the median wall time of an energies
+    call (the observables pass and its read-back) are stored in it."""
+    t_init = time.perf_counter()
     lat = sl.from_recipe(recipe)
+    lat.synchronize()
+    init_s = time.perf_counter() - t_init
     order, dt = recipe["order"], recipe["dt"]
     if tile:
         tx, vx, tz, pf = (int(x) for x in tile.split(","))
@@ -110,6 +115,14 @@ def measure(sl, recipe, steps, warmup, tile=None, fields=None):
     passes, pass_ms = lat.kernel_timing()
     lat.set_kernel_timing(False)
     e = lat.energies()
+    if diag is not None:
+        ts = []
+        for _ in range(5):
+            t = time.perf_counter()
+            lat.energies()
+            ts.append(time.perf_counter() - t)
+        diag["init_s"] = init_s
+        diag["energies_s"] = sorted(ts)[len(ts) // 2]
     tile = lat.tile()
     if fields is not None:
         fields["phi"], fields["pi"] = lat.get_fields()
@@ -426,8 +439,10 @@ def main():
                            precision=args.precision)
     log("workload", recipe["workload"], args.n, "order", args.order, args.precision)
     f64_fields = {}
+    diag = {}
     wall, passes, pass_ms, e, tile = measure(sl, recipe, args.steps, args.warmup, args.tile,
-                                             fields=f64_fields if args.precision == "f64" else None)
+                                             fields=f64_fields if args.precision == "f64" else None,
+                                             diag=diag)
     nf = recipe["nfields"]
     n3 = args.n ** 3
     b = 8 if args.precision == "f64" else 4
@@ -464,6 +479,11 @@ def main():
                      "bytes_per_launch": bytes_per_pass},
         "friedmann_residual": e["friedmann_residual"],
         "stage_updates_per_s": value * stages,
+        # off the step path: the initial state (vacuum modes, DFTs, constraint)
+        # and the observables pass (reads phi and pi once: 2 b N_f n^3 bytes)
+        "diagnostics": {"init_ms": diag["init_s"] * 1e3,
+                        "energies_ms": diag["energies_s"] * 1e3,
+                        "energies_read_GBs": 2 * b * nf * n3 / diag["energies_s"] / 1e9},
     }
     copy_gbs = sl.symlat.hbm_copy_bench(1 << 31, 10)
     out["roofline"]["copy_GBs"] = copy_gbs

@@ -9,6 +9,11 @@ namespace symlat {
 namespace {
 
 constexpr int kDiagBlocksMax = 1024;
+// target tile count of the 7-point observables pass: two tiles per CU
+// (measured at 256^3: 2048 and 1024 tiles took 10 % and 6 % longer; a tile
+// writes 2 nsums doubles of partials and the buffer holds 4096 tiles of
+// the largest count, the most that n = 1024 makes)
+constexpr int kDiagTiles = 512;
 
 struct Bufs {
   const void* phi[2];
@@ -141,6 +146,173 @@ __global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScala
   }
 }
 
+// The same sums for the 7-point stencil, walked like the fused pass: a
+// workgroup owns a kEX x kEY column tile (one wavefront per row) and marches
+// tz planes up in z.  Each lane keeps the drifted field of its site at z-1,
+// z, z+1 in registers; plane z goes to LDS (double-buffered, one barrier per
+// plane) with a one-cell periodic ring of halo cells that designated lanes
+// load, so every plane of the tile is read from memory once.  The loads run
+// one plane ahead of the arithmetic (own column two planes ahead, halo one).
+// Per site the terms and their order are those of energies_kernel; a lane
+// adds its sites' terms plainly over the chunk (at most tz of each) and the
+// lanes' and tiles' totals are combined with compensation.
+constexpr int kEX = 64, kEY = kBlock / kEX;
+constexpr int kELX = kEX + 2, kEPlane = kELX * (kEY + 2);
+
+template <typename T, int NF, int KIND>
+__global__ __launch_bounds__(kBlock) void energies7_kernel(Bufs B, const DevScalars* sc,
+                                                          PotArgs prm, int n, int zs, int tz,
+                                                          double* partials) {
+  constexpr int NV = nsums<NF>();
+  __shared__ KSum scratch[4 * NV];
+  __shared__ double lds[2][NF][kEPlane];
+  const int par = sc->parity;
+  const T* __restrict__ phi = static_cast<const T*>(B.phi[par]);
+  const T* __restrict__ pi = static_cast<const T*>(B.pi[par]);
+  const double c = sc->c_pend;
+  PotT<double> pot;
+#pragma unroll
+  for (int i = 0; i < kMaxFields; ++i) pot.p[i] = prm.p[i];
+  const size_t n2 = size_t(n) * n;
+  double shift[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) shift[i] = fma(c, double(pi[i * n2]), double(phi[i * n2]));
+
+  const int ntx = (n + kEX - 1) / kEX, nty = (n + kEY - 1) / kEY;
+  int b = blockIdx.x;
+  const int xt = b % ntx;
+  b /= ntx;
+  const int yt = b % nty;
+  const int zt = b / nty;
+  const int x0 = xt * kEX, y0 = yt * kEY, z0 = zt * tz;
+  const int wx = min(kEX, n - x0), wy = min(kEY, n - y0), zend = min(z0 + tz, n);
+  const int tid = int(threadIdx.x), tx = tid % kEX, ty = tid / kEX;
+  const bool active = tx < wx && ty < wy;
+  const int own = (ty + 1) * kELX + tx + 1;
+  // every lane issues the same loads (idle lanes read the tile's first
+  // column, in range and unused), so that no branch around them makes the
+  // compiler wait for the loads in flight
+  const size_t r = active ? size_t(y0 + ty) * n + (x0 + tx) : size_t(y0) * n + x0;
+
+  // halo job: the rows above and below, the columns left and right
+  bool hjob = false;
+  int hl = 0;
+  size_t hr = r;
+  if (tid < kEX) {
+    if (tid < wx) { hjob = true; hr = size_t((y0 - 1 + n) % n) * n + x0 + tid; hl = tid + 1; }
+  } else if (tid < 2 * kEX) {
+    const int t = tid - kEX;
+    if (t < wx) { hjob = true; hr = size_t((y0 + wy) % n) * n + x0 + t; hl = (wy + 1) * kELX + t + 1; }
+  } else if (tid < 2 * kEX + kEY) {
+    const int q = tid - 2 * kEX;
+    if (q < wy) { hjob = true; hr = size_t(y0 + q) * n + (x0 - 1 + n) % n; hl = (q + 1) * kELX; }
+  } else if (tid < 2 * kEX + 2 * kEY) {
+    const int q = tid - 2 * kEX - kEY;
+    if (q < wy) {
+      hjob = true;
+      hr = size_t(y0 + q) * n + (x0 + wx) % n;
+      hl = (q + 1) * kELX + wx + 1;
+    }
+  }
+
+  auto wrapz = [n](int zz) { return zz < 0 ? zz + n : (zz >= n ? zz - n : zz); };
+  auto load = [&](int zz, int i, size_t rr, double& p) {
+    const size_t o = (size_t(zz) * zs + i) * n2 + rr;
+    p = double(pi[o]);
+    return double(phi[o]);
+  };
+
+  double part[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) part[k] = 0.0;
+  // drifted field at z-1, z, z+1 and momenta at z, z+1 of the own site;
+  // drifted halo cell of plane z
+  double fm[NF], fc[NF], fp[NF], pc[NF], pp[NF], hc[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    double p = 0.0;
+    const double f = load(wrapz(z0 - 1), i, r, p);
+    fm[i] = fma(c, p, f);
+    const double g = load(z0, i, r, pc[i]);
+    fc[i] = fma(c, pc[i], g);
+    const double h = load(wrapz(z0 + 1), i, r, pp[i]);
+    fp[i] = fma(c, pp[i], h);
+    const double hh = load(z0, i, hr, p);
+    hc[i] = fma(c, p, hh);
+  }
+  int buf = 0;
+  for (int z = z0; z < zend; ++z) {
+    // next iteration's loads; past the chunk end they re-read the last
+    // plane they need (in range, unused)
+    double fn[NF], pn[NF], hn[NF], hq[NF];
+    const int z1 = min(z + 1, zend - 1), z2 = wrapz(min(z + 2, zend));
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      fn[i] = load(z2, i, r, pn[i]);
+      hn[i] = load(z1, i, hr, hq[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      if (active) lds[buf][i][own] = fc[i];
+      if (hjob) lds[buf][i][hl] = hc[i];
+    }
+    __syncthreads();
+    if (active) {
+      double f[NF];
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        const double* L = lds[buf][i];
+        const double fcv = fc[i];
+        // neighbours in the order x-1, x+1, y-1, y+1, z-1, z+1
+        const double nb[6] = {L[own - 1], L[own + 1], L[own - kELX], L[own + kELX], fm[i], fp[i]};
+        double D = -6.0 * fcv, G = 0.0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          D += nb[q];
+          const double d = nb[q] - fcv;
+          G += d * d;
+        }
+        G = 0.5 * G;
+        part[5 * i + 0] += pc[i] * pc[i];
+        part[5 * i + 1] += G;
+        const double ds = fcv - shift[i];
+        part[5 * i + 2] += ds;
+        part[5 * i + 3] += ds * ds;
+        part[5 * i + 4] += fcv * D;
+        f[i] = fcv;
+      }
+      double V, dV[NF];
+      potential<KIND, NF, double>(f, pot, V, dV);
+      part[5 * NF] += V;
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      fm[i] = fc[i];
+      fc[i] = fp[i];
+      pc[i] = pp[i];
+      fp[i] = fma(c, pn[i], fn[i]);
+      pp[i] = pn[i];
+      hc[i] = fma(c, hq[i], hn[i]);
+    }
+    buf ^= 1;
+  }
+  KSum acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    acc[k] = KSum{0.0, 0.0};
+    kadd(acc[k], part[k]);
+  }
+  block_reduce<NV>(acc, scratch);
+  if (threadIdx.x == 0) {
+    double* out = partials + size_t(blockIdx.x) * 2 * NV;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      out[2 * k] = acc[k].s;
+      out[2 * k + 1] = acc[k].c;
+    }
+  }
+}
+
 // Reduce energies partials, compute observables; mode 1 also solves the
 // constraint H = 0 for p_a (expanding branch) and sets S2.
 template <int NF>
@@ -239,10 +411,23 @@ template <typename T, int NF, int KIND>
 hipError_t energies_t(const LatView& v, double* sums, sl_energies_t* out, int mode, hipStream_t s) {
   const Bufs B = bufs_of(v);
   const size_t n3 = size_t(v.n) * v.n * v.n;
-  int nb = int((n3 + kBlock - 1) / kBlock);
-  if (nb > kDiagBlocksMax) nb = kDiagBlocksMax;
-  hipLaunchKernelGGL((energies_kernel<T, NF, KIND>), dim3(nb), dim3(kBlock), 0, s, B, v.sc,
-                     v.prm, v.n, v.zs, v.st, v.partials);
+  int nb = 0;
+  if (v.st.kind == 0) {
+    // z-chunks so that the tiles number about kDiagTiles (at most one chunk
+    // per plane)
+    const int cols = ((v.n + kEX - 1) / kEX) * ((v.n + kEY - 1) / kEY);
+    int ntz = kDiagTiles / cols;
+    ntz = ntz < 1 ? 1 : (ntz > v.n ? v.n : ntz);
+    const int tz = (v.n + ntz - 1) / ntz;
+    nb = cols * ((v.n + tz - 1) / tz);
+    hipLaunchKernelGGL((energies7_kernel<T, NF, KIND>), dim3(nb), dim3(kBlock), 0, s, B, v.sc,
+                       v.prm, v.n, v.zs, tz, v.partials);
+  } else {
+    nb = int((n3 + kBlock - 1) / kBlock);
+    if (nb > kDiagBlocksMax) nb = kDiagBlocksMax;
+    hipLaunchKernelGGL((energies_kernel<T, NF, KIND>), dim3(nb), dim3(kBlock), 0, s, B, v.sc,
+                       v.prm, v.n, v.zs, v.st, v.partials);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((energies_finalize<NF>), dim3(1), dim3(kBlock), 0, s, v.partials, nb, v.sc,
