@@ -16,6 +16,7 @@ Prints one JSON line:
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -87,8 +88,9 @@ def measure(sl, recipe, steps, warmup, tile=None, fields=None, diag=None):
     then time the fused passes with HIP events over a second region of the
     same length.  With a dict `fields`, the final (phi, pi) are stored in it
     as FP64 host arrays; with a dict `diag`, the wall time of creating the
-    lattice with its initial state and the median wall time of an energies
-    call (the observables pass and its read-back) are stored in it."""
+    lattice with its initial state and the median wall times of an energies
+    call (the observables pass and its read-back) and of a spectra call are
+    stored in it."""
     t_init = time.perf_counter()
     lat = sl.from_recipe(recipe)
     lat.synchronize()
@@ -123,6 +125,15 @@ def measure(sl, recipe, steps, warmup, tile=None, fields=None, diag=None):
             ts.append(time.perf_counter() - t)
         diag["init_s"] = init_s
         diag["energies_s"] = sorted(ts)[len(ts) // 2]
+        # spectra of one field (DFT on the device, binned; Sec. 2.4): median
+        # of three calls
+        nbins = int(math.ceil(math.sqrt(3) * recipe["n"] / 2)) + 2   # up to the corner mode
+        ts = []
+        for _ in range(3):
+            t = time.perf_counter()
+            lat.spectra(0, nbins)
+            ts.append(time.perf_counter() - t)
+        diag["spectra_s"] = sorted(ts)[1]
     tile = lat.tile()
     if fields is not None:
         fields["phi"], fields["pi"] = lat.get_fields()
@@ -483,7 +494,8 @@ def main():
         # and the observables pass (reads phi and pi once: 2 b N_f n^3 bytes)
         "diagnostics": {"init_ms": diag["init_s"] * 1e3,
                         "energies_ms": diag["energies_s"] * 1e3,
-                        "energies_read_GBs": 2 * b * nf * n3 / diag["energies_s"] / 1e9},
+                        "energies_read_GBs": 2 * b * nf * n3 / diag["energies_s"] / 1e9,
+                        "spectra_ms_one_field": diag["spectra_s"] * 1e3},
     }
     copy_gbs = sl.symlat.hbm_copy_bench(1 << 31, 10)
     out["roofline"]["copy_GBs"] = copy_gbs

@@ -128,6 +128,66 @@ __global__ __launch_bounds__(kBlock) void dft_axis_kernel(int n, const double2* 
   out[e] = make_double2(re, im);
 }
 
+// The same transform for n = 2^L by the Stockham radix-2 recursion: for
+// sub-transform size m = 1, 2, .., n/2 (l = n / 2m), the pairs x[k + j m]
+// and x[k + j m + n/2] (j < l, k < m) give y[k + 2 j m] = sum and
+// y[k + 2 j m + m] = tw[j m] (difference); after L stages the output is in
+// natural order.  A workgroup loads `lines` whole lines into LDS (for the y
+// and z axes, `lines` neighbouring columns x, so the loads are coalesced),
+// runs the stages between two LDS buffers and writes the lines back.
+__global__ __launch_bounds__(kBlock) void fft_axis_kernel(int n, int logn, int lines,
+                                                         const double2* __restrict__ in,
+                                                         double2* __restrict__ out,
+                                                         const double2* __restrict__ tw,
+                                                         int axis) {
+  extern __shared__ double2 sbuf[];  // two buffers of lines * n values
+  const int tid = int(threadIdx.x);
+  const size_t n2 = size_t(n) * n;
+  const int total = lines * n;
+  size_t base, jstride, lstride;
+  if (axis == 0) {  // rows: line-major and contiguous
+    base = size_t(blockIdx.x) * total;
+    jstride = 1;
+    lstride = size_t(n);
+  } else {          // `lines` neighbouring x at one z (axis 1) or one y (axis 2)
+    const int groups = n / lines;
+    const int xg = int(blockIdx.x % unsigned(groups)), other = int(blockIdx.x / unsigned(groups));
+    lstride = 1;
+    jstride = axis == 1 ? size_t(n) : n2;
+    base = (axis == 1 ? size_t(other) * n2 : size_t(other) * n) + size_t(xg) * lines;
+  }
+  double2* x = sbuf;
+  double2* y = sbuf + total;
+  for (int idx = tid; idx < total; idx += kBlock) {
+    int l, j;
+    if (axis == 0) { l = idx >> logn; j = idx & (n - 1); } else { j = idx / lines; l = idx - j * lines; }
+    x[l * n + j] = in[base + size_t(l) * lstride + size_t(j) * jstride];
+  }
+  __syncthreads();
+  const int half = n >> 1;
+  for (int s = 0; s < logn; ++s) {
+    const int m = 1 << s;
+    for (int b = tid; b < lines * half; b += kBlock) {
+      const int line = b >> (logn - 1), t = b & (half - 1);
+      const int j = t >> s, k = t & (m - 1);
+      const double2 w = tw[j * m];
+      const double2 c0 = x[line * n + k + j * m], c1 = x[line * n + k + j * m + half];
+      const double dr = c0.x - c1.x, di = c0.y - c1.y;
+      y[line * n + k + 2 * j * m] = make_double2(c0.x + c1.x, c0.y + c1.y);
+      y[line * n + k + 2 * j * m + m] = make_double2(w.x * dr - w.y * di, w.x * di + w.y * dr);
+    }
+    __syncthreads();
+    double2* t2 = x;
+    x = y;
+    y = t2;
+  }
+  for (int idx = tid; idx < total; idx += kBlock) {
+    int l, j;
+    if (axis == 0) { l = idx >> logn; j = idx & (n - 1); } else { j = idx / lines; l = idx - j * lines; }
+    out[base + size_t(l) * lstride + size_t(j) * jstride] = x[l * n + j];
+  }
+}
+
 template <typename T>
 __global__ void add_real_kernel(void* phi0, const double2* F, size_t n3, size_t n2, int zs,
                                 int field, double base, double scale) {
@@ -285,6 +345,21 @@ hipError_t launch_twiddles(int n, int sign, double2* tw, hipStream_t s) {
 
 hipError_t launch_dft_axis(int n, const double2* in, double2* out, const double2* tw, int axis,
                            hipStream_t s) {
+  if (n >= 2 && (n & (n - 1)) == 0) {
+    // power of two: the radix-2 kernel, lines * n <= 2048 (two 32 KB LDS
+    // buffers) and at most n lines, so that the y and z axes group whole
+    // columns
+    int logn = 0;
+    while ((1 << logn) < n) ++logn;
+    int lines = 2048 / n;
+    if (lines > n) lines = n;
+    if (lines < 1) lines = 1;
+    const unsigned nb = unsigned(size_t(n) * n / lines);
+    hipLaunchKernelGGL(fft_axis_kernel, dim3(nb), dim3(kBlock),
+                       size_t(2) * lines * n * sizeof(double2), s, n, logn, lines, in, out, tw,
+                       axis);
+    return hipGetLastError();
+  }
   const size_t n3 = size_t(n) * n * n;
   const size_t nb = (n3 + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(dft_axis_kernel, dim3(unsigned(nb)), dim3(kBlock), size_t(n) * sizeof(double2),

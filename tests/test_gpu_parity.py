@@ -282,8 +282,10 @@ def test_spectrum_matches_oracle(n):
         np.testing.assert_allclose(P, Po, rtol=1e-8, atol=1e-12 * Po.max())
 
 
-@pytest.mark.parametrize("n", [24, 15])
+@pytest.mark.parametrize("n", [24, 15, 32, 64])
 def test_vacuum_init_matches_oracle(n):
+    """Powers of two take the radix-2 transform, other sizes the direct
+    one: both against the oracle's initial state."""
     c = synth.preheat(n=n)
     c["amplitude"] = 1e-3
     g = sl.from_recipe(c)
