@@ -802,22 +802,25 @@ sl_status sl_linear_evolve(sl_linear* L, int64_t steps, double dt, int32_t order
       float best = 1e30f;
       int win = 1;
       hipError_t err = hipSuccess;
-      for (int v = 0; v < kGrowthVariants && err == hipSuccess; ++v) {
-        err = hipEventRecord(t0, L->stream);
-        if (err == hipSuccess) {
-          hipLaunchKernelGGL(f.growth[v], dim3(grid_for_variant(v)), dim3(kBlock), 0, L->stream,
-                             L->M, L->k2, L->ncls, tb, k * W.s, 1);
-          err = hipGetLastError();
+      // best of three launches per variant, variants interleaved, so that a
+      // slow first launch does not decide
+      for (int rep = 0; rep < 3 && err == hipSuccess; ++rep)
+        for (int v = 0; v < kGrowthVariants && err == hipSuccess; ++v) {
+          err = hipEventRecord(t0, L->stream);
+          if (err == hipSuccess) {
+            hipLaunchKernelGGL(f.growth[v], dim3(grid_for_variant(v)), dim3(kBlock), 0, L->stream,
+                               L->M, L->k2, L->ncls, tb, k * W.s, 1);
+            err = hipGetLastError();
+          }
+          if (err == hipSuccess) err = hipEventRecord(t1, L->stream);
+          if (err == hipSuccess) err = hipEventSynchronize(t1);
+          float ms = 0.0f;
+          if (err == hipSuccess) err = hipEventElapsedTime(&ms, t0, t1);
+          if (err == hipSuccess && ms < best) {
+            best = ms;
+            win = v;
+          }
         }
-        if (err == hipSuccess) err = hipEventRecord(t1, L->stream);
-        if (err == hipSuccess) err = hipEventSynchronize(t1);
-        float ms = 0.0f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, t0, t1);
-        if (err == hipSuccess && ms < best) {
-          best = ms;
-          win = v;
-        }
-      }
       (void)hipEventDestroy(t0);
       (void)hipEventDestroy(t1);
       if (err != hipSuccess) return fail(SL_E_DEVICE, "growth variant timing: %s", hipGetErrorString(err));
