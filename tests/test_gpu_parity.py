@@ -267,7 +267,7 @@ def test_energies_match_oracle():
     assert abs(eg["h_total"] - eo["h_total"]) <= 1e-10 * scale
 
 
-@pytest.mark.parametrize("n", [16, 15])
+@pytest.mark.parametrize("n", [16, 15, 128])
 def test_spectrum_matches_oracle(n):
     c, phi, pi = _preheat_state(n, seed=14, amp=1e-2)
     o, g = _pair(c, phi, pi)
