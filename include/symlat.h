@@ -361,7 +361,8 @@ sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order
  * z-chunks); for the three fastest, per member size (largest share
  * of sites first, two rounds of coordinate descent) the same tx candidates
  * as sl_autotune and
- * z-chunks n/{1, 2, 4, 8} are tried for all members of that size, timing
+ * z-chunks n/{1, 2, 4, 8} (and n/3, n/6 where they divide n) are tried for
+ * all members of that size, timing
  * the batched pass alone (best of `reps`
  * HIP-event timings of two passes; the members' states are left
  * unchanged), and keep a shape only if it is at least 0.5 % faster; last,

@@ -1695,7 +1695,8 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
         int btx = ref_tx, btz = ref_tz;
         for (int tx : tx_candidates(n, vx)) {
           if (B->st_kind != 0 && 2 * tx + 2 * (kBlock / tx) + 4 > kBlock) continue;
-          for (int d : {1, 2, 4, 8}) {
+          for (int d : {1, 2, 3, 4, 6, 8}) {
+            if (d % 3 == 0 && n % d != 0) continue;  // thirds only where they divide n
             const int tz = n / d;
             if (tz < 4 && d != 1) continue;
             if (tx == ref_tx && tz == ref_tz) continue;
