@@ -51,3 +51,31 @@ def test_admission_by_footprint():
     # delta-N output: one e-fold count per run, ordered by the initial field
     ef = [r["efolds"] for r in results]
     assert all(e > 0 for e in ef)
+
+
+def test_pooled_handles_between_calls_equal_alone():
+    """Handles kept in a caller's pool serve the next call's requests (no
+    new handle made) and their results equal the same runs alone, with and
+    without the per-step record in the earlier call."""
+    sizes = [32, 64, 32, 64]
+    pool = serve.HandlePool()
+    first, s1 = serve.serve(_requests([0.0] * 4, sizes, steps=30), dt=0.005, order=4,
+                            max_slots=4, tick_steps=10, history=True, pool=pool)
+    assert s1["reused"] == 0 and len(pool) == 4
+    reqs = _requests([0.0, 0.0, 0.01, 0.02], sizes, steps=40)
+    results, s2 = serve.serve(reqs, dt=0.005, order=4, max_slots=4, tick_steps=20,
+                              keep_fields=True, pool=pool)
+    say("pooled serve stats", s2)
+    assert s2["reused"] == 4 and s2["runs"] == 4 and len(pool) == 4
+    for res in results:
+        req = reqs[res["id"]]
+        alone = sl.from_recipe(req.recipe)
+        tx, vx, _, tz, pf = res["tile"]
+        alone.set_tile(tx, vx, tz, pf)
+        alone.evolve(req.steps, 0.005, 4)
+        phi, pi = alone.get_fields()
+        assert np.array_equal(phi, res["phi"]) and np.array_equal(pi, res["pi"]), res["id"]
+        assert alone.background() == (res["eta"], res["a"], res["p_a"])
+        alone.close()
+    pool.close()
+    assert len(pool) == 0
