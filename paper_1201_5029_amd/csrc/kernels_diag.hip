@@ -202,7 +202,11 @@ __global__ __launch_bounds__(kBlock) void energies7_kernel(Bufs B, const DevScal
     if (tid < wx) { hjob = true; hr = size_t((y0 - 1 + n) % n) * n + x0 + tid; hl = tid + 1; }
   } else if (tid < 2 * kEX) {
     const int t = tid - kEX;
-    if (t < wx) { hjob = true; hr = size_t((y0 + wy) % n) * n + x0 + t; hl = (wy + 1) * kELX + t + 1; }
+    if (t < wx) {
+      hjob = true;
+      hr = size_t((y0 + wy) % n) * n + x0 + t;
+      hl = (wy + 1) * kELX + t + 1;
+    }
   } else if (tid < 2 * kEX + kEY) {
     const int q = tid - 2 * kEX;
     if (q < wy) { hjob = true; hr = size_t(y0 + q) * n + (x0 - 1 + n) % n; hl = (q + 1) * kELX; }

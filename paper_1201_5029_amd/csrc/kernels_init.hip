@@ -160,7 +160,13 @@ __global__ __launch_bounds__(kBlock) void fft_axis_kernel(int n, int logn, int l
   double2* y = sbuf + total;
   for (int idx = tid; idx < total; idx += kBlock) {
     int l, j;
-    if (axis == 0) { l = idx >> logn; j = idx & (n - 1); } else { j = idx / lines; l = idx - j * lines; }
+    if (axis == 0) {
+      l = idx >> logn;
+      j = idx & (n - 1);
+    } else {
+      j = idx / lines;
+      l = idx - j * lines;
+    }
     x[l * n + j] = in[base + size_t(l) * lstride + size_t(j) * jstride];
   }
   __syncthreads();
@@ -183,7 +189,13 @@ __global__ __launch_bounds__(kBlock) void fft_axis_kernel(int n, int logn, int l
   }
   for (int idx = tid; idx < total; idx += kBlock) {
     int l, j;
-    if (axis == 0) { l = idx >> logn; j = idx & (n - 1); } else { j = idx / lines; l = idx - j * lines; }
+    if (axis == 0) {
+      l = idx >> logn;
+      j = idx & (n - 1);
+    } else {
+      j = idx / lines;
+      l = idx - j * lines;
+    }
     out[base + size_t(l) * lstride + size_t(j) * jstride] = x[l * n + j];
   }
 }

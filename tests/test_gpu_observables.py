@@ -42,7 +42,8 @@ def test_observables_across_tiles(n, kind, precision, steps):
         g.evolve(steps, 0.005, 4)
         o.evolve(steps, 0.005, 4)
     eg, eo = g.energies(), o.energies()
-    say("n", n, kind, precision, "rho", eg["rho"], eo["rho"], "grad", eg["grad"][:nf], eo["grad"][:nf])
+    say("n", n, kind, precision, "rho", eg["rho"], eo["rho"], "grad", eg["grad"][:nf],
+        eo["grad"][:nf])
     for k in ("rho", "pressure", "pot", "hubble", "a", "p_a", "w_eos"):
         assert eg[k] == pytest.approx(eo[k], rel=1e-10, abs=1e-300), k
     for k in ("kin", "grad", "mean", "var"):
