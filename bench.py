@@ -193,7 +193,8 @@ def measure_served(sl, nruns, steps):
                    "one handle per slot in the server's pool; every request re-initialises one",
         "burst": {"makespan_s": burst["makespan_s"], "value": burst["field_site_updates_per_s"],
                   "p50_s": burst["p50_s"], "p99_s": burst["p99_s"], "reused": burst["reused"]},
-        "poisson": {"rate_per_s": 0.8 * capacity, "makespan_s": pois["makespan_s"],
+        "poisson": {"rate_per_s": 0.8 * capacity, "rate_vs_burst_capacity": 0.8,
+                    "makespan_s": pois["makespan_s"],
                     "value": pois["field_site_updates_per_s"], "p50_s": pois["p50_s"],
                     "p99_s": pois["p99_s"], "peak_resident": pois["peak_resident"]},
         "fp64_single_runs": {"wall_s": t64, "value": sups / t64},
