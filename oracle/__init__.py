@@ -18,6 +18,8 @@ composition prescribes, with no merging, fusion or lazy bookkeeping:
                 Fourier-space perturbations, every mode evolved on its own.
 * ``rng``       the counter-based SplitMix64 generator and Box-Muller normals,
                 written from their published definitions.
+* ``deltan``    the separate-universe read-out of a scan: the constraint's
+                total density along a run and the uniform-density e-folds.
 
 Every function is pinned by a ``-m "not gpu"`` test against a closed form, an
 invariant, a printed constant or brute force; see the test modules named
@@ -30,4 +32,4 @@ from .lattice import (  # noqa: F401
     stencil_ok, stencil_max_keff2, keff2_modes, mode_spectra,
 )
 from .linear import LinearLattice  # noqa: F401
-from . import rng  # noqa: F401
+from . import deltan, rng  # noqa: F401

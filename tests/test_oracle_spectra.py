@@ -108,20 +108,48 @@ def test_delta_n_statistics_exact_on_quadratic():
     assert st["runs"] == 40
 
 
-def test_uniform_density_efolds_exact_on_power_law():
-    """Radiation-like expansion a = 1 + c eta: H = c / a^2, rho = 3 m^2 H^2
-    ~ a^-4, so ln rho is linear in ln a and the interpolated crossing is
-    exact; p_a follows from H = -p_a / (6 V_L m^2 a^2)."""
-    from paper_1201_5029_amd import serve
-    n, mpl, c = 8, 0.7, 0.3
+def _radiation_history(n=8, mpl=0.7, c=0.3):
+    """Radiation-like expansion a = 1 + c eta: H = a'/a^2 = c / a^2 and
+    rho = 3 m^2 H^2 ~ a^-4, so ln rho is linear in ln a; p_a follows from
+    a' = -p_a / (6 V_L m^2)."""
     eta = np.arange(1, 200) * 0.05
     a = 1.0 + c * eta
-    hub = c / a ** 2
-    p_a = -hub * 6.0 * n ** 3 * mpl ** 2 * a ** 2
-    rho = serve.friedmann_density(a, p_a, n, mpl)
-    np.testing.assert_allclose(rho, 3 * mpl ** 2 * hub ** 2, rtol=1e-14)
+    p_a = -c * 6.0 * n ** 3 * mpl ** 2 * np.ones_like(a)
+    return n, mpl, c, a, p_a
+
+
+def test_oracle_uniform_density_efolds_exact_on_power_law():
+    """The oracle's constraint density is 3 m^2 (c/a^2)^2 in closed form and
+    its interpolated crossing of a power law is exact."""
+    n, mpl, c, a, p_a = _radiation_history()
+    rho = oracle.deltan.constraint_density(a, p_a, n, mpl)
+    np.testing.assert_allclose(rho, 3 * mpl ** 2 * (c / a ** 2) ** 2, rtol=1e-14)
     rho_ref = 3 * mpl ** 2 * c ** 2 / 2.345 ** 4      # rho at a = 2.345
-    N = serve.uniform_density_efolds(a, rho, rho_ref)
+    N = oracle.deltan.efolds_at_density(a, rho, rho_ref)
     assert N == pytest.approx(math.log(2.345), rel=1e-12)
-    assert math.isnan(serve.uniform_density_efolds(a, rho, rho.min() / 2))
-    assert serve.uniform_density_efolds(a, rho, rho.max() * 2) == pytest.approx(math.log(a[0]))
+    assert math.isnan(oracle.deltan.efolds_at_density(a, rho, rho.min() / 2))
+    assert oracle.deltan.efolds_at_density(a, rho, rho.max() * 2) == pytest.approx(math.log(a[0]))
+
+
+def test_oracle_history_matches_radiation_closed_form():
+    """Fields held at zero with radiation only: a(eta) = a0 + sqrt(rho_r /
+    (3 m^2)) eta exactly, and the recorded constraint density is the
+    radiation density rho_r / a^4 (first Friedmann equation)."""
+    n, mpl, rho_r = 4, 0.9, 0.37
+    lat = oracle.Lattice(n, 3.0, oracle.Potential("free", (1.0,)), mpl=mpl, rho_rad0=rho_r)
+    lat.solve_constraint()
+    eta, a, p_a, rho = oracle.deltan.evolve_recording(lat, 25, 0.05, 4)
+    np.testing.assert_allclose(eta, 0.05 * np.arange(1, 26), rtol=1e-14)
+    np.testing.assert_allclose(a, 1.0 + math.sqrt(rho_r / (3 * mpl ** 2)) * eta, rtol=1e-13)
+    np.testing.assert_allclose(rho, rho_r / a ** 4, rtol=1e-12)
+
+
+def test_served_uniform_density_efolds_equal_oracle():
+    """The serving module's host interpolation gives the oracle's e-folds."""
+    from paper_1201_5029_amd import serve
+    n, mpl, c, a, p_a = _radiation_history()
+    rho = oracle.deltan.constraint_density(a, p_a, n, mpl)
+    for ref in (rho[0] * 2, rho[17], 0.5 * (rho[40] + rho[41]), rho[-1], rho[-1] / 3):
+        got = serve.uniform_density_efolds(a, rho, ref)
+        want = oracle.deltan.efolds_at_density(a, rho, ref)
+        assert (math.isnan(got) and math.isnan(want)) or got == pytest.approx(want, rel=1e-14)

@@ -1,6 +1,7 @@
 """Pins of the oracle's stencils (Sec. 2.1, eq. (2.7), (2.8), (2.17)) and
 potentials (Sec. 3) against closed forms, brute force and complex steps."""
 import itertools
+import os
 
 import numpy as np
 import pytest
@@ -113,6 +114,34 @@ def test_qball_regular_at_origin():
     # u ln u -> 0: the potential is continuous at the origin
     small = np.full((2, 1), 1e-150)
     assert abs(pot.V(small)[0]) < 1e-290
+
+
+def _worked_values():
+    path = os.path.join(os.path.dirname(__file__), "golden", "potential_worked_values.txt")
+    rows = []
+    with open(path) as fh:
+        for line in fh:
+            if not line.strip() or line.startswith("#"):
+                continue
+            tok = line.split()
+            kind, vals = tok[0], [float(t) for t in tok[1:]]
+            nf = 1 if kind == "oscillon" else 2
+            rows.append((kind, vals[:3], vals[3:3 + nf], vals[3 + nf], vals[4 + nf:]))
+    return rows
+
+
+@pytest.mark.parametrize("row", _worked_values(), ids=lambda r: "%s-%s" % (r[0], r[2]))
+def test_oscillon_and_qball_worked_values(row):
+    """Sec. 3.2 and 3.3 potentials at hand-computed points (fixture with the
+    exact derivations): pins the coefficients lam/4 and g/6, the sign of
+    each term, u = (phi1^2 + phi2^2)/2 and the 1 + K + K ln(u/M^2) factor of
+    the Q-ball force, which the complex-step gradient pin cannot tell apart
+    from a consistent slip in V and dV together."""
+    kind, params, phi, V, dV = row
+    pot = oracle.Potential(kind, params)
+    f = np.array(phi, dtype=float).reshape(len(phi), 1)
+    assert float(pot.V(f)[0]) == pytest.approx(V, rel=1e-13, abs=1e-15)
+    np.testing.assert_allclose(pot.dV(f)[:, 0], dV, rtol=1e-13, atol=1e-15)
 
 
 def test_chaotic_potential_closed_form():
