@@ -165,8 +165,7 @@ def measure_served(sl, nruns, steps):
                                    history=True, pool=pool)
     # uniform-density Delta N: ln a where rho = 3 m_pl^2 H^2 first falls to
     # the latest density every run reaches (the largest final density)
-    rho = [serve.friedmann_density(res["history"][1], res["history"][2], recipes[j]["n"],
-                                   recipes[j]["mpl"]) for j, res in enumerate(burst_res)]
+    rho = [res["history"][3] for res in burst_res]    # recorded on the device
     rho_ref = max(r[-1] for r in rho)
     n_ud = [serve.uniform_density_efolds(res["history"][1], rho[j], rho_ref)
             for j, res in enumerate(burst_res)]

@@ -154,8 +154,11 @@ sl_status sl_lattice_create_with_buffers(const sl_config* cfg, void* hip_stream,
 sl_status sl_lattice_destroy(sl_lattice* lat);
 
 /* Select the potential family and copy its nparams parameters (see
- * sl_potential).  SL_E_INVALID if the family does not fit nfields or
- * nparams is wrong.  Must precede sl_init_fluctuations / sl_evolve. */
+ * sl_potential; the models of Sec. 3.1-3.3).  SL_E_INVALID if the family
+ * does not fit nfields or nparams is wrong.  Must precede
+ * sl_init_fluctuations / sl_evolve.  A batch member may take new
+ * parameters of its family (its next batched step uses them; its tile is
+ * kept); SL_E_STATE if it is given another family. */
 sl_status sl_set_potential(sl_lattice* lat, int32_t kind, const double* params, int32_t nparams);
 
 /* Discrete Laplacian of eq. (2.7), from the cubic family the paper draws
@@ -206,7 +209,9 @@ sl_status sl_evolve(sl_lattice* lat, int64_t steps, double dt, int32_t order);
  * copy them to *out; synchronises the stream. */
 sl_status sl_energies(sl_lattice* lat, sl_energies_t* out);
 
-/* Field power spectrum of phi_field: F_n = DFT(phi)/n^3, modes binned by
+/* Field power spectrum of phi_field (the spectra of the post-processing
+ * step, Sec. 2.4; the field of the synchronised state, eq. (2.12)):
+ * F_n = DFT(phi)/n^3, modes binned by
  * |n| rounded half away from zero (decided in integers), the n = 0 mode
  * excluded, modes with bin >= nbins dropped.  k_out[b] = 2 pi <|n|>_b / L,
  * p_out[b] = <|F_n|^2>_b, count_out[b] = number of modes; empty bins are
@@ -230,27 +235,41 @@ sl_status sl_spectra(sl_lattice* lat, int32_t field, int32_t nbins, double* k_ou
                      double* pf_out, double* pe_out, double* pn_out, int64_t* count_out,
                      double* m2eff_out);
 
-/* Copy the synchronised fields to host FP64 arrays of nfields*n^3 each
- * (either pointer may be NULL).  Synchronises. */
+/* Copy the synchronised state -- the lattice fields phi_i and their
+ * canonical momenta pi_i = a^2 phi_i' (eq. (2.12)), the field variables of
+ * the Hamiltonian (2.13), with any pending field drift applied -- to
+ * caller-owned host FP64 arrays of nfields*n^3 each, layout [field][z][y][x]
+ * (either pointer may be NULL).  SL_E_NOMEM if the device staging buffer
+ * cannot be allocated.  Synchronises. */
 sl_status sl_get_fields(sl_lattice* lat, double* phi_out, double* pi_out);
 
-/* Replace the state by host FP64 arrays (rounded to the storage precision),
- * set a and eta = 0 and p_a; p_a = NaN means "solve the constraint H = 0".
- * A potential must be set.  SL_E_INVALID for NULL arrays or a <= 0. */
+/* Replace the state (phi_i, pi_i of eq. (2.12)) by caller-owned host
+ * FP64 arrays of nfields*n^3 each, layout [field][z][y][x] (rounded to the
+ * storage precision), set a, eta = 0 and p_a; p_a = NaN means "solve the
+ * constraint that the Hamiltonian (2.13) vanishes" (the first Friedmann
+ * equation (2.18); expanding branch, p_a < 0).  A potential must be
+ * set.  SL_E_INVALID for NULL arrays or a <= 0; SL_E_STATE without a
+ * potential; SL_E_NONFINITE if the state is not finite or the constraint
+ * has no real p_a. */
 sl_status sl_set_fields(sl_lattice* lat, const double* phi, const double* pi,
                         double a, double p_a);
 
-/* Background history: with capacity > 0, every completed step (alone or in
- * a batch) appends (eta, a, p_a) at its end to a device buffer of that many
- * records (further steps are not recorded); capacity 0 releases it.  The
- * record restarts at 0 entries here and whenever the state is reset
- * (sl_init_fluctuations, sl_set_fields).  sl_get_history copies up to cap
- * records to host arrays and reports the number recorded in *count.  Used
- * for the uniform-density Delta N of a scan (Sec. 2.4): H = -p_a / (6 V_L
- * m_pl^2 a^2) and rho = 3 m_pl^2 H^2 along the run.  Synchronises. */
+/* Background history (for the uniform-density Delta N of a scan over
+ * initial values, Sec. 2.4 and Sec. 4): with capacity > 0, every completed
+ * step (alone or in a batch) appends (eta, a, p_a, rho) at its end to a
+ * device buffer of that many records (further steps are not recorded);
+ * capacity 0 releases it.  rho is the total density on that time slice from
+ * the first Friedmann equation (2.18): rho = 3 m_pl^2 H^2 with the Hubble
+ * rate H = a'/a^2, a' = -p_a / (6 V_L m_pl^2) (eq. (2.14));
+ * 0 in a static background.  The record restarts at 0 entries here and
+ * whenever the state is reset (sl_init_fluctuations, sl_set_fields).
+ * sl_get_history copies up to cap records into four host arrays of cap
+ * entries (caller-owned; all four non-NULL when a record is copied) and
+ * reports the number recorded in *count.  SL_E_NOMEM if the buffer cannot
+ * be allocated (the lattice then records nothing).  Synchronises. */
 sl_status sl_set_history(sl_lattice* lat, int64_t capacity);
-sl_status sl_get_history(sl_lattice* lat, double* eta, double* a, double* p_a, int64_t cap,
-                         int64_t* count);
+sl_status sl_get_history(sl_lattice* lat, double* eta, double* a, double* p_a, double* rho,
+                         int64_t cap, int64_t* count);
 
 /* Conformal time, scale factor and its momentum.  Synchronises. */
 sl_status sl_get_background(sl_lattice* lat, double* eta, double* a, double* p_a);
@@ -259,7 +278,7 @@ sl_status sl_get_background(sl_lattice* lat, double* eta, double* a, double* p_a
 sl_status sl_synchronize(sl_lattice* lat);
 
 /* Device bytes a lattice of this configuration holds from creation to
- * destruction (0 if invalid); sl_set_history adds 24 bytes per record.
+ * destruction (0 if invalid); sl_set_history adds 32 bytes per record.
  * sl_transient_bytes: the most any single call on such a lattice allocates
  * on top while it runs and frees before returning (vacuum or white initial
  * state, sl_set_fields / sl_get_fields staging, sl_spectrum, sl_spectra);

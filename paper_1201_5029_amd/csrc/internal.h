@@ -43,6 +43,9 @@ constexpr int kMaxBins = 2048;
 // x 4 sites x 8 bytes.
 constexpr size_t kSinkBytes = size_t(kBlock) * 2 * kMaxFields * 4 * 8;
 
+// Doubles per background history record: eta, a, p_a, rho.
+constexpr int kHistRecord = 4;
+
 // Sticky device-side error bits in DevScalars::status.
 constexpr int kStatusNonFinite = 1;
 
@@ -62,7 +65,7 @@ struct DevScalars {
   double S3_last;  // last H3 lattice sum (diagnostic)
   int32_t parity;  // which ping-pong buffer holds the state
   int32_t status;  // sticky error bits
-  double* hist;      // optional record of (eta, a, p_a) at the end of each step
+  double* hist;      // optional record of (eta, a, p_a, rho) at the end of each step
   int64_t hist_cap;  // records the buffer holds
   int64_t hist_n;    // records written since the last reset
 };

@@ -667,10 +667,15 @@ __device__ void finalize_body(DevScalars* sc, const double* partials, int nblock
     S.parity ^= 1;
     if (end_of_step) S.eta = S.eta + h;
     if (end_of_step && S.hist != nullptr && S.hist_n < S.hist_cap) {
-      double* r = S.hist + 3 * S.hist_n;
+      // total density on this time slice from the first Friedmann equation
+      // (2.18): rho = 3 m_pl^2 H^2 with H = a'/a^2 and a' = -p_a/(6 V_L m_pl^2)
+      // (eq. (2.14))
+      const double hub = -S.p_a * K.inv6VLm2 / (S.a * S.a);
+      double* r = S.hist + kHistRecord * S.hist_n;
       r[0] = S.eta;
       r[1] = S.a;
       r[2] = S.p_a;
+      r[3] = 3.0 * K.mpl2 * hub * hub;
       S.hist_n = S.hist_n + 1;
     }
     if (has_next) begin_stage(S, K, w_next, h);

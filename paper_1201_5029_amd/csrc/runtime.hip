@@ -435,14 +435,57 @@ sl_status fft_alloc(sl_lattice* L, FftScratch& S) {
 }
 
 // 3-D DFT a -> b (a is clobbered); sign +1: sum f_n exp(+2 pi i n.j/N).
-sl_status dft3(sl_lattice* L, FftScratch& S, int sign) {
+// 3-D DFT of a into b (a is overwritten); tw holds n twiddles.
+sl_status dft3(sl_lattice* L, double2* a, double2* b, double2* tw, int sign) {
   const int n = L->cfg.n;
-  HIP_TRY(launch_twiddles(n, sign, S.tw, L->stream));
-  HIP_TRY(launch_dft_axis(n, S.a, S.b, S.tw, 0, L->stream));
-  HIP_TRY(launch_dft_axis(n, S.b, S.a, S.tw, 1, L->stream));
-  HIP_TRY(launch_dft_axis(n, S.a, S.b, S.tw, 2, L->stream));
+  HIP_TRY(launch_twiddles(n, sign, tw, L->stream));
+  HIP_TRY(launch_dft_axis(n, a, b, tw, 0, L->stream));
+  HIP_TRY(launch_dft_axis(n, b, a, tw, 1, L->stream));
+  HIP_TRY(launch_dft_axis(n, a, b, tw, 2, L->stream));
   return SL_OK;
 }
+
+sl_status dft3(sl_lattice* L, FftScratch& S, int sign) { return dft3(L, S.a, S.b, S.tw, sign); }
+
+size_t spectrum_part_bytes(int n, int nbins) {
+  return size_t(spectrum_blocks(n)) * 3 * size_t(nbins) * sizeof(double);
+}
+
+sl_status spectrum_check(sl_lattice* L, int field, int nbins, const double* k_out,
+                         const double* p_out, const int64_t* count_out) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  if (field < 0 || field >= L->cfg.nfields) return fail(SL_E_INVALID, "field index out of range");
+  if (nbins < 1 || nbins > kMaxBins) return fail(SL_E_INVALID, "nbins must be in [1, %d]", kMaxBins);
+  if (!k_out || !p_out || !count_out) return fail(SL_E_INVALID, "output array is NULL");
+  return SL_OK;
+}
+
+// Field power spectrum with caller-provided device scratch: a, b (n^3
+// complex each), tw (n complex), part (spectrum_part_bytes).  Allocates no
+// device memory; synchronises the lattice's stream.
+sl_status spectrum_run(sl_lattice* L, int field, int nbins, double2* a, double2* b, double2* tw,
+                       double* part, double* k_out, double* p_out, int64_t* count_out) {
+  std::vector<double> host(size_t(3) * nbins);
+  hipError_t e = launch_field_to_complex(L->v, field, a, L->stream);
+  if (e == hipSuccess) {
+    const sl_status st = dft3(L, a, b, tw, -1);
+    if (st != SL_OK) return st;
+    e = launch_spectrum_bins(L->cfg.n, L->cfg.L, b, nbins, part, L->spec_dev, L->stream);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host.data(), L->spec_dev, host.size() * sizeof(double), hipMemcpyDeviceToHost,
+                       L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return fail(SL_E_DEVICE, "spectrum: %s", hipGetErrorString(e));
+  for (int k = 0; k < nbins; ++k) {
+    k_out[k] = host[k];
+    p_out[k] = host[nbins + k];
+    count_out[k] = int64_t(host[2 * nbins + k]);
+  }
+  DevScalars Sc;
+  return read_scalars(L, &Sc);
+}
+
 
 }  // namespace
 
@@ -685,6 +728,9 @@ sl_status sl_set_potential(sl_lattice* L, int32_t kind, const double* params, in
   for (int i = 0; i < nparams; ++i)
     if (!std::isfinite(params[i])) return fail(SL_E_INVALID, "parameter %d is not finite", i);
   if (kind == SL_POT_QBALL_LOG && !(params[2] > 0.0)) return fail(SL_E_INVALID, "M^2 must be > 0");
+  if (L->batch && kind != L->pot_kind)
+    return fail(SL_E_STATE, "a batch member keeps its potential family (remove it from the batch first)");
+  if (L->batch) HIP_TRY(hipStreamSynchronize(batch_stream(L->batch)));
   PotArgs dev{};
   for (int i = 0; i < nparams; ++i) {
     L->pot_raw[i] = params[i];
@@ -696,6 +742,12 @@ sl_status sl_set_potential(sl_lattice* L, int32_t kind, const double* params, in
   L->pot_kind = kind;
   L->pot_set = true;
   refresh_m2max(L);
+  if (L->batch) {
+    // a member keeps its tile (the batch's kernel is built for its per-lane
+    // shape); the batch re-uploads its run table with the new parameters
+    batch_member_changed(L->batch);
+    return SL_OK;
+  }
   const TuneKey key{L->device, L->cfg.n, L->cfg.nfields, L->cfg.precision, kind, L->v.st.kind};
   TuneVal tv;
   if (tune_cache().find(key, &tv)) {
@@ -891,7 +943,7 @@ sl_status sl_set_history(sl_lattice* L, int64_t capacity) {
     L->hist_dev = nullptr;
   }
   if (capacity > 0 &&
-      hipMalloc(reinterpret_cast<void**>(&L->hist_dev), size_t(capacity) * 3 * sizeof(double)) != hipSuccess) {
+      hipMalloc(reinterpret_cast<void**>(&L->hist_dev), size_t(capacity) * kHistRecord * sizeof(double)) != hipSuccess) {
     L->hist_dev = nullptr;
     capacity = 0;
     S.hist = nullptr;
@@ -907,8 +959,8 @@ sl_status sl_set_history(sl_lattice* L, int64_t capacity) {
   return SL_OK;
 }
 
-sl_status sl_get_history(sl_lattice* L, double* eta, double* a, double* p_a, int64_t cap,
-                         int64_t* count) {
+sl_status sl_get_history(sl_lattice* L, double* eta, double* a, double* p_a, double* rho,
+                         int64_t cap, int64_t* count) {
   if (!L || !count) return fail(SL_E_INVALID, "lattice handle or count is NULL");
   DevScalars S;
   sl_status st = read_scalars(L, &S);
@@ -916,13 +968,14 @@ sl_status sl_get_history(sl_lattice* L, double* eta, double* a, double* p_a, int
   *count = S.hist_n;
   const int64_t m = S.hist_n < cap ? S.hist_n : cap;
   if (m > 0) {
-    if (!eta || !a || !p_a) return fail(SL_E_INVALID, "output array is NULL");
-    std::vector<double> h(size_t(m) * 3);
+    if (!eta || !a || !p_a || !rho) return fail(SL_E_INVALID, "output array is NULL");
+    std::vector<double> h(size_t(m) * kHistRecord);
     HIP_TRY(hipMemcpy(h.data(), L->hist_dev, h.size() * sizeof(double), hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < m; ++i) {
-      eta[i] = h[3 * i];
-      a[i] = h[3 * i + 1];
-      p_a[i] = h[3 * i + 2];
+      eta[i] = h[kHistRecord * i];
+      a[i] = h[kHistRecord * i + 1];
+      p_a[i] = h[kHistRecord * i + 2];
+      rho[i] = h[kHistRecord * i + 3];
     }
   }
   return SL_OK;
@@ -975,40 +1028,17 @@ sl_status sl_get_fields(sl_lattice* L, double* phi_out, double* pi_out) {
 
 sl_status sl_spectrum(sl_lattice* L, int32_t field, int32_t nbins, double* k_out, double* p_out,
                       int64_t* count_out) {
-  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
-  if (field < 0 || field >= L->cfg.nfields) return fail(SL_E_INVALID, "field index out of range");
-  if (nbins < 1 || nbins > kMaxBins) return fail(SL_E_INVALID, "nbins must be in [1, %d]", kMaxBins);
-  if (!k_out || !p_out || !count_out) return fail(SL_E_INVALID, "output array is NULL");
-  FftScratch S;
-  sl_status st = fft_alloc(L, S);
+  sl_status st = spectrum_check(L, field, nbins, k_out, p_out, count_out);
   if (st != SL_OK) return st;
-  const int nb = spectrum_blocks(L->cfg.n);
+  FftScratch S;
+  st = fft_alloc(L, S);
+  if (st != SL_OK) return st;
   double* part = nullptr;
-  if (hipMalloc(&part, size_t(nb) * 3 * nbins * sizeof(double)) != hipSuccess)
+  if (hipMalloc(&part, spectrum_part_bytes(L->cfg.n, nbins)) != hipSuccess)
     return fail(SL_E_NOMEM, "cannot allocate spectrum partials");
-  std::vector<double> host(size_t(3) * nbins);
-  hipError_t e = launch_field_to_complex(L->v, field, S.a, L->stream);
-  if (e == hipSuccess) {
-    st = dft3(L, S, -1);
-    if (st != SL_OK) {
-      (void)hipFree(part);
-      return st;
-    }
-    e = launch_spectrum_bins(L->cfg.n, L->cfg.L, S.b, nbins, part, L->spec_dev, L->stream);
-  }
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(host.data(), L->spec_dev, host.size() * sizeof(double), hipMemcpyDeviceToHost,
-                       L->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  st = spectrum_run(L, field, nbins, S.a, S.b, S.tw, part, k_out, p_out, count_out);
   (void)hipFree(part);
-  if (e != hipSuccess) return fail(SL_E_DEVICE, "spectrum: %s", hipGetErrorString(e));
-  for (int b = 0; b < nbins; ++b) {
-    k_out[b] = host[b];
-    p_out[b] = host[nbins + b];
-    count_out[b] = int64_t(host[2 * nbins + b]);
-  }
-  DevScalars Sc;
-  return read_scalars(L, &Sc);
+  return st;
 }
 
 sl_status sl_spectra(sl_lattice* L, int32_t field, int32_t nbins, double* k_out, double* pf_out,

@@ -101,8 +101,8 @@ class HandlePool:
 
 def _resident_bytes(req, history):
     """Device bytes a served run holds while resident (with its per-step
-    background record when history is on: 3 doubles per step)."""
-    return req.footprint + (24 * req.steps if history else 0)
+    background record when history is on: 4 doubles per step)."""
+    return req.footprint + (32 * req.steps if history else 0)
 
 
 def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
@@ -110,8 +110,9 @@ def serve(requests, dt, order, max_slots=64, tick_steps=25, hbm_budget=None,
           sleep=time.sleep):
     """Run the request loop to completion.  Returns (results, stats).
 
-    history: record (eta, a, p_a) at the end of every step of each run on the
-    device and return it with the result (for the uniform-density Delta N).
+    history: record (eta, a, p_a, rho) at the end of every step of each run
+    on the device and return it with the result (for the uniform-density
+    Delta N; rho is the density the library derives from the constraint).
 
     tune: before the first tick, let the batch autotuner pick the pass
     shapes of the runs admitted first unless their kinds were tuned before
@@ -261,14 +262,6 @@ def delta_n(phi0, efolds):
     return dict(N0=float(N0), N1=float(N1), N2=float(N2), sigma_N=float(np.std(N)),
                 f_NL=float(5.0 / 6.0 * N2 / (N1 * N1)) if N1 != 0 else float("nan"),
                 runs=int(N.size))
-
-
-def friedmann_density(a, p_a, n, mpl):
-    """rho = 3 m_pl^2 H^2 with H = -p_a / (6 V_L m_pl^2 a^2), V_L = n^3: the
-    total density the constraint H = 0 implies along a run (eq. (2.18))."""
-    a = np.asarray(a, dtype=np.float64)
-    hub = -np.asarray(p_a, dtype=np.float64) / (6.0 * float(n) ** 3 * mpl * mpl * a * a)
-    return 3.0 * mpl * mpl * hub * hub
 
 
 def uniform_density_efolds(a, rho, rho_ref):

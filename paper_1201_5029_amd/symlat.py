@@ -136,7 +136,7 @@ def load():
         "sl_batch_autotune": (I32, [P, I32, dp]),
         "sl_spectra": (I32, [P, I32, I32, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int64), dp]),
         "sl_set_history": (I32, [P, I64]),
-        "sl_get_history": (I32, [P, dp, dp, dp, I64, ctypes.POINTER(I64)]),
+        "sl_get_history": (I32, [P, dp, dp, dp, dp, I64, ctypes.POINTER(I64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -339,19 +339,21 @@ class Lattice:
         return k, pf, pe, pn, c, m2.value
 
     def set_history(self, capacity):
-        """Record (eta, a, p_a) at the end of each step, up to capacity."""
+        """Record (eta, a, p_a, rho) at the end of each step, up to capacity."""
         _check(self._lib.sl_set_history(self._h, int(capacity)))
 
     def history(self, cap=None):
-        """(eta, a, p_a) arrays of the recorded steps."""
+        """(eta, a, p_a, rho) arrays of the recorded steps; rho is the total
+        density the library derives from the constraint."""
         n = ctypes.c_int64()
-        _check(self._lib.sl_get_history(self._h, None, None, None, 0, ctypes.byref(n)))
+        _check(self._lib.sl_get_history(self._h, None, None, None, None, 0, ctypes.byref(n)))
         m = n.value if cap is None else min(n.value, int(cap))
         dp = ctypes.POINTER(ctypes.c_double)
-        eta, a, pa = np.zeros(m), np.zeros(m), np.zeros(m)
+        eta, a, pa, rho = np.zeros(m), np.zeros(m), np.zeros(m), np.zeros(m)
         _check(self._lib.sl_get_history(self._h, eta.ctypes.data_as(dp), a.ctypes.data_as(dp),
-                                        pa.ctypes.data_as(dp), m, ctypes.byref(n)))
-        return eta, a, pa
+                                        pa.ctypes.data_as(dp), rho.ctypes.data_as(dp), m,
+                                        ctypes.byref(n)))
+        return eta, a, pa, rho
 
     # -- launch shape and timing ---------------------------------------------
     def tile(self):

@@ -146,9 +146,9 @@ def test_batch_autotune_keeps_state_and_equals_alone():
 
 
 def test_history_records_every_step_alone_and_batched():
-    """The device history holds (eta, a, p_a) at the end of each step: equal
-    bit for bit to the background read after single-step calls, through the
-    captured chunks of a long call, and for a batch member."""
+    """The device history holds (eta, a, p_a, rho) at the end of each step:
+    equal bit for bit to the background read after single-step calls,
+    through the captured chunks of a long call, and for a batch member."""
     sl.symlat.load().sl_autotune_forget()
     r = _runs("f64", [32])[0]
     ref = sl.from_recipe(r)
@@ -159,8 +159,8 @@ def test_history_records_every_step_alone_and_batched():
     one = sl.from_recipe(r)
     one.set_history(100)
     one.evolve(40, 0.005, 4)                      # one captured 32-step chunk + 8 eager
-    eta, a, pa = one.history()
-    assert len(a) == 40
+    eta, a, pa, rho = one.history()
+    assert len(a) == 40 and np.all(rho > 0)
     assert [tuple(x) for x in zip(eta, a, pa)] == bg
     one.set_history(5)
     one.evolve(10, 0.005, 4)
@@ -295,3 +295,33 @@ def test_batch_with_fewer_tiles_than_xcds():
             assert _same(a, m), sizes
             assert not np.array_equal(f0, m.get_fields()[0])   # every lattice moved
         b.close()
+
+
+def test_member_parameter_change_equals_alone():
+    """A batch member given new parameters of its family keeps its tile and
+    steps with the new parameters, like the same lattice alone; another
+    family is refused while it is a member."""
+    sl.symlat.load().sl_autotune_forget()
+    recipes = _runs("f64", [32, 48])
+    mixed = [sl.from_recipe(r) for r in recipes]
+    alone = [sl.from_recipe(r) for r in recipes]
+    b = sl.Batch()
+    for m in mixed:
+        b.add(m)
+    b.step(6, 0.005, 4)
+    for a in alone:
+        a.evolve(6, 0.005, 4)
+    tile = mixed[1].tile()
+    new = (1.0, 0.5 * recipes[1]["params"][1])
+    mixed[1].set_potential("chaotic2", new)
+    alone[1].set_potential("chaotic2", new)
+    assert mixed[1].tile() == tile
+    with pytest.raises(sl.SymlatError) as e:
+        mixed[0].set_potential("free", (1.0, 1.0))
+    assert e.value.status == 4   # SL_E_STATE
+    b.step(9, 0.005, 4)
+    for a in alone:
+        a.evolve(9, 0.005, 4)
+    for j in range(2):
+        assert _same(alone[j], mixed[j]), j
+    b.close()

@@ -151,25 +151,42 @@ def test_largest_side_fp32_white():
 def test_deltan96_batch_fullsize_sampled():
     """The Delta-N ensemble at its full size (96 runs, n in {32, 64, 96},
     FP32, 4th order) as one batch in the shapes the batch tuner picks, as
-    the benchmark runs it: sampled members equal the same runs advanced
-    alone with the recorded shape, bit for bit, and the background of every
-    member grows."""
-    recipes = synth.delta_n_scan(nruns=96, steps=30)
+    the benchmark runs it, 100 steps: sampled members equal the same runs
+    advanced alone with the recorded shape, bit for bit; one member of each
+    size is within the FP32 gate of the oracle run from the oracle's own
+    initial state (rel-L2 per array, Friedmann residual); the background of
+    every member grows."""
+    steps = 100
+    recipes = synth.delta_n_scan(nruns=96, steps=steps)
     lats = [sl.from_recipe(r) for r in recipes]
     b = sl.Batch()
     for lat in lats:
         b.add(lat)
     b.autotune(reps=2)
     a0 = [lat.background()[1] for lat in lats]
-    b.step(30, recipes[0]["dt"], recipes[0]["order"])
+    b.step(steps, recipes[0]["dt"], recipes[0]["order"])
     b.synchronize()
     assert all(lat.background()[1] > a for lat, a in zip(lats, a0))
+    checked = set()
     for j in (0, 17, 41, 64, 80, 95):          # every size is among them
         r = recipes[j]
+        if r["n"] not in checked:
+            checked.add(r["n"])
+            o = oracle.Lattice(r["n"], r["L"], oracle.Potential(r["potential"], r["params"]),
+                               mpl=r["mpl"])
+            o.init_fluctuations(r["phi0"], r["pi0"], r["fluct"], r["amplitude"], r["seed"])
+            o.evolve(steps, r["dt"], r["order"])
+            gphi, gpi = lats[j].get_fields()
+            e1, e2 = rel_l2(gphi, o.phi), rel_l2(gpi, o.pi)
+            resid = lats[j].energies()["friedmann_residual"]
+            ea = abs(lats[j].background()[1] - o.a) / o.a
+            say("delta-N member", j, r["n"], "vs oracle: rel-L2", e1, e2, "residual", resid, "a", ea)
+            assert max(e1, e2) <= 1e-4 and resid <= 1e-3 and ea <= 1e-6, j
+            del o, gphi, gpi
         alone = sl.from_recipe(r)
         tx, vx, _, tz, pf = lats[j].tile()
         alone.set_tile(tx, vx, tz, pf)
-        alone.evolve(30, r["dt"], r["order"])
+        alone.evolve(steps, r["dt"], r["order"])
         fa, pa = alone.get_fields()
         fb, pb = lats[j].get_fields()
         say("delta-N member", j, r["n"], lats[j].tile())

@@ -155,3 +155,18 @@ def test_linear_split_calls_and_errors():
         g1.evolve(1, 0.01, 3)
     with pytest.raises(sl.SymlatError):
         g1.set_stencil((-6.0, 1.0, 0.1, 0.0))
+
+
+@pytest.mark.parametrize("n,order,steps", [(64, 6, 30), (48, 4, 40)])
+def test_linear_preheat_working_size(n, order, steps):
+    """At a working size (64^3: 6 545 classes for 262 144 modes, radix-2
+    transforms; 48^3: the direct transform), where the class ranking covers
+    many folded wave-number multisets, against the oracle that evolves every
+    mode on its own."""
+    phi, pi = _state(n, 2, 48, PREHEAT["phi0"], [0.0, 0.0], 1e-4)
+    o, g = _pair(n, PREHEAT["L"], "chaotic2", PREHEAT["params"], phi, pi, mpl=PREHEAT["mpl"])
+    assert g.classes() == math.comb(n // 2 + 3, 3)
+    g.evolve(steps, PREHEAT["dt"], order)
+    o.evolve(steps, PREHEAT["dt"], order)
+    e = _compare(o, g, "linear preheat %d^3 order %d" % (n, order))
+    assert max(e.values()) <= TOL

@@ -79,3 +79,50 @@ def test_pooled_handles_between_calls_equal_alone():
         alone.close()
     pool.close()
     assert len(pool) == 0
+
+
+def test_served_results_vs_oracle():
+    """Served 32^3 results (FP32 storage, staggered arrivals, shared batch
+    ticks) against the FP64 oracle run of each request from the oracle's own
+    initial state: fields within the FP32 gate (rel-L2 per array <= 1e-4),
+    the Friedmann residual, and the recorded background (a, and the density
+    rho = 3 m_pl^2 H^2 the device records at each step) against the
+    oracle's record of the same run; then the uniform-density e-folds of
+    the served scan against the oracle's."""
+    import oracle
+    import oracle.deltan
+    from gpu_util import rel_l2
+
+    steps = 60
+    sizes = [32] * 6
+    arrivals = [0.0, 0.0, 0.01, 0.02, 0.03, 0.05]
+    reqs = _requests(arrivals, sizes, steps=steps)
+    results, stats = serve.serve(reqs, dt=0.005, order=4, max_slots=4, tick_steps=20,
+                                 keep_fields=True, history=True)
+    assert stats["runs"] == len(reqs)
+    rho_dev, rho_or, a_dev, a_or = [], [], [], []
+    for res in results:
+        r = reqs[res["id"]].recipe
+        o = oracle.Lattice(r["n"], r["L"], oracle.Potential(r["potential"], r["params"]),
+                           mpl=r["mpl"])
+        o.init_fluctuations(r["phi0"], r["pi0"], r["fluct"], r["amplitude"], r["seed"])
+        eta_o, a_o, pa_o, rho_o = oracle.deltan.evolve_recording(o, steps, 0.005, 4)
+        e1, e2 = rel_l2(res["phi"], o.phi), rel_l2(res["pi"], o.pi)
+        eta_d, a_d, pa_d, rho_d = res["history"]
+        ea = float(np.max(np.abs(a_d - a_o) / a_o))
+        er = float(np.max(np.abs(rho_d - rho_o) / rho_o))
+        say("served", res["id"], "vs oracle: rel-L2", e1, e2, "a", ea, "rho", er)
+        assert len(a_d) == steps
+        np.testing.assert_allclose(eta_d, eta_o, rtol=1e-13)
+        assert max(e1, e2) <= 1e-4 and ea <= 1e-6 and er <= 1e-5, res["id"]
+        rho_dev.append(rho_d)
+        rho_or.append(rho_o)
+        a_dev.append(a_d)
+        a_or.append(a_o)
+    ref_d = max(r[-1] for r in rho_dev)
+    ref_o = max(r[-1] for r in rho_or)
+    for ad, rd, ao, ro in zip(a_dev, rho_dev, a_or, rho_or):
+        nd = serve.uniform_density_efolds(ad, rd, ref_d)
+        no = oracle.deltan.efolds_at_density(ao, ro, ref_o)
+        say("uniform-density N", nd, no)
+        assert abs(nd - no) <= 1e-6

@@ -35,7 +35,7 @@ class FakeLattice:
         self.cap = cap
 
     def history(self):
-        return ([], [], [])
+        return ([], [], [], [])
 
     def get_fields(self):
         return None, None
@@ -228,7 +228,7 @@ def test_a_caller_pool_keeps_handles_between_calls(fake):
     assert st["reused"] == 0 and len(FakeLattice.made) == 3 and len(pool) == 3
     assert not any(m.closed for m in FakeLattice.made)
     assert all(m.cap == 20 for m in FakeLattice.made)
-    assert pool.bytes == 3 * (100 * 32 + 24 * 20)
+    assert pool.bytes == 3 * (100 * 32 + 32 * 20)
     res, st = serve.serve([_req(i, 32, 0.0, 20) for i in range(3)], 0.005, 4, max_slots=4,
                           tick_steps=20, hbm_budget=10 ** 9, pool=pool, clock=fake,
                           sleep=fake.sleep)
