@@ -142,7 +142,9 @@ sl_status sl_lattice_create(const sl_config* cfg, void* hip_stream, sl_lattice**
  * handle zero-fills them at creation, uses them until sl_lattice_destroy and
  * never frees them; the caller keeps them alive that long and touches them
  * only between synchronising calls.  Which buffer holds the state alternates
- * with the stages: read it with sl_get_fields.  The small buffers (partial
+ * with the stages, and in FP32 storage the arrays hold each field's and
+ * momentum's remainder around a homogeneous FP64 offset the handle keeps:
+ * read the state with sl_get_fields.  The small buffers (partial
  * sums, scalars) are still the handle's.  SL_E_INVALID if an array is NULL,
  * misaligned, not device memory of this device, shorter than needed inside
  * its allocation, or overlaps another.  sl_footprint_bytes still counts the
@@ -307,12 +309,14 @@ sl_status sl_kernel_timing(sl_lattice* lat, int64_t* passes, double* total_ms);
 /* Launch shape of the fused pass: tx lanes along x (8 .. 64), each
  * holding vx consecutive x-sites (1, 2 or 4; n must be divisible by vx),
  * ty = floor(256/tx) rows (the remaining 256 - tx*ty lanes of the workgroup
- * idle), tz z-planes per workgroup, and the prefetch depth pf of
- * the z-march (1: next plane loaded each iteration; 2: own column two
- * planes and halo one plane ahead).  Lattices with more than two fields run
- * with vx = 1, pf = 1; any stencil other than the 7-point one runs with
- * pf = 1 and vx = 1 or 2 (2 only up to two fields; 2 tx + 2 ty + 4 <= 256
- * halo lanes, true for every tx).  A batch
+ * idle), tz z-planes per workgroup, and the pass mode pf: the prefetch
+ * depth of the z-march (1: next plane loaded each iteration; 2: own column
+ * two planes and halo one plane ahead), plus 4 to write the results with
+ * non-temporal stores (so they do not displace halo data in the L2; the
+ * 7-point stencil with vx = 2 or 4 only), i.e. pf in {1, 2, 5, 6}.
+ * Lattices with more than two fields run with vx = 1, pf = 1; any stencil
+ * other than the 7-point one runs with pf = 1 and vx = 1 or 2 (2 only up to
+ * two fields; 2 tx + 2 ty + 4 <= 256 halo lanes, true for every tx).  A batch
  * member keeps its vx and pf.  sl_get_tile reports the shape in use; sl_set_tile
  * overrides it (tz = 0: z-chunk chosen from the kernel's occupancy so the
  * grid fills whole rounds of resident workgroups).  SL_E_INVALID for
@@ -323,8 +327,8 @@ sl_status sl_set_tile(sl_lattice* lat, int32_t tx, int32_t vx, int32_t tz, int32
 
 /* Autotuner: time candidate shapes (tx in {16, 32, 64}, 8 with vx = 4, and
  * n/vx when that is in [8, 64] and not a power of two, i.e. a whole row per
- * tile; vx in {1, 2, 4} dividing n; pf in {1, 2}; tz in {occupancy choice,
- * n/16, n/8, n/4, n/2})
+ * tile; vx in {1, 2, 4} dividing n; pf in {1, 2, 5, 6}; tz in {occupancy choice,
+ * n/16, n/8, n/4, n/2}, at least 8, and for n <= 128 also 1, 2 and 4)
  * on the lattice's current state: best of `reps` HIP-event timings of two
  * consecutive stages (fused pass + finalize, each reading what the previous
  * wrote, as inside sl_evolve) with the drift and kick coefficients frozen at

@@ -145,6 +145,104 @@ __device__ __forceinline__ void potential(const T (&f)[NF], const PotT<T>& P, T&
   }
 }
 
+// Constants of the difference form below that depend only on the offsets
+// (uniform over a pass): for the Q-ball family u0 = (fb_0^2 + fb_1^2)/2, its
+// reciprocal, ln(u0/M^2) and dV(fb).
+template <typename T>
+struct SplitK {
+  T u0, inv_u0, L0, dv0[2];
+  bool has_u0;
+};
+
+template <int KIND, int NF, typename T>
+__device__ __forceinline__ SplitK<T> split_consts(const double (&fb)[NF], const PotArgs& prm) {
+  SplitK<T> k{};
+  if constexpr (KIND == SL_POT_QBALL_LOG) {
+    const double u0 = 0.5 * (fb[0] * fb[0] + fb[1] * fb[1]);
+    k.has_u0 = u0 > 0.0;
+    k.u0 = T(u0);
+    k.inv_u0 = k.has_u0 ? T(1.0 / u0) : T(0);
+    const double L0 = k.has_u0 ? log(u0 * prm.p[2]) : 0.0;
+    k.L0 = T(L0);
+    const double g0 = k.has_u0 ? prm.p[0] * (1.0 + prm.p[1] + prm.p[1] * L0) : 0.0;
+    k.dv0[0] = T(g0 * fb[0]);
+    k.dv0[1] = T(g0 * fb[1]);
+  }
+  return k;
+}
+
+// V at fb + d and dV(fb + d) - dV(fb), for FP32 remainders d around FP64
+// offsets fb: each difference is written as d times a factor (algebraic
+// identities of the family), so that it keeps the relative precision of d
+// instead of cancelling two values near dV(fb).  V is formed from the full
+// values (it only enters FP64 lattice sums).
+template <int KIND, int NF, typename T>
+__device__ __forceinline__ void potential_split(const T (&fb)[NF], const T (&d)[NF],
+                                                const PotT<T>& P, const SplitK<T>& k, T& V,
+                                                T (&ddV)[NF]) {
+  T x[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) x[i] = fb[i] + d[i];
+  if constexpr (KIND == SL_POT_FREE) {
+    V = T(0);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      ddV[i] = P.p[i] * d[i];
+      V += T(0.5) * (P.p[i] * x[i]) * x[i];
+    }
+  } else if constexpr (KIND == SL_POT_CHAOTIC2) {
+    // dV0 = phi (m2 + G chi^2), dV1 = G phi^2 chi
+    const T m2 = P.p[0], G = P.p[1];
+    const T f2 = x[0] * x[0], c2 = x[1] * x[1];
+    const T mc = m2 + G * c2;
+    V = T(0.5) * f2 * mc;
+    const T dc2 = d[1] * (T(2) * fb[1] + d[1]);  // chi^2 - chi0^2
+    const T df2 = d[0] * (T(2) * fb[0] + d[0]);  // phi^2 - phi0^2
+    ddV[0] = d[0] * mc + fb[0] * (G * dc2);
+    ddV[1] = G * (f2 * d[1] + fb[1] * df2);
+  } else if constexpr (KIND == SL_POT_OSCILLON) {
+    // dV = m2 x - lam x^3 + g x^5; x^k - b^k = d sum_j x^j b^(k-1-j)
+    const T m2 = P.p[0], lam = P.p[1], g = P.p[2];
+    const T xx = x[0], b = fb[0], x2 = xx * xx, b2 = b * b, xb = xx * b;
+    V = x2 * (T(0.5) * m2 + x2 * (T(-0.25) * lam + x2 * (g * T(1.0 / 6.0))));
+    const T s3 = x2 + xb + b2;
+    const T s5 = x2 * x2 + xb * (x2 + b2) + x2 * b2 + b2 * b2;
+    ddV[0] = d[0] * (m2 - lam * s3 + g * s5);
+  } else {
+    // V = m2 u (1 + K ln(u/M^2)), dV_i = m2 phi_i g(u), g = 1 + K + K ln(u/M^2):
+    // dV_i(x) - dV_i(fb) = m2 (d_i g(u) + fb_i K ln(u/u0))
+    const T m2 = P.p[0], K = P.p[1], invM2 = P.p[2];
+    const T u = T(0.5) * (x[0] * x[0] + x[1] * x[1]);
+    if (!(u > T(0))) {
+      V = T(0);
+      ddV[0] = -k.dv0[0];
+      ddV[1] = -k.dv0[1];
+    } else if (k.has_u0) {
+      // r = ln(u/u0) = ln(1 + q), q = (u - u0)/u0 formed from the remainders:
+      // w = 1 + q rounded, e = q - (w - 1) exactly (Fast2Sum, |q| <= 1), and
+      // ln(1 + q) = ln(w) + e/w + O(e^2), with 1/w ~ 2 - w (|e| <= 2^-24);
+      // far below u0 the log of u/u0 itself, one log per site either way
+      const T du = fb[0] * d[0] + fb[1] * d[1] + T(0.5) * (d[0] * d[0] + d[1] * d[1]);
+      const T q = du * k.inv_u0;
+      const bool near = q > T(-0.5) && q < T(1);
+      const T w = T(1) + q;
+      const T e = q - (w - T(1));
+      const T r = logf(near ? w : u * k.inv_u0) + (near ? e * (T(2) - w) : T(0));
+      const T Lu = k.L0 + r;
+      V = m2 * u * (T(1) + K * Lu);
+      const T gu = T(1) + K + K * Lu;
+      ddV[0] = m2 * (d[0] * gu + fb[0] * (K * r));
+      ddV[1] = m2 * (d[1] * gu + fb[1] * (K * r));
+    } else {
+      const T lg = logf(u * invM2);
+      V = m2 * u * (T(1) + K * lg);
+      const T gu = m2 * (T(1) + K + K * lg);
+      ddV[0] = gu * x[0];
+      ddV[1] = gu * x[1];
+    }
+  }
+}
+
 // Field drift phi + c pi as one fused multiply-add, so every tile computes
 // the same value for a site.
 __device__ __forceinline__ float drift(float phi, float pi, float c) { return fmaf(c, pi, phi); }

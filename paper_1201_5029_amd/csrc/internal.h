@@ -68,6 +68,20 @@ struct DevScalars {
   double* hist;      // optional record of (eta, a, p_a, rho) at the end of each step
   int64_t hist_cap;  // records the buffer holds
   int64_t hist_n;    // records written since the last reset
+  // FP32 storage holds each field and momentum as an FP64 homogeneous offset
+  // plus an FP32 remainder: phi_i = off_phi[i] + stored, pi_i = off_pi[i] +
+  // stored (the pending drift applies to both parts).  FP64 storage keeps
+  // the offsets at 0.  A pass forms the offsets of the state it writes,
+  // off_phi + c_next off_pi and off_pi - beta dV(that), and its first tile
+  // records them for the stage finalize (PassParams::offs).
+  double off_phi[kMaxFields];
+  double off_pi[kMaxFields];
+};
+
+// Homogeneous offsets of a state (see DevScalars).
+struct Offsets {
+  double phi[kMaxFields];
+  double pi[kMaxFields];
 };
 
 // Per-lattice constants of the scalar updates.
@@ -81,6 +95,8 @@ struct BgConsts {
   double dx2;
   double L;
   int32_t expand;    // 1: self-consistent expansion, 0: static a
+  int32_t split;     // 1: FP32 remainders around FP64 offsets (see DevScalars)
+  int32_t nf;
   int32_t pad;
 };
 
@@ -101,9 +117,17 @@ struct Stencil {
 // Launch shape of the tiled passes: TX lanes in x (8 .. 64) each holding VX
 // consecutive sites (tile width TX*VX), TY = floor(256/TX) rows in y (the
 // last 256 - TX*TY lanes of the workgroup idle), TZ planes per z-chunk.
+// Pass mode pf: the prefetch depth of the z-march (1 or 2 planes), plus
+// kPfNontemporal when the results are written with non-temporal stores
+// (7-point pass, at most two fields, 2 or 4 sites per lane).
+constexpr int kPfNontemporal = 4;
+inline int pf_depth(int pf) { return pf & 3; }
+inline bool pf_nt(int pf) { return (pf & kPfNontemporal) != 0; }
+inline bool pf_valid(int pf) { return pf_depth(pf) == 1 || pf_depth(pf) == 2; }
+
 struct Tile {
   int tx, ty, tz, vx;
-  int pf;  // prefetch depth of the z-march (1 or 2 planes)
+  int pf;  // pass mode: prefetch depth (1 or 2) | kPfNontemporal
   int ntx, nty, ntz;
   int nblocks() const { return ntx * nty * ntz; }
 };
@@ -116,6 +140,7 @@ struct PassParams {
   void* pi_w[2];
   const DevScalars* sc;
   double* partials;
+  double* offs;  // FP32 storage: offsets of the written state (phi[nf], pi[nf])
   void* sink;  // per-thread slots that absorb the stores of idle lanes
   PotArgs prm;
   double stc[4];  // stencil weights (27-point pass only)
@@ -129,6 +154,7 @@ struct PassParams {
 struct BatchRun {
   DevScalars* sc;
   double* partials;
+  const double* offs;
   BgConsts bg;
   int ntiles;
   int pad;
@@ -140,6 +166,7 @@ struct LatView {
   void* pi[2];           // ping-pong momentum buffers
   DevScalars* sc;
   double* partials;      // per-block (sum, compensation) pairs
+  double* offs;          // 2 kMaxFields doubles: offsets the last pass wrote around
   void* sink;            // kSinkBytes of store slots for idle lanes of the pass
   int n, nf, prec, pot;  // prec: sl_precision, pot: sl_potential
   // Field layout: element (field i, plane z, in-plane r = y n + x) of a phi or
@@ -192,16 +219,20 @@ hipError_t launch_sum_pi2(const LatView& v, hipStream_t s);
 hipError_t launch_export(const LatView& v, double* phi_out, double* pi_out, hipStream_t s);
 // Store FP64 staging arrays into buffer 0 in the storage precision and reset
 // the scalars: parity 0, no pending drift, eta = 0, the given a and p_a.
+// off: the offsets the state is stored around (all 0 in FP64 storage).
 hipError_t launch_import(const LatView& v, const double* phi_in, const double* pi_in, double a,
-                         double p_a, hipStream_t s);
-hipError_t launch_reset_scalars(const LatView& v, double a, double p_a, hipStream_t s);
+                         double p_a, const Offsets& off, hipStream_t s);
+hipError_t launch_reset_scalars(const LatView& v, double a, double p_a, const Offsets& off,
+                                hipStream_t s);
 // Copy the scalars of the nruns runs of a batch table into out_dev[0 .. nruns).
 hipError_t launch_gather_scalars(const BatchRun* runs_dev, int nruns, DevScalars* out_dev,
                                  hipStream_t s);
 
 // ---- initial state and spectrum (kernels_init.hip) ------------------------
+// Every site of buffer 0 = (phi0, pi0) less the state's offsets (the
+// remainders are 0 in FP32 storage with offsets phi0, pi0).
 hipError_t launch_fill_homogeneous(const LatView& v, const double* phi0, const double* pi0,
-                                   hipStream_t s);
+                                   const Offsets& off, hipStream_t s);
 // Vacuum k-space amplitudes of one field into cbuf (complex FP64, n^3).
 hipError_t launch_vacuum_modes(const LatView& v, double2* cbuf, int field, double m2eff,
                                double amp, uint64_t seed, hipStream_t s);

@@ -37,7 +37,7 @@ constexpr int nsums() { return 5 * NF + 1; }
 // stencil: the 26 neighbours weighted by class (face, edge, corner).
 template <typename T>
 __device__ void stencil27_at(const T* __restrict__ phi, const T* __restrict__ pi, double c,
-                             int i, int zs, int n, int x, int y, int z, double f,
+                             double offp, int i, int zs, int n, int x, int y, int z, double f,
                              const Stencil& st, double& D, double& G) {
   const size_t n2 = size_t(n) * n;
   double acc[4] = {0.0, 0.0, 0.0, 0.0}, g[4] = {0.0, 0.0, 0.0, 0.0};
@@ -50,7 +50,7 @@ __device__ void stencil27_at(const T* __restrict__ phi, const T* __restrict__ pi
         if (cls == 0) continue;
         const int xx = x + dx < 0 ? n - 1 : (x + dx >= n ? 0 : x + dx);
         const size_t e = (size_t(zz) * zs + i) * n2 + size_t(yy) * n + xx;
-        const double v = fma(c, double(pi[e]), double(phi[e]));
+        const double v = offp + fma(c, double(pi[e]), double(phi[e]));
         acc[cls] += v;
         const double d = v - f;
         g[cls] += d * d;
@@ -75,11 +75,18 @@ __global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScala
 #pragma unroll
   for (int i = 0; i < kMaxFields; ++i) pot.p[i] = prm.p[i];
   const size_t n2 = size_t(n) * n, n3 = n2 * n;
+  // offsets of the stored remainders (0 in FP64 storage), drifted by c
+  double offp[NF], offq[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    offq[i] = sc->off_pi[i];
+    offp[i] = sc->off_phi[i] + c * offq[i];
+  }
 
   // field i of plane z starts at (z zs + i) n^2
   double shift[NF];
 #pragma unroll
-  for (int i = 0; i < NF; ++i) shift[i] = fma(c, double(pi[i * n2]), double(phi[i * n2]));
+  for (int i = 0; i < NF; ++i) shift[i] = offp[i] + fma(c, double(pi[i * n2]), double(phi[i * n2]));
 
   KSum acc[NV];
 #pragma unroll
@@ -101,8 +108,9 @@ __global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScala
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
       const size_t o = (size_t(z) * zs + i) * n2 + r;
-      const double pc = double(pi[o]);
-      const double fcv = fma(c, pc, double(phi[o]));
+      const double pr = double(pi[o]);
+      const double pc = offq[i] + pr;
+      const double fcv = offp[i] + fma(c, pr, double(phi[o]));
       f[i] = fcv;
       double D, G;
       if (st.kind == 0) {
@@ -110,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScala
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
           const size_t on = (nz[q] * zs + i) * n2 + nr[q];
-          nb[q] = fma(c, double(pi[on]), double(phi[on]));
+          nb[q] = offp[i] + fma(c, double(pi[on]), double(phi[on]));
         }
         D = -6.0 * fcv;
         G = 0.0;
@@ -122,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void energies_kernel(Bufs B, const DevScala
         }
         G = 0.5 * G;
       } else {
-        stencil27_at<T>(phi, pi, c, i, zs, n, x, y, z, fcv, st, D, G);
+        stencil27_at<T>(phi, pi, c, offp[i], i, zs, n, x, y, z, fcv, st, D, G);
       }
       kadd(acc[5 * i + 0], pc * pc);
       kadd(acc[5 * i + 1], G);
@@ -174,9 +182,16 @@ __global__ __launch_bounds__(kBlock) void energies7_kernel(Bufs B, const DevScal
 #pragma unroll
   for (int i = 0; i < kMaxFields; ++i) pot.p[i] = prm.p[i];
   const size_t n2 = size_t(n) * n;
+  // offsets of the stored remainders (0 in FP64 storage), drifted by c
+  double offp[NF], offq[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    offq[i] = sc->off_pi[i];
+    offp[i] = sc->off_phi[i] + c * offq[i];
+  }
   double shift[NF];
 #pragma unroll
-  for (int i = 0; i < NF; ++i) shift[i] = fma(c, double(pi[i * n2]), double(phi[i * n2]));
+  for (int i = 0; i < NF; ++i) shift[i] = offp[i] + fma(c, double(pi[i * n2]), double(phi[i * n2]));
 
   const int ntx = (n + kEX - 1) / kEX, nty = (n + kEY - 1) / kEY;
   int b = blockIdx.x;
@@ -220,6 +235,7 @@ __global__ __launch_bounds__(kBlock) void energies7_kernel(Bufs B, const DevScal
   }
 
   auto wrapz = [n](int zz) { return zz < 0 ? zz + n : (zz >= n ? zz - n : zz); };
+  // remainders of phi and pi at one site
   auto load = [&](int zz, int i, size_t rr, double& p) {
     const size_t o = (size_t(zz) * zs + i) * n2 + rr;
     p = double(pi[o]);
@@ -236,13 +252,15 @@ __global__ __launch_bounds__(kBlock) void energies7_kernel(Bufs B, const DevScal
   for (int i = 0; i < NF; ++i) {
     double p = 0.0;
     const double f = load(wrapz(z0 - 1), i, r, p);
-    fm[i] = fma(c, p, f);
+    fm[i] = offp[i] + fma(c, p, f);
     const double g = load(z0, i, r, pc[i]);
-    fc[i] = fma(c, pc[i], g);
+    fc[i] = offp[i] + fma(c, pc[i], g);
+    pc[i] = offq[i] + pc[i];
     const double h = load(wrapz(z0 + 1), i, r, pp[i]);
-    fp[i] = fma(c, pp[i], h);
+    fp[i] = offp[i] + fma(c, pp[i], h);
+    pp[i] = offq[i] + pp[i];
     const double hh = load(z0, i, hr, p);
-    hc[i] = fma(c, p, hh);
+    hc[i] = offp[i] + fma(c, p, hh);
   }
   int buf = 0;
   for (int z = z0; z < zend; ++z) {
@@ -294,9 +312,9 @@ __global__ __launch_bounds__(kBlock) void energies7_kernel(Bufs B, const DevScal
       fm[i] = fc[i];
       fc[i] = fp[i];
       pc[i] = pp[i];
-      fp[i] = fma(c, pn[i], fn[i]);
-      pp[i] = pn[i];
-      hc[i] = fma(c, hq[i], hn[i]);
+      fp[i] = offp[i] + fma(c, pn[i], fn[i]);
+      pp[i] = offq[i] + pn[i];
+      hc[i] = offp[i] + fma(c, hq[i], hn[i]);
     }
     buf ^= 1;
   }
@@ -353,14 +371,15 @@ __global__ __launch_bounds__(kBlock) void energies_finalize(const double* partia
   for (int i = 0; i < NF; ++i) {
     // shift used by the sum kernel: phi_sync at site 0
     double sh;
+    const double offp = S.off_phi[i] + S.c_pend * S.off_pi[i];
     if (prec == SL_FP32) {
       const float* ph = static_cast<const float*>(B.phi[par]);
       const float* pp = static_cast<const float*>(B.pi[par]);
-      sh = fma(S.c_pend, double(pp[i * n2]), double(ph[i * n2]));
+      sh = offp + fma(S.c_pend, double(pp[i * n2]), double(ph[i * n2]));
     } else {
       const double* ph = static_cast<const double*>(B.phi[par]);
       const double* pp = static_cast<const double*>(B.pi[par]);
-      sh = fma(S.c_pend, pp[i * n2], ph[i * n2]);
+      sh = offp + fma(S.c_pend, pp[i * n2], ph[i * n2]);
     }
     E.kin[i] = (s[5 * i] / VL) / (2.0 * a6);
     E.grad[i] = (s[5 * i + 1] / VL) / (2.0 * a2 * K.dx2);
@@ -471,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void sum_pi2_kernel(Bufs B, const DevScalar
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += stride) {
     const size_t i = e / n3;  // field i, site e - i n^3
-    const double p = double(pi[field_site(int(i), e - i * n3, zs, n2)]);
+    const double p = sc->off_pi[i] + double(pi[field_site(int(i), e - i * n3, zs, n2)]);
     kadd(acc[0], p * p);
   }
   block_reduce<1>(acc, scratch);
@@ -512,23 +531,25 @@ __global__ void export_kernel(Bufs B, const DevScalars* sc, size_t count, int nf
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += stride) {
     const size_t d = device_index(e, zs, n2, n3);
-    const double p = double(pi[d]);
-    if (phi_out) phi_out[e] = fma(c, p, double(phi[d]));
-    if (pi_out) pi_out[e] = p;
+    const size_t i = e / n3;
+    const double pr = double(pi[d]);
+    if (phi_out) phi_out[e] = (sc->off_phi[i] + c * sc->off_pi[i]) + fma(c, pr, double(phi[d]));
+    if (pi_out) pi_out[e] = sc->off_pi[i] + pr;
   }
 }
 
 template <typename T>
 __global__ void import_kernel(void* phi0, void* pi0, size_t count, int nf, int zs, size_t n2,
-                              const double* phi_in, const double* pi_in) {
+                              const double* phi_in, const double* pi_in, Offsets off) {
   T* __restrict__ phi = static_cast<T*>(phi0);
   T* __restrict__ pi = static_cast<T*>(pi0);
   const size_t n3 = count / nf;
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += stride) {
     const size_t d = device_index(e, zs, n2, n3);
-    phi[d] = static_cast<T>(phi_in[e]);
-    pi[d] = static_cast<T>(pi_in[e]);
+    const size_t i = e / n3;
+    phi[d] = static_cast<T>(phi_in[e] - off.phi[i]);
+    pi[d] = static_cast<T>(pi_in[e] - off.pi[i]);
   }
 }
 
@@ -539,9 +560,13 @@ __global__ void gather_scalars_kernel(const BatchRun* __restrict__ runs, int nru
   if (r < nruns) out[r] = *runs[r].sc;
 }
 
-__global__ void reset_scalars_kernel(DevScalars* sc, double a, double p_a) {
+__global__ void reset_scalars_kernel(DevScalars* sc, double a, double p_a, Offsets off) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     DevScalars S = *sc;  // keeps the history buffer; a reset restarts it
+    for (int i = 0; i < kMaxFields; ++i) {
+      S.off_phi[i] = off.phi[i];
+      S.off_pi[i] = off.pi[i];
+    }
     S.a = a;
     S.p_a = p_a;
     S.eta = 0.0;
@@ -603,17 +628,17 @@ hipError_t launch_export(const LatView& v, double* phi_out, double* pi_out, hipS
 }
 
 hipError_t launch_import(const LatView& v, const double* phi_in, const double* pi_in, double a,
-                         double p_a, hipStream_t s) {
+                         double p_a, const Offsets& off, hipStream_t s) {
   const size_t count = size_t(v.nf) * v.n * v.n * v.n;
   if (v.prec == SL_FP32)
     hipLaunchKernelGGL(import_kernel<float>, dim3(grid_for(count)), dim3(kBlock), 0, s, v.phi[0],
-                       v.pi[0], count, v.nf, v.zs, size_t(v.n) * v.n, phi_in, pi_in);
+                       v.pi[0], count, v.nf, v.zs, size_t(v.n) * v.n, phi_in, pi_in, off);
   else
     hipLaunchKernelGGL(import_kernel<double>, dim3(grid_for(count)), dim3(kBlock), 0, s, v.phi[0],
-                       v.pi[0], count, v.nf, v.zs, size_t(v.n) * v.n, phi_in, pi_in);
+                       v.pi[0], count, v.nf, v.zs, size_t(v.n) * v.n, phi_in, pi_in, off);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(reset_scalars_kernel, dim3(1), dim3(64), 0, s, v.sc, a, p_a);
+  hipLaunchKernelGGL(reset_scalars_kernel, dim3(1), dim3(64), 0, s, v.sc, a, p_a, off);
   return hipGetLastError();
 }
 
@@ -625,8 +650,9 @@ hipError_t launch_gather_scalars(const BatchRun* runs_dev, int nruns, DevScalars
   return hipGetLastError();
 }
 
-hipError_t launch_reset_scalars(const LatView& v, double a, double p_a, hipStream_t s) {
-  hipLaunchKernelGGL(reset_scalars_kernel, dim3(1), dim3(64), 0, s, v.sc, a, p_a);
+hipError_t launch_reset_scalars(const LatView& v, double a, double p_a, const Offsets& off,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(reset_scalars_kernel, dim3(1), dim3(64), 0, s, v.sc, a, p_a, off);
   return hipGetLastError();
 }
 

@@ -38,15 +38,15 @@ __device__ __forceinline__ double normal(uint64_t seed, uint64_t field, uint64_t
 
 template <typename T>
 __global__ void fill_homogeneous_kernel(void* phi0, void* pi0, int nf, int zs, size_t n2,
-                                        size_t n3, PotArgs v0, PotArgs p0) {
+                                        size_t n3, PotArgs v0, PotArgs p0, Offsets off) {
   T* phi = static_cast<T*>(phi0);
   T* pi = static_cast<T*>(pi0);
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n3 * nf; e += stride) {
     const int i = int(e / n3);  // field i, site e - i n^3
     const size_t d = field_site(i, e - size_t(i) * n3, zs, n2);
-    phi[d] = static_cast<T>(v0.p[i]);
-    pi[d] = static_cast<T>(p0.p[i]);
+    phi[d] = static_cast<T>(v0.p[i] - off.phi[i]);
+    pi[d] = static_cast<T>(p0.p[i] - off.pi[i]);
   }
 }
 
@@ -255,10 +255,11 @@ __global__ void field_to_complex_kernel(const void* const phi_b0, const void* co
   const T* phi = static_cast<const T*>(par ? phi_b1 : phi_b0);
   const T* pi = static_cast<const T*>(par ? pi_b1 : pi_b0);
   const double c = sc->c_pend;
+  const double offp = sc->off_phi[field] + c * sc->off_pi[field];
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n3; e += stride) {
     const size_t d = field_site(field, e, zs, n2);
-    F[e] = make_double2(fma(c, double(pi[d]), double(phi[d])), 0.0);
+    F[e] = make_double2(offp + fma(c, double(pi[d]), double(phi[d])), 0.0);
   }
 }
 
@@ -325,7 +326,7 @@ int grid_for(size_t count) {
 }  // namespace
 
 hipError_t launch_fill_homogeneous(const LatView& v, const double* phi0, const double* pi0,
-                                   hipStream_t s) {
+                                   const Offsets& off, hipStream_t s) {
   PotArgs a{}, b{};
   for (int i = 0; i < v.nf; ++i) {
     a.p[i] = phi0[i];
@@ -335,10 +336,10 @@ hipError_t launch_fill_homogeneous(const LatView& v, const double* phi0, const d
   const int nb = grid_for(n3 * v.nf);
   if (v.prec == SL_FP32)
     hipLaunchKernelGGL(fill_homogeneous_kernel<float>, dim3(nb), dim3(kBlock), 0, s, v.phi[0],
-                       v.pi[0], v.nf, v.zs, size_t(v.n) * v.n, n3, a, b);
+                       v.pi[0], v.nf, v.zs, size_t(v.n) * v.n, n3, a, b, off);
   else
     hipLaunchKernelGGL(fill_homogeneous_kernel<double>, dim3(nb), dim3(kBlock), 0, s, v.phi[0],
-                       v.pi[0], v.nf, v.zs, size_t(v.n) * v.n, n3, a, b);
+                       v.pi[0], v.nf, v.zs, size_t(v.n) * v.n, n3, a, b, off);
   return hipGetLastError();
 }
 

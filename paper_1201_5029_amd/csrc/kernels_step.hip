@@ -81,6 +81,40 @@ __device__ __forceinline__ void stv(T* __restrict__ p, const T (&v)[VX]) {
   }
 }
 
+// The same stores with the non-temporal hint: the results of a pass are
+// read only by the next pass, so they should not displace the halo rows and
+// planes that neighbouring tiles are about to read from the L2.
+template <typename T, int VX>
+__device__ __forceinline__ void stv_nt(T* __restrict__ p, const T (&v)[VX]) {
+  if constexpr (VX == 2 && sizeof(T) == 8) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 q = {v[0], v[1]};
+    __builtin_nontemporal_store(q, reinterpret_cast<d2*>(p));
+  } else if constexpr (VX == 4 && sizeof(T) == 8) {
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    const d4 q = {v[0], v[1], v[2], v[3]};
+    __builtin_nontemporal_store(q, reinterpret_cast<d4*>(p));
+  } else if constexpr (VX == 4) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 q = {v[0], v[1], v[2], v[3]};
+    __builtin_nontemporal_store(q, reinterpret_cast<f4*>(p));
+  } else if constexpr (VX == 2) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 q = {v[0], v[1]};
+    __builtin_nontemporal_store(q, reinterpret_cast<f2*>(p));
+  } else {
+    __builtin_nontemporal_store(v[0], p);
+  }
+}
+
+template <bool NT, typename T, int VX>
+__device__ __forceinline__ void stv_mode(T* __restrict__ p, const T (&v)[VX]) {
+  if constexpr (NT)
+    stv_nt<T, VX>(p, v);
+  else
+    stv<T, VX>(p, v);
+}
+
 // Workgroups are dealt to the 8 XCDs round-robin (id mod 8).  Renumber them
 // so that each XCD receives a contiguous run of tiles: neighbouring tiles,
 // whose halos overlap, then share that XCD's L2.
@@ -89,6 +123,38 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int per = nb / kXcd, rem = nb % kXcd;
   const int x = b % kXcd, i = b / kXcd;
   return x * per + (x < rem ? x : rem) + i;
+}
+
+// FP32 storage: the offsets of the state this pass writes -- the homogeneous
+// parts of the stage's drift and kick, fbar = off_phi + c off_pi and
+// pibar = off_pi - beta dV(fbar), in FP64 (every lane forms the same values)
+// -- and the constants of the difference form of dV around fbar.  The first
+// tile records them for the stage finalize.
+template <int KIND, int NF, typename T>
+__device__ __forceinline__ void split_offsets(const PassParams& P, int tile_id, double (&fbar)[NF],
+                                              double (&pibar)[NF], T (&fbT)[NF], SplitK<T>& sk) {
+  const DevScalars& S = *P.sc;
+  const double c = S.c_next, beta = S.beta;
+  PotT<double> pd;
+#pragma unroll
+  for (int k = 0; k < kMaxFields; ++k) pd.p[k] = P.prm.p[k];
+  double V0, dv[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) fbar[i] = fma(c, S.off_pi[i], S.off_phi[i]);
+  potential<KIND, NF, double>(fbar, pd, V0, dv);
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    pibar[i] = fma(-beta, dv[i], S.off_pi[i]);
+    fbT[i] = static_cast<T>(fbar[i]);
+  }
+  sk = split_consts<KIND, NF, T>(fbar, P.prm);
+  if (tile_id == 0 && threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      P.offs[i] = fbar[i];
+      P.offs[kMaxFields + i] = pibar[i];
+    }
+  }
 }
 
 // PF = 1: the next plane is loaded at the top of each z-iteration and used
@@ -100,7 +166,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // instructions: in the PF = 2 kernel idle lanes load a clamped in-range
 // address and store into a private sink slot, and x-halo cells are fetched
 // as the aligned VX-wide group that contains them.
-template <typename T, int NF, int KIND, int VX, int PF>
+template <typename T, int NF, int KIND, int VX, int PF, bool NT>
 __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* lds,
                                           KSum* red_scratch) {
   const int par = P.sc->parity;
@@ -114,6 +180,13 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
   PotT<T> pot;
 #pragma unroll
   for (int i = 0; i < kMaxFields; ++i) pot.p[i] = static_cast<T>(P.prm.p[i]);
+  // FP32 storage: the arrays hold remainders around FP64 offsets; the
+  // offsets of the state this pass writes come with the stage coefficients
+  constexpr bool kSplit = sizeof(T) == 4;
+  double fbar[NF], pibar[NF];
+  T fbT[NF];
+  SplitK<T> sk{};
+  if constexpr (kSplit) split_offsets<KIND, NF, T>(P, tile_id, fbar, pibar, fbT, sk);
 
   const int n = P.n;
   const size_t n2 = size_t(n) * n;
@@ -247,8 +320,8 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
     // the previous plane's stores.
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      stv<T, VX>(sink + (2 * i) * VX, fc[i]);
-      stv<T, VX>(sink + (2 * i + 1) * VX, pc[i]);
+      stv_mode<NT, T, VX>(sink + (2 * i) * VX, fc[i]);
+      stv_mode<NT, T, VX>(sink + (2 * i + 1) * VX, pc[i]);
     }
   }
 
@@ -288,12 +361,21 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
           f[i] = fc[i][v];
           D[i] = ((Li[-1] + Li[1]) + (Li[-LX] + Li[LX])) + (fm[i][v] + fp[i][v]) - T(6) * f[i];
         }
-        potential<KIND, NF, T>(f, pot, V, dV);
+        if constexpr (kSplit)
+          potential_split<KIND, NF, T>(fbT, f, pot, sk, V, dV);  // dV(fbar + f) - dV(fbar)
+        else
+          potential<KIND, NF, T>(f, pot, V, dV);
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
           pn[i][v] = pc[i][v] + alpha * D[i] - beta * dV[i];
-          dd += double(f[i]) * double(D[i]);
-          p2 += double(pn[i][v]) * double(pn[i][v]);
+          if constexpr (kSplit) {
+            dd += (fbar[i] + double(f[i])) * double(D[i]);
+            const double q = pibar[i] + double(pn[i][v]);
+            p2 += q * q;
+          } else {
+            dd += double(f[i]) * double(D[i]);
+            p2 += double(pn[i][v]) * double(pn[i][v]);
+          }
         }
         vs += double(V);
       }
@@ -302,8 +384,8 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
         const size_t oc = (size_t(z) * P.zs + i) * n2 + col;
         T* po = active ? phi_out + oc : sink + (2 * i) * VX;
         T* qo = active ? pi_out + oc : sink + (2 * i + 1) * VX;
-        stv<T, VX>(po, fc[i]);
-        stv<T, VX>(qo, pn[i]);
+        stv_mode<NT, T, VX>(po, fc[i]);
+        stv_mode<NT, T, VX>(qo, pn[i]);
       }
       if (active) {
         kadd(acc_dd, dd);
@@ -364,6 +446,11 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T*
   PotT<T> pot;
 #pragma unroll
   for (int i = 0; i < kMaxFields; ++i) pot.p[i] = static_cast<T>(P.prm.p[i]);
+  constexpr bool kSplit = sizeof(T) == 4;  // remainders around FP64 offsets
+  double fbar[NF], pibar[NF];
+  T fbT[NF];
+  SplitK<T> sk{};
+  if constexpr (kSplit) split_offsets<KIND, NF, T>(P, tile_id, fbar, pibar, fbT, sk);
 
   const int n = P.n;
   const size_t n2 = size_t(n) * n;
@@ -505,12 +592,21 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T*
           f[i] = fB[i][v];
           D[i] = ((w0 * f[i] + w1 * faces) + w2 * edges) + w3 * corners;
         }
-        potential<KIND, NF, T>(f, pot, V, dV);
+        if constexpr (kSplit)
+          potential_split<KIND, NF, T>(fbT, f, pot, sk, V, dV);
+        else
+          potential<KIND, NF, T>(f, pot, V, dV);
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
           pn[i][v] = qB[i][v] + alpha * D[i] - beta * dV[i];
-          dd += double(f[i]) * double(D[i]);
-          p2 += double(pn[i][v]) * double(pn[i][v]);
+          if constexpr (kSplit) {
+            dd += (fbar[i] + double(f[i])) * double(D[i]);
+            const double q = pibar[i] + double(pn[i][v]);
+            p2 += q * q;
+          } else {
+            dd += double(f[i]) * double(D[i]);
+            p2 += double(pn[i][v]) * double(pn[i][v]);
+          }
         }
         vs += double(V);
       }
@@ -550,12 +646,14 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T*
   }
 }
 
+// ST: 0 = 7-point pass, 1 = any member of the cubic family (27-point pass),
+// 2 = 7-point pass with non-temporal result stores.
 template <typename T, int NF, int KIND, int VX, int PF, int ST>
 __device__ __forceinline__ void pass_any(const PassParams& P, int tile_id, T* lds, KSum* red) {
-  if constexpr (ST == 0)
-    pass_tile<T, NF, KIND, VX, PF>(P, tile_id, lds, red);
-  else
+  if constexpr (ST == 1)
     pass_tile27<T, NF, KIND, VX>(P, tile_id, lds, red);
+  else
+    pass_tile<T, NF, KIND, VX, PF, ST == 2>(P, tile_id, lds, red);
 }
 
 template <typename T, int NF, int KIND, int VX, int PF, int ST>
@@ -609,12 +707,19 @@ __global__ __launch_bounds__(kBlock) void batched_pass_kernel(const PassParams* 
 
 // End of stage j: H3(w h) kick of p_a, H2(w h/2) kick of p_a, owed drift
 // c = (w h/2)/a^2 of that H2, then H1(w h/2).
-__device__ void end_stage(DevScalars& S, const BgConsts& K, double w, double h, double SdD,
-                          double SV, double S2) {
+__device__ void end_stage(DevScalars& S, const BgConsts& K, const double* offs, double w,
+                          double h, double SdD, double SV, double S2) {
 #pragma clang fp contract(off)
   const double a = S.a_kick;
   const double tau = w * h;
   const double half = 0.5 * tau;
+  if (K.split) {
+    // the pass wrote the remainders around the offsets it recorded
+    for (int i = 0; i < K.nf; ++i) {
+      S.off_phi[i] = offs[i];
+      S.off_pi[i] = offs[kMaxFields + i];
+    }
+  }
   if (K.expand) {
     const double S3 = a * SdD * K.inv_dx2 - 4.0 * a * a * a * SV;
     S.S3_last = S3;
@@ -648,7 +753,8 @@ __device__ void begin_stage(DevScalars& S, const BgConsts& K, double w, double h
   S.beta = a * a * a * a * tau;
 }
 
-__device__ void finalize_body(DevScalars* sc, const double* partials, int nblocks, const BgConsts& K,
+__device__ void finalize_body(DevScalars* sc, const double* partials, const double* offs,
+                              int nblocks, const BgConsts& K,
                               double w, double w_next, double h, int has_next, int end_of_step,
                               KSum* scratch) {
   KSum v[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
@@ -663,7 +769,7 @@ __device__ void finalize_body(DevScalars* sc, const double* partials, int nblock
     const double SdD = v[0].s + v[0].c;
     const double SV = v[1].s + v[1].c;
     const double S2 = v[2].s + v[2].c;
-    end_stage(S, K, w, h, SdD, SV, S2);
+    end_stage(S, K, offs, w, h, SdD, SV, S2);
     S.parity ^= 1;
     if (end_of_step) S.eta = S.eta + h;
     if (end_of_step && S.hist != nullptr && S.hist_n < S.hist_cap) {
@@ -687,11 +793,12 @@ __device__ void finalize_body(DevScalars* sc, const double* partials, int nblock
 }
 
 __global__ __launch_bounds__(kBlock) void stage_finalize_kernel(DevScalars* sc, const double* partials,
-                                                               int nblocks, BgConsts K, double w,
-                                                               double w_next, double h, int has_next,
+                                                               const double* offs, int nblocks,
+                                                               BgConsts K, double w, double w_next,
+                                                               double h, int has_next,
                                                                int end_of_step) {
   __shared__ KSum scratch[4 * 3];
-  finalize_body(sc, partials, nblocks, K, w, w_next, h, has_next, end_of_step, scratch);
+  finalize_body(sc, partials, offs, nblocks, K, w, w_next, h, has_next, end_of_step, scratch);
 }
 
 // One workgroup per run of a batch.
@@ -700,7 +807,8 @@ __global__ __launch_bounds__(kBlock) void batched_finalize_kernel(const BatchRun
                                                                  int has_next, int end_of_step) {
   __shared__ KSum scratch[4 * 3];
   const BatchRun& R = runs[blockIdx.x];
-  finalize_body(R.sc, R.partials, R.ntiles, R.bg, w, w_next, h, has_next, end_of_step, scratch);
+  finalize_body(R.sc, R.partials, R.offs, R.ntiles, R.bg, w, w_next, h, has_next, end_of_step,
+                scratch);
 }
 
 __global__ void batched_begin_kernel(const BatchRun* __restrict__ runs, int nruns, double w,
@@ -731,6 +839,7 @@ PassParams make_params(const LatView& v) {
   }
   P.sc = v.sc;
   P.partials = v.partials;
+  P.offs = v.offs;
   P.sink = v.sink;
   P.prm = v.prm;
   for (int k = 0; k < 4; ++k) P.stc[k] = v.st.c[k];
@@ -773,7 +882,19 @@ PassKernel pick_t(const Tile& t, int st) {
     return k;
   }
   if constexpr (NF <= 2) {
-    if (t.pf == 2) {
+    const int depth = pf_depth(t.pf);
+    if (pf_nt(t.pf) && t.vx >= 2) {
+      // non-temporal result stores (2 or 4 sites per lane)
+      if (depth == 2) {
+        k.fn = t.vx == 4 ? pass_kernel<T, NF, KIND, 4, 2, 2> : pass_kernel<T, NF, KIND, 2, 2, 2>;
+        k.bfn = t.vx == 4 ? batched_pass_kernel<T, NF, KIND, 4, 2, 2>
+                          : batched_pass_kernel<T, NF, KIND, 2, 2, 2>;
+      } else {
+        k.fn = t.vx == 4 ? pass_kernel<T, NF, KIND, 4, 1, 2> : pass_kernel<T, NF, KIND, 2, 1, 2>;
+        k.bfn = t.vx == 4 ? batched_pass_kernel<T, NF, KIND, 4, 1, 2>
+                          : batched_pass_kernel<T, NF, KIND, 2, 1, 2>;
+      }
+    } else if (depth == 2) {
       k.fn = t.vx == 4 ? pass_kernel<T, NF, KIND, 4, 2, 0>
                        : (t.vx == 2 ? pass_kernel<T, NF, KIND, 2, 2, 0>
                                     : pass_kernel<T, NF, KIND, 1, 2, 0>);
@@ -824,8 +945,10 @@ PassKernel pick(int prec, int pot, int nf, const Tile& t, int st) {
 
 hipError_t launch_pass(const LatView& v, hipStream_t s) {
   if (v.nf < 1 || v.nf > kMaxFields) return hipErrorInvalidValue;
+  if (!pf_valid(v.tile.pf)) return hipErrorInvalidValue;
   if (v.nf > 2 && (v.tile.vx != 1 || v.tile.pf != 1)) return hipErrorInvalidValue;
   if (v.st.kind != 0 && (v.tile.vx > 2 || v.tile.pf != 1)) return hipErrorInvalidValue;
+  if (pf_nt(v.tile.pf) && v.tile.vx < 2) return hipErrorInvalidValue;
   // the 27-point pass needs lanes for 2 rows + 2 columns + 4 corners of halo
   if (v.st.kind != 0 && 2 * v.tile.tx + 2 * v.tile.ty + 4 > kBlock) return hipErrorInvalidValue;
   const PassKernel k = pick(v.prec, v.pot, v.nf, v.tile, v.st.kind);
@@ -878,7 +1001,7 @@ int pass_blocks_per_cu(int prec, int pot, int nf, const Tile& t, int stencil_kin
 
 hipError_t launch_stage_finalize(const LatView& v, double w, double w_next, double h, int has_next,
                                  int end_of_step, hipStream_t s) {
-  hipLaunchKernelGGL(stage_finalize_kernel, dim3(1), dim3(kBlock), 0, s, v.sc, v.partials,
+  hipLaunchKernelGGL(stage_finalize_kernel, dim3(1), dim3(kBlock), 0, s, v.sc, v.partials, v.offs,
                      v.tile.nblocks(), v.bg, w, w_next, h, has_next, end_of_step);
   return hipGetLastError();
 }

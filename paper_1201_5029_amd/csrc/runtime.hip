@@ -228,7 +228,7 @@ size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 // starting on a 256-byte boundary) and the small buffers below, at these
 // offsets inside one block.
 struct AuxLayout {
-  size_t sc, partials, sink, sums, energies, spec, total;
+  size_t sc, offs, partials, sink, sums, energies, spec, total;
   AuxLayout() {
     size_t o = 0;
     auto take = [&o](size_t bytes) {
@@ -237,6 +237,7 @@ struct AuxLayout {
       return at;
     };
     sc = take(sizeof(DevScalars));
+    offs = take(sizeof(double) * 2 * kMaxFields);
     partials = take(partial_doubles() * sizeof(double));
     sink = take(kSinkBytes);
     sums = take(sizeof(double) * (5 * kMaxFields + 1));
@@ -626,6 +627,8 @@ sl_status create_impl(const sl_config* cfg, void* hip_stream, void* const* user,
   v.bg.mpl2 = cfg->mpl * cfg->mpl;
   v.bg.L = cfg->L;
   v.bg.expand = cfg->expansion == SL_EXPAND_SELF ? 1 : 0;
+  v.bg.split = cfg->precision == SL_FP32 ? 1 : 0;
+  v.bg.nf = cfg->nfields;
   v.st = Stencil{{-6.0, 1.0, 0.0, 0.0}, 0, 0};
   {
     int tx, vx, pf;
@@ -673,6 +676,7 @@ sl_status create_impl(const sl_config* cfg, void* hip_stream, void* const* user,
     char* base = static_cast<char*>(L->aux_mem);
     v.sc = reinterpret_cast<DevScalars*>(base + aux.sc);
     v.partials = reinterpret_cast<double*>(base + aux.partials);
+    v.offs = reinterpret_cast<double*>(base + aux.offs);
     v.sink = base + aux.sink;
     L->sums_dev = reinterpret_cast<double*>(base + aux.sums);
     L->energies_dev = reinterpret_cast<sl_energies_t*>(base + aux.energies);
@@ -692,7 +696,8 @@ sl_status create_impl(const sl_config* cfg, void* hip_stream, void* const* user,
     }
   }
   (void)hipMemsetAsync(v.sc, 0, sizeof(DevScalars), L->stream);
-  if (launch_reset_scalars(v, cfg->a0, 0.0, L->stream) != hipSuccess ||
+  (void)hipMemsetAsync(v.offs, 0, sizeof(double) * 2 * kMaxFields, L->stream);
+  if (launch_reset_scalars(v, cfg->a0, 0.0, Offsets{}, L->stream) != hipSuccess ||
       hipStreamSynchronize(L->stream) != hipSuccess) {
     free_all(L);
     delete L;
@@ -776,8 +781,20 @@ sl_status sl_init_fluctuations(sl_lattice* L, const double* phi0, const double* 
   if (kind == SL_FLUCT_VACUUM && !hessian_diag(L->pot_kind, nf, L->pot_raw, phi0, m2eff))
     return fail(SL_E_INVALID, "effective mass undefined at the homogeneous point");
 
-  HIP_TRY(launch_reset_scalars(L->v, L->cfg.a0, 0.0, L->stream));
-  HIP_TRY(launch_fill_homogeneous(L->v, phi0, pi0, L->stream));
+  // FP32 storage keeps the homogeneous values as FP64 offsets and stores
+  // only the fluctuations; FP64 storage stores the whole values
+  Offsets off{};
+  double base[kMaxFields] = {};
+  for (int i = 0; i < nf; ++i) {
+    if (L->v.bg.split) {
+      off.phi[i] = phi0[i];
+      off.pi[i] = pi0[i];
+    } else {
+      base[i] = phi0[i];
+    }
+  }
+  HIP_TRY(launch_reset_scalars(L->v, L->cfg.a0, 0.0, off, L->stream));
+  HIP_TRY(launch_fill_homogeneous(L->v, phi0, pi0, off, L->stream));
   if (kind == SL_FLUCT_VACUUM) {
     FftScratch S;
     sl_status st = fft_alloc(L, S);
@@ -786,7 +803,7 @@ sl_status sl_init_fluctuations(sl_lattice* L, const double* phi0, const double* 
       HIP_TRY(launch_vacuum_modes(L->v, S.a, i, m2eff[i], amplitude, seed, L->stream));
       st = dft3(L, S, +1);
       if (st != SL_OK) return st;
-      HIP_TRY(launch_add_real(L->v, S.b, i, phi0[i], 1.0, L->stream));
+      HIP_TRY(launch_add_real(L->v, S.b, i, base[i], 1.0, L->stream));
     }
     HIP_TRY(hipStreamSynchronize(L->stream));
   } else if (kind == SL_FLUCT_WHITE) {
@@ -799,7 +816,7 @@ sl_status sl_init_fluctuations(sl_lattice* L, const double* phi0, const double* 
     }
     hipError_t e = hipSuccess;
     for (int i = 0; i < nf && e == hipSuccess; ++i)
-      e = launch_white(L->v, g, mean, i, phi0[i], amplitude, seed, L->stream);
+      e = launch_white(L->v, g, mean, i, base[i], amplitude, seed, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     (void)hipFree(g);
     (void)hipFree(mean);
@@ -830,7 +847,20 @@ sl_status sl_set_fields(sl_lattice* L, const double* phi, const double* pi, doub
   if (e == hipSuccess)
     e = hipMemcpyAsync(stage + count, pi, count * sizeof(double), hipMemcpyHostToDevice, L->stream);
   const bool solve = std::isnan(p_a);
-  if (e == hipSuccess) e = launch_import(L->v, stage, stage + count, a, solve ? 0.0 : p_a, L->stream);
+  // FP32 storage: remainders around each array's lattice mean (FP64 offsets)
+  Offsets off{};
+  if (L->v.bg.split) {
+    for (int i = 0; i < L->cfg.nfields; ++i) {
+      double sp = 0.0, sq = 0.0;
+      for (size_t k = 0; k < L->n3; ++k) {
+        sp += phi[i * L->n3 + k];
+        sq += pi[i * L->n3 + k];
+      }
+      off.phi[i] = sp / double(L->n3);
+      off.pi[i] = sq / double(L->n3);
+    }
+  }
+  if (e == hipSuccess) e = launch_import(L->v, stage, stage + count, a, solve ? 0.0 : p_a, off, L->stream);
   if (e == hipSuccess) e = launch_sum_pi2(L->v, L->stream);
   if (e == hipSuccess && solve) e = launch_energies(L->v, L->sums_dev, L->energies_dev, 1, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
@@ -1145,7 +1175,8 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
   if (reps < 1 || reps > 100) return fail(SL_E_INVALID, "reps must be in [1, 100]");
   if (vx_only != 0 && vx_only != 1 && vx_only != 2 && vx_only != 4)
     return fail(SL_E_INVALID, "vx_only must be 0, 1, 2 or 4");
-  if (pf_only != 0 && pf_only != 1 && pf_only != 2) return fail(SL_E_INVALID, "pf_only must be 0, 1 or 2");
+  if (pf_only != 0 && !pf_valid(pf_only))
+    return fail(SL_E_INVALID, "pf_only must be 0 or a pass mode (1, 2, 5 or 6)");
   const int n = L->cfg.n;
   // a batch member keeps its per-lane shape (the batch's kernel is built
   // for it)
@@ -1164,13 +1195,20 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
   for (int vx : {1, 2, 4}) {
     if (n % vx != 0 || (many && vx != 1) || (st27 && vx > 2) || (vx_only && vx != vx_only)) continue;
     for (int tx : tx_candidates(n, vx)) {
-      for (int pf : {1, 2}) {
+      for (int pf : {1, 2, 1 | kPfNontemporal, 2 | kPfNontemporal}) {
         if (((many || st27) && pf != 1) || (pf_only && pf != pf_only)) continue;
+        if (pf_nt(pf) && vx < 2) continue;
         std::vector<int> tzs = {0};
         for (int d : {16, 8, 4, 2}) {
           const int tz = n / d;
           if (tz >= 8 && std::find(tzs.begin(), tzs.end(), tz) == tzs.end()) tzs.push_back(tz);
         }
+        // lattices small enough to stay in the last-level cache are bound by
+        // the latency of each workgroup's serial z-march, not by bandwidth:
+        // short chunks give more, shorter marches
+        if (n <= 128)
+          for (int tz : {1, 2, 4})
+            if (std::find(tzs.begin(), tzs.end(), tz) == tzs.end()) tzs.push_back(tz);
         for (int tz : tzs) {
           const Tile t = tile_geometry(n, tx, vx, tz > 0 ? tz : n, pf);
           if (long(t.nblocks()) > kMaxPassBlocks) continue;
@@ -1194,6 +1232,7 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
   frozen.c_next = 0.0;
   frozen.alpha = 0.0;
   frozen.beta = 0.0;
+
   frozen.hist = nullptr;  // tuning stages are not recorded
   HIP_TRY(hipMemcpy(L->v.sc, &frozen, sizeof frozen, hipMemcpyHostToDevice));
   hipEvent_t e0, e1;
@@ -1273,11 +1312,12 @@ sl_status sl_set_tile(sl_lattice* L, int32_t tx, int32_t vx, int32_t tz, int32_t
   if (tx < 8 || tx > 64) return fail(SL_E_INVALID, "tx must be in [8, 64]");
   if (vx != 1 && vx != 2 && vx != 4) return fail(SL_E_INVALID, "vx must be 1, 2 or 4");
   if (L->cfg.n % vx != 0) return fail(SL_E_INVALID, "vx = %d needs n divisible by %d", vx, vx);
-  if (pf != 1 && pf != 2) return fail(SL_E_INVALID, "pf must be 1 or 2");
+  if (!pf_valid(pf)) return fail(SL_E_INVALID, "pf must be 1 or 2, plus 4 for non-temporal stores");
   if (L->cfg.nfields > 2 && (vx != 1 || pf != 1))
     return fail(SL_E_INVALID, "more than two fields run with vx = 1 and pf = 1 only");
   if (L->v.st.kind != 0 && (vx > 2 || pf != 1))
     return fail(SL_E_INVALID, "the 27-point stencil runs with vx = 1 or 2 and pf = 1");
+  if (pf_nt(pf) && vx < 2) return fail(SL_E_INVALID, "non-temporal stores need vx = 2 or 4");
   if (L->batch && (vx != L->v.tile.vx || pf != L->v.tile.pf))
     return fail(SL_E_STATE, "a batch member keeps its vx and pf (remove it from the batch first)");
   if (tz < 0 || tz > L->cfg.n) return fail(SL_E_INVALID, "tz must be in [0, n]");
@@ -1450,6 +1490,7 @@ sl_status batch_upload(sl_batch* B) {
     pp[r] = pass_params(L->v);
     br[r].sc = L->v.sc;
     br[r].partials = L->v.partials;
+    br[r].offs = L->v.offs;
     br[r].bg = L->v.bg;
     br[r].ntiles = L->v.tile.nblocks();
     br[r].pad = 0;
@@ -1666,8 +1707,9 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
   for (int vx : {1, 2, 4}) {
     bool ok = !(B->nf > 2 && vx != 1) && !(B->st_kind != 0 && vx > 2);
     for (const auto& sz : sizes) ok = ok && sz.second % vx == 0;
-    for (int pf : {1, 2})
-      if (ok && !((B->nf > 2 || B->st_kind != 0) && pf != 1)) lane_shapes.push_back({vx, pf});
+    for (int pf : {1, 2, 1 | kPfNontemporal, 2 | kPfNontemporal})
+      if (ok && !((B->nf > 2 || B->st_kind != 0) && pf != 1) && !(pf_nt(pf) && vx < 2))
+        lane_shapes.push_back({vx, pf});
   }
   batch_drop_graph(B);
   // shapes are tuned with one workgroup per tile; phase 3 picks the grid

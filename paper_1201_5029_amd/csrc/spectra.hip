@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void meff_kernel(Bufs4 B, const DevScalars*
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
       const size_t o = field_site(i, e, zs, n2);
-      f[i] = fma(c, double(pi[o]), double(phi[o]));
+      f[i] = (sc->off_phi[i] + c * sc->off_pi[i]) + fma(c, double(pi[o]), double(phi[o]));
     }
     d2v_diag<KIND, NF, double>(f, pot, d);
 #pragma unroll
@@ -101,9 +101,10 @@ template <typename T>
 __global__ void momentum_to_complex_kernel(Bufs4 B, const DevScalars* sc, size_t n3, size_t n2,
                                            int zs, int field, double2* F) {
   const T* pi = static_cast<const T*>(B.pi[sc->parity]);
+  const double off = sc->off_pi[field];
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n3; e += stride)
-    F[e] = make_double2(double(pi[field_site(field, e, zs, n2)]), 0.0);
+    F[e] = make_double2(off + double(pi[field_site(field, e, zs, n2)]), 0.0);
 }
 
 __device__ __forceinline__ int shell_index(long long m) {

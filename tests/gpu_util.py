@@ -65,6 +65,21 @@ def rel_l2(got, ref):
     return worst
 
 
+def fluct_rel_l2(got, ref):
+    """rel-L2 of the fluctuation part of each array (its own lattice mean
+    removed), worst array: ||(g - <g>) - (r - <r>)||_2 / ||r - <r>||_2.  In
+    the linear regime the homogeneous value dominates the full-field
+    measure; this one sees the error of the perturbations themselves."""
+    worst = 0.0
+    for g, r in zip(got, ref):
+        dr = r - r.mean()
+        nr = np.linalg.norm(dr)
+        if nr == 0:
+            continue
+        worst = max(worst, float(np.linalg.norm((g - g.mean()) - dr) / nr))
+    return worst
+
+
 def compare_state(g, o):
     """(field error, momentum error, rel error of a, rel error of p_a)."""
     phi, pi = g.get_fields()

@@ -55,15 +55,24 @@ def test_caller_buffers_equal_owned(precision):
         assert np.array_equal(fo, fe) and np.array_equal(po, pe)
         assert own.background() == ext.background()
         # the state lives in the caller's arrays: the current buffer holds the
-        # storage-precision fields (drift pending, so compare the momenta)
+        # storage-precision momenta (drift pending, so compare the momenta);
+        # FP32 storage holds each momentum's remainder around the handle's
+        # FP64 homogeneous offset, so there the difference is one constant
+        # per field
         ext.synchronize()
         host = np.empty(nf * n ** 3, dtype=np.float64 if precision == "f64" else np.float32)
         pis = []
         for k in (1, 3):
             assert hip.hipMemcpy(host.ctypes.data, bufs[k], nbytes, 2) == 0
             # device layout [z][field][y][x] -> [field][z][y][x]
-            pis.append(host.copy().reshape(n, nf, n, n).transpose(1, 0, 2, 3))
-        assert any(np.array_equal(x.astype(np.float64), pe) for x in pis)
+            pis.append(host.copy().reshape(n, nf, n, n).transpose(1, 0, 2, 3).astype(np.float64))
+        if precision == "f64":
+            assert any(np.array_equal(x, pe) for x in pis)
+        else:
+            def offset_only(x):
+                return all(np.ptp(pe[i] - x[i]) <= 1e-14 * max(1.0, np.abs(pe[i]).max())
+                           for i in range(nf))
+            assert any(offset_only(x) for x in pis)
         ext.close()
         own.close()
         assert hip.hipMemcpy(host.ctypes.data, bufs[1], nbytes, 2) == 0   # still valid

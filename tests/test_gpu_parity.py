@@ -13,7 +13,7 @@ import pytest
 import oracle
 import paper_1201_5029_amd as sl
 import synth
-from gpu_util import compare_state, gpu_lattice, max_rel, oracle_lattice, rel_l2, say
+from gpu_util import compare_state, fluct_rel_l2, gpu_lattice, max_rel, oracle_lattice, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 
@@ -86,10 +86,12 @@ def test_preheat32_fp32_storage():
     o.evolve(100, c["dt"], 4)
     gphi, gpi = g.get_fields()
     e1, e2 = rel_l2(gphi, o.phi), rel_l2(gpi, o.pi)
+    f1, f2 = fluct_rel_l2(gphi, o.phi), fluct_rel_l2(gpi, o.pi)
     resid = g.energies()["friedmann_residual"]
     _, a, pa = g.background()
-    say("preheat32 fp32 rel-L2", e1, e2, "residual", resid, "a", a, o.a)
+    say("preheat32 fp32 rel-L2", e1, e2, "fluctuations", f1, f2, "residual", resid, "a", a, o.a)
     assert max(e1, e2) <= FP32_L2_TOL
+    assert max(f1, f2) <= FP32_L2_TOL
     assert resid <= FP32_RESID_TOL
     assert a == pytest.approx(o.a, rel=1e-6)
 
@@ -104,9 +106,11 @@ def test_preheat32_end_to_end_fp32():
     o.evolve(100, c["dt"], 4)
     gphi, gpi = g.get_fields()
     e1, e2 = rel_l2(gphi, o.phi), rel_l2(gpi, o.pi)
+    f1, f2 = fluct_rel_l2(gphi, o.phi), fluct_rel_l2(gpi, o.pi)
     resid = g.energies()["friedmann_residual"]
-    say("end-to-end fp32", e1, e2, resid)
+    say("end-to-end fp32", e1, e2, "fluctuations", f1, f2, resid)
     assert max(e1, e2) <= FP32_L2_TOL and resid <= FP32_RESID_TOL
+    assert max(f1, f2) <= FP32_L2_TOL
 
 
 @pytest.mark.parametrize("order,steps", [(2, 30), (6, 20), (8, 10)])

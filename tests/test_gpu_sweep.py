@@ -71,6 +71,27 @@ def _cases_lanes(count=16, seed=20120298):
 CASES_LANES = _cases_lanes()
 
 
+def _cases_nontemporal(count=10, seed=20120297):
+    """Cases for the pass modes with non-temporal result stores (pf = 5, 6:
+    depth 1 or 2 plus 4), which the 7-point pass runs for up to two fields
+    with 2 or 4 sites per lane."""
+    rng = np.random.default_rng(seed)
+    models = [m for m in MODELS if len(m[2]) <= 2]
+    out = []
+    for _ in range(count):
+        kind, params, base, mpl = models[int(rng.integers(len(models)))]
+        n = int(2 * rng.integers(2, 21))
+        vx = 4 if (n % 4 == 0 and rng.random() < 0.6) else 2
+        tx = int(rng.choice([8, 16, 32, 64])) if vx == 4 else int(rng.choice([16, 32, 64]))
+        pf = int(rng.choice([5, 6]))
+        tz = int(rng.integers(0, n + 1))
+        out.append((kind, params, base, mpl, n, None, (tx, vx, tz, pf)))
+    return out
+
+
+CASES_NT = _cases_nontemporal()
+
+
 def _run_case(case, spec, seed):
     kind, params, base, mpl, n, stencil, tile = spec
     nf = len(base)
@@ -100,12 +121,18 @@ def test_sweep_lanes(case):
     _run_case(case, CASES_LANES[case], 9100 + case)
 
 
-@pytest.mark.parametrize("case", range(0, len(CASES), 3))
+@pytest.mark.parametrize("case", range(len(CASES_NT)))
+def test_sweep_nontemporal(case):
+    _run_case(case, CASES_NT[case], 9200 + case)
+
+
+@pytest.mark.parametrize("case", list(range(0, len(CASES), 3)) +
+                         list(range(len(CASES), len(CASES) + len(CASES_NT), 2)))
 def test_sweep_fp32_storage(case):
     """Every third case with FP32 field storage: relative L2 error of the
     fields and momenta within the FP32 gate (1e-4)."""
     from gpu_util import rel_l2
-    kind, params, base, mpl, n, stencil, tile = CASES[case]
+    kind, params, base, mpl, n, stencil, tile = (CASES + CASES_NT)[case]
     nf = len(base)
     L = 0.5 * n
     scale = max(abs(b) for b in base)
