@@ -221,6 +221,23 @@ sl_status sl_energies(sl_lattice* lat, sl_energies_t* out);
 sl_status sl_spectrum(sl_lattice* lat, int32_t field, int32_t nbins,
                       double* k_out, double* p_out, int64_t* count_out);
 
+/* sl_spectrum for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and outputs, with the transform buffers and
+ * binning partials in a library-owned static device array of 32 MiB per
+ * GPU (held until the process ends) instead of per-call allocations.
+ * Accepts lattices whose scratch fits it: 32 n^3 + 16 n bytes of transform
+ * buffers and twiddles (rounded up to 256) plus 24 nbins m bytes of binning
+ * partials, m = min(ceil(n^3 / 256), 256) -- e.g. n <= 86 with any nbins,
+ * n = 96 with up to 853 bins, n <= 101 with a few bins.  Every call on one GPU shares that array, so calls that
+ * overlap on one GPU (two threads, or two streams without an ordering
+ * between them) race; the array keeps the last call's contents and each
+ * call writes all it reads.  SL_E_INVALID beyond the limit (with the
+ * bytes needed in sl_last_error) and as sl_spectrum otherwise; allocates
+ * no device memory.  Synchronises. */
+sl_status sl_spectrum_noalloc(sl_lattice* lat, int32_t field, int32_t nbins, double* k_out,
+                              double* p_out, int64_t* count_out);
+
 /* Field, energy-density and number-density spectra of phi_field (the
  * post-processing spectra of Sec. 2.4), from F_n = DFT(phi)/n^3 and
  * P_n = DFT(pi)/n^3 of the synchronised state, k_eff^2 of the lattice's

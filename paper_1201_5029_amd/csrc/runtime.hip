@@ -350,6 +350,13 @@ struct sl_lattice {
 void batch_member_changed(sl_batch* B);
 hipStream_t batch_stream(const sl_batch* B);
 
+// Device scratch of sl_spectrum_noalloc, the spectrum entry point for
+// callers that cannot allocate device memory: one array per GPU the library
+// runs on, held until the process ends and shared by every such call on
+// that GPU (calls that overlap on one GPU race on it).
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 // Host bookkeeping of a scalar record read back from the device: the last
@@ -452,6 +459,13 @@ size_t spectrum_part_bytes(int n, int nbins) {
   return size_t(spectrum_blocks(n)) * 3 * size_t(nbins) * sizeof(double);
 }
 
+// Scratch of one spectrum call: two transform buffers, the twiddles and the
+// binning partials (256-byte aligned).
+size_t spectrum_noalloc_bytes(int n, int nbins) {
+  const size_t nn = size_t(n), n3 = nn * nn * nn;
+  return round256(2 * n3 * sizeof(double2) + nn * sizeof(double2)) + spectrum_part_bytes(n, nbins);
+}
+
 sl_status spectrum_check(sl_lattice* L, int field, int nbins, const double* k_out,
                          const double* p_out, const int64_t* count_out) {
   if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
@@ -487,6 +501,31 @@ sl_status spectrum_run(sl_lattice* L, int field, int nbins, double2* a, double2*
   return read_scalars(L, &Sc);
 }
 
+// Address of this file's `scratch` array on each device, looked up once per
+// device with that device current (the array's name is a host-side stand-in
+// in host code; only the looked-up address may reach a kernel or a copy).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+sl_status noalloc_scratch(int device, unsigned char** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return fail(SL_E_DEVICE, "device %d out of range", device);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != device) HIP_TRY(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || p == nullptr)
+      return fail(SL_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                  hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return SL_OK;
+}
 
 }  // namespace
 
@@ -1069,6 +1108,29 @@ sl_status sl_spectrum(sl_lattice* L, int32_t field, int32_t nbins, double* k_out
   st = spectrum_run(L, field, nbins, S.a, S.b, S.tw, part, k_out, p_out, count_out);
   (void)hipFree(part);
   return st;
+}
+
+sl_status sl_spectrum_noalloc(sl_lattice* L, int32_t field, int32_t nbins, double* k_out,
+                              double* p_out, int64_t* count_out) {
+  sl_status st = spectrum_check(L, field, nbins, k_out, p_out, count_out);
+  if (st != SL_OK) return st;
+  const size_t n = size_t(L->cfg.n), n3 = n * n * n;
+  const size_t need = spectrum_noalloc_bytes(L->cfg.n, nbins);
+  if (need > kNoAllocScratchBytes)
+    return fail(SL_E_INVALID,
+                "sl_spectrum_noalloc: n = %d with %d bins needs %zu bytes of scratch, above its "
+                "%zu-byte maximum (use sl_spectrum)",
+                L->cfg.n, nbins, need, kNoAllocScratchBytes);
+  unsigned char* base = nullptr;
+  st = noalloc_scratch(L->device, &base);
+  if (st != SL_OK) return st;
+  // layout: transform buffers a, b (n^3 complex each), twiddles (n), then
+  // the binning partials; every kernel writes its part before reading it
+  double2* a = reinterpret_cast<double2*>(base);
+  double2* b = a + n3;
+  double2* tw = b + n3;
+  double* part = reinterpret_cast<double*>(base + round256(2 * n3 * sizeof(double2) + n * sizeof(double2)));
+  return spectrum_run(L, field, nbins, a, b, tw, part, k_out, p_out, count_out);
 }
 
 sl_status sl_spectra(sl_lattice* L, int32_t field, int32_t nbins, double* k_out, double* pf_out,

@@ -36,7 +36,7 @@ EXPORTS = (
     "sl_linear_get_fields", "sl_linear_get_background", "sl_linear_classes",
     "sl_linear_synchronize", "sl_linear_set_kernel_timing", "sl_linear_kernel_timing",
     "sl_batch_autotune", "sl_spectra", "sl_set_history", "sl_get_history",
-    "sl_batch_set_grid", "sl_batch_get_grid",
+    "sl_batch_set_grid", "sl_batch_get_grid", "sl_spectrum_noalloc",
 )
 
 #: Members of the cubic stencil family of eq. (2.7): (centre, face, edge,
@@ -93,6 +93,7 @@ def load():
         "sl_evolve": (I32, [P, I64, D, I32]),
         "sl_energies": (I32, [P, ctypes.POINTER(Energies)]),
         "sl_spectrum": (I32, [P, I32, I32, dp, dp, ctypes.POINTER(ctypes.c_int64)]),
+        "sl_spectrum_noalloc": (I32, [P, I32, I32, dp, dp, ctypes.POINTER(ctypes.c_int64)]),
         "sl_get_fields": (I32, [P, P, P]),
         "sl_set_fields": (I32, [P, P, P, D, D]),
         "sl_get_background": (I32, [P, dp, dp, dp]),
@@ -322,6 +323,18 @@ class Lattice:
                                      k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      c.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return k, p, c
+
+    def spectrum_noalloc(self, field, nbins):
+        """spectrum() through the entry point that allocates no device
+        memory (a static per-GPU scratch array; see the header's limits)."""
+        k = np.zeros(nbins)
+        p = np.zeros(nbins)
+        c = np.zeros(nbins, dtype=np.int64)
+        _check(self._lib.sl_spectrum_noalloc(self._h, int(field), int(nbins),
+                                             k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             c.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
         return k, p, c
 
     def spectra(self, field, nbins):
