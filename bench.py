@@ -48,7 +48,33 @@ def parse():
     p.add_argument("--serve-steps", type=int, default=500)
     p.add_argument("--tile", default=None,
                    help="tx,vx,tz,pf pass shape instead of the autotuner's choice")
+    p.add_argument("--only", default=None,
+                   help="comma-separated lines to run beside the main line, for profiler "
+                        "runs: fp32, qball512, configs, batched, stencil27, linear, serve "
+                        "(the others are skipped, as with their --no- switches)")
+    p.add_argument("--shapes", default=None,
+                   help="JSON object (or a file holding one) of pass shapes per line instead "
+                        "of the tuners' choices: keys main, fp32, qball512, stencil27, "
+                        "preheat256_order4, preheat128, oscillon128 ('tx,vx,tz,pf') and "
+                        "batched (list of [n, tx, vx, tz, pf]); a run prints the shapes it "
+                        "used under 'shapes'")
     return p.parse_args()
+
+
+SHAPES = {}
+
+
+def load_shapes(arg):
+    """Pass shapes given on the command line (a JSON object or a file)."""
+    if not arg:
+        return {}
+    text = open(arg).read() if os.path.exists(arg) else arg
+    return json.loads(text)
+
+
+def tile_str(t):
+    """'tx,vx,tz,pf' of a tile() tuple (tx, vx, ty, tz, pf)."""
+    return "%d,%d,%d,%d" % (t[0], t[1], t[3], t[4])
 
 
 def log(*a):
@@ -81,6 +107,23 @@ def measured_traffic(workload, precision, tile):
                 and f[6] == h):
             return int(f[7])
     return None
+
+
+def _rel_l2(a, b):
+    import numpy as np
+    return max(float(np.linalg.norm(x - y) / np.linalg.norm(y)) for x, y in zip(a, b))
+
+
+def _fluct_rel_l2(a, b):
+    """rel-L2 of the fluctuation part (each array's mean removed)."""
+    import numpy as np
+    out = 0.0
+    for x, y in zip(a, b):
+        dy = y - y.mean()
+        ny = np.linalg.norm(dy)
+        if ny > 0:
+            out = max(out, float(np.linalg.norm((x - x.mean()) - dy) / ny))
+    return out
 
 
 def measure(sl, recipe, steps, warmup, tile=None, fields=None, diag=None):
@@ -216,10 +259,17 @@ def measure_batched(sl, nruns=96, steps=100):
     recipes = synth.delta_n_scan(nruns=nruns, steps=steps)
     dt, order = recipes[0]["dt"], recipes[0]["order"]
     lats = [sl.from_recipe(r) for r in recipes]
+    fixed = {int(s[0]): s[1:] for s in SHAPES.get("batched", [])}
+    for r, lat in zip(recipes, lats):
+        if r["n"] in fixed:
+            lat.set_tile(*fixed[r["n"]])
     b = sl.Batch()
     for lat in lats:
         b.add(lat)
-    pass_ms = b.autotune(reps=5)
+    if fixed:
+        pass_ms = b.time_pass(reps=5)
+    else:
+        pass_ms = b.autotune(reps=5)
     grid = b.grid()
     shapes = sorted(set((r["n"],) + tuple(lat.tile()) for r, lat in zip(recipes, lats)))
     b.step(10, dt, order)          # captures the batch's chunk graph before the timed region
@@ -228,6 +278,21 @@ def measure_batched(sl, nruns=96, steps=100):
     b.step(steps, dt, order)
     b.synchronize()
     wall = time.perf_counter() - t0
+    # error of one member of each size against the same run alone in FP64
+    # (the FP64 path is the one pinned to the oracle)
+    import numpy as np
+    err, seen = {}, set()
+    for j, r in enumerate(recipes):
+        if r["n"] in seen:
+            continue
+        seen.add(r["n"])
+        ref = sl.from_recipe(dict(r, precision="f64"))
+        ref.evolve(10 + steps, dt, order)
+        f64, p64 = ref.get_fields()
+        f32, p32 = lats[j].get_fields()
+        ref.close()
+        err[str(r["n"])] = {"phi_rel_l2": _rel_l2(f32, f64), "pi_rel_l2": _rel_l2(p32, p64),
+                            "fluct_rel_l2": max(_fluct_rel_l2(f32, f64), _fluct_rel_l2(p32, p64))}
     sites = sum(r["n"] ** 3 for r in recipes)
     stages = len(sl.composition_weights(order))
     bytes_pass = 4 * 4 * 2 * sites
@@ -242,6 +307,8 @@ def measure_batched(sl, nruns=96, steps=100):
             "pass_ms": pass_ms, "pass_achieved_GBs": bytes_pass / (pass_ms * 1e-3) / 1e9,
             "pass_frac": bytes_pass / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "bytes_per_pass": bytes_pass, "shapes_n_tx_vx_ty_tz_pf": shapes,
+            "error_vs_fp64": dict(err, steps=10 + steps,
+                                  against="one member of each size advanced alone in FP64"),
             "workgroups": {"launched": grid[1],
                            "form": "persistent" if grid[0] > 0 else "one per tile"}}
 
@@ -252,7 +319,7 @@ def measure_stencil27(sl, steps=50, warmup=5):
     as the 7-point pass."""
     import synth
     r = dict(synth.preheat(n=256, order=6, dt=0.0025, precision="f64"), stencil="27")
-    wall, passes, pass_ms, e, tile = measure(sl, r, steps, warmup)
+    wall, passes, pass_ms, e, tile = measure(sl, r, steps, warmup, SHAPES.get("stencil27"))
     n3 = 256 ** 3
     avg = pass_ms / passes / 1e3
     return {"workload": "preheat two-field chaotic, 256^3, order 6, FP64, 27-point stencil "
@@ -314,11 +381,11 @@ def measure_linear(sl, n=256, steps=400, order=6, warmup=20):
 PAPER_256_ORDER4 = {"Tesla C2050": 2 * 256 ** 3 / 0.132, "GTX 470": 2 * 256 ** 3 / 0.152}
 
 
-def measure_config(sl, recipe, steps, warmup=10):
+def measure_config(sl, recipe, steps, key, warmup=10):
     """One more workload on the single-lattice path: field-site-updates/s
     and the pass's HBM roofline (for lattices that fit the 256 MB MALL the
     bandwidth is effective, not HBM-only)."""
-    wall, passes, pass_ms, e, tile = measure(sl, recipe, steps, warmup)
+    wall, passes, pass_ms, e, tile = measure(sl, recipe, steps, warmup, SHAPES.get(key))
     n3 = recipe["n"] ** 3
     nf = recipe["nfields"]
     b = 8 if recipe["precision"] == "f64" else 4
@@ -332,15 +399,62 @@ def measure_config(sl, recipe, steps, warmup=10):
             "friedmann_residual": e["friedmann_residual"]}
 
 
+def collect_shapes(out, main_tile):
+    """The pass shapes this run used, in the form --shapes takes."""
+    sh = {"main": tile_str(main_tile)}
+    for key, line in (("fp32", "fp32_storage"), ("qball512", "qball512_fp32"),
+                      ("stencil27", "stencil27_fp64"), ("preheat256_order4", "preheat256_fp64_order4"),
+                      ("preheat128", "preheat128_fp64_order6"),
+                      ("oscillon128", "oscillon128_fp32_order4")):
+        if line in out and "tile" in out[line]:
+            sh[key] = tile_str(out[line]["tile"])
+    if "batched_c4" in out:
+        sh["batched"] = [[s[0], s[1], s[2], s[4], s[5]]
+                         for s in out["batched_c4"]["shapes_n_tx_vx_ty_tz_pf"]]
+    return sh
+
+
+def fp64_error(sl, recipe, tile, steps=100):
+    """An FP32-storage line against the same recipe in FP64 storage on the
+    GPU (the path the tests pin to the oracle), `steps` steps from the same
+    device initial state: rel-L2 of the full fields and of their
+    fluctuation parts."""
+    lat = sl.from_recipe(recipe)
+    lat.set_tile(*[int(x) for x in tile_str(tile).split(",")])
+    lat.evolve(steps, recipe["dt"], recipe["order"])
+    f, q = lat.get_fields()
+    lat.close()
+    ref = sl.from_recipe(dict(recipe, precision="f64"))
+    ref.evolve(steps, recipe["dt"], recipe["order"])
+    f64, p64 = ref.get_fields()
+    ref.close()
+    return {"phi_rel_l2": _rel_l2(f, f64), "pi_rel_l2": _rel_l2(q, p64),
+            "fluct_rel_l2": max(_fluct_rel_l2(f, f64), _fluct_rel_l2(q, p64)),
+            "steps": steps, "against": "the FP64 run of the same workload on the GPU"}
+
+
 def measure_qball512(sl, steps=20, warmup=3):
     """Q-ball configuration at 512^3 (FP32 fields, 6th order): the headline
     roofline point whose working set (4.3 GB) is far beyond the 256 MB MALL."""
     import synth
     r = synth.qball(n=512, precision="f32")
-    wall, passes, pass_ms, e, tile = measure(sl, r, steps, warmup)
+    f32 = {}
+    wall, passes, pass_ms, e, tile = measure(sl, r, steps, warmup, SHAPES.get("qball512"),
+                                             fields=f32)
     n3 = 512 ** 3
     avg = pass_ms / passes / 1e3
+    # the same run in FP64 storage on the GPU (the path pinned to the oracle)
+    total = max(warmup, 33) + 2 * steps
+    ref = sl.from_recipe(dict(r, precision="f64"))
+    ref.evolve(total, r["dt"], r["order"])
+    f64, p64 = ref.get_fields()
+    ref.close()
+    err = {"phi_rel_l2": _rel_l2(f32["phi"], f64), "pi_rel_l2": _rel_l2(f32["pi"], p64),
+           "fluct_rel_l2": max(_fluct_rel_l2(f32["phi"], f64), _fluct_rel_l2(f32["pi"], p64)),
+           "steps": total, "against": "the FP64 run of the same workload on the GPU"}
+    del f32, f64, p64
     return {"workload": "Q-ball log potential, 512^3, two fields, order 6, dt 0.005, FP32 fields",
+            "error_vs_fp64": err,
             "value": n3 * 2 * steps / wall, "ms_per_step": wall / steps * 1e3,
             "pass_ms": avg * 1e3, "achieved_GBs": 4 * 4 * 2 * n3 / avg / 1e9,
             "frac": 4 * 4 * 2 * n3 / avg / 1e9 / HBM_PEAK_GBS, "tile": list(tile),
@@ -433,6 +547,16 @@ def cpu_parity_config():
 
 def main():
     args = parse()
+    SHAPES.update(load_shapes(args.shapes))
+    if args.only is not None:
+        keep = set(x for x in args.only.split(",") if x)
+        args.no_fp32 = "fp32" not in keep
+        args.no_512 = "qball512" not in keep
+        args.no_configs = "configs" not in keep
+        args.no_batched = "batched" not in keep
+        args.no_27 = "stencil27" not in keep
+        args.no_linear = "linear" not in keep
+        args.no_serve = "serve" not in keep
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the method's multi-GPU forms are not built "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
@@ -451,7 +575,8 @@ def main():
     log("workload", recipe["workload"], args.n, "order", args.order, args.precision)
     f64_fields = {}
     diag = {}
-    wall, passes, pass_ms, e, tile = measure(sl, recipe, args.steps, args.warmup, args.tile,
+    wall, passes, pass_ms, e, tile = measure(sl, recipe, args.steps, args.warmup,
+                                             args.tile or SHAPES.get("main"),
                                              fields=f64_fields if args.precision == "f64" else None,
                                              diag=diag)
     nf = recipe["nfields"]
@@ -503,13 +628,12 @@ def main():
     if not args.no_fp32 and args.precision == "f64":
         r32 = dict(recipe, precision="f32")
         f32_fields = {}
-        w32, p32, ms32, e32, tile32 = measure(sl, r32, args.steps, args.warmup, fields=f32_fields)
-        import numpy as np
-
-        def rel_l2(a, b):
-            return max(float(np.linalg.norm(x - y) / np.linalg.norm(y)) for x, y in zip(a, b))
-        err = {"phi_rel_l2": rel_l2(f32_fields["phi"], f64_fields["phi"]),
-               "pi_rel_l2": rel_l2(f32_fields["pi"], f64_fields["pi"]),
+        w32, p32, ms32, e32, tile32 = measure(sl, r32, args.steps, args.warmup, SHAPES.get("fp32"),
+                                              fields=f32_fields)
+        err = {"phi_rel_l2": _rel_l2(f32_fields["phi"], f64_fields["phi"]),
+               "pi_rel_l2": _rel_l2(f32_fields["pi"], f64_fields["pi"]),
+               "fluct_rel_l2": max(_fluct_rel_l2(f32_fields["phi"], f64_fields["phi"]),
+                                   _fluct_rel_l2(f32_fields["pi"], f64_fields["pi"])),
                "steps": 2 * args.steps + max(args.warmup, 33),
                "against": "the FP64 run of the same workload on the GPU (pinned to the oracle)"}
         del f32_fields, f64_fields
@@ -522,13 +646,17 @@ def main():
         out["qball512_fp32"] = measure_qball512(sl)
     if not args.no_configs and args.precision == "f64" and args.n == 256:
         log("other configurations ...")
-        o4 = measure_config(sl, synth.preheat(n=256, order=4, dt=0.0025, precision="f64"), 100)
+        o4 = measure_config(sl, synth.preheat(n=256, order=4, dt=0.0025, precision="f64"), 100,
+                            "preheat256_order4")
         o4["paper_context"] = {k: {"value": v, "ratio": o4["value"] / v}
                                for k, v in PAPER_256_ORDER4.items()}
         out["preheat256_fp64_order4"] = o4
         out["preheat128_fp64_order6"] = measure_config(
-            sl, synth.preheat(n=128, order=6, dt=0.0025, precision="f64"), 200)
-        out["oscillon128_fp32_order4"] = measure_config(sl, synth.oscillon(n=128), 200)
+            sl, synth.preheat(n=128, order=6, dt=0.0025, precision="f64"), 200, "preheat128")
+        osc = synth.oscillon(n=128)
+        out["oscillon128_fp32_order4"] = measure_config(sl, osc, 200, "oscillon128")
+        out["oscillon128_fp32_order4"]["error_vs_fp64"] = fp64_error(
+            sl, osc, out["oscillon128_fp32_order4"]["tile"])
     if not args.no_batched and args.precision == "f64" and args.n == 256:
         log("batched ensemble ...")
         out["batched_c4"] = measure_batched(sl)
@@ -547,6 +675,7 @@ def main():
         out["cpu_baseline"]["parity_32"] = cpu_pre["parity_32"]
         if "served" in out:
             out["served"]["cpu_ensemble_baseline"] = cpu_pre["ensemble"]
+    out["shapes"] = collect_shapes(out, tile)
     print(json.dumps(out), flush=True)
 
 

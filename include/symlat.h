@@ -342,6 +342,20 @@ sl_status sl_get_tile(sl_lattice* lat, int32_t* tx, int32_t* vx, int32_t* ty, in
                       int32_t* pf);
 sl_status sl_set_tile(sl_lattice* lat, int32_t tx, int32_t vx, int32_t tz, int32_t pf);
 
+/* Stage chaining of sl_evolve.  The scalar update that closes a stage
+ * (the p_a kicks of eq. (2.14) with the lattice sums of the stage, and the
+ * drift coefficient of the next) either runs as its own one-workgroup
+ * kernel after each fused pass (mode 0), or is folded into the next pass
+ * (mode 1): every workgroup of that pass reduces the previous pass's
+ * per-tile sums and forms the same scalars before its z-march, and one
+ * finalize kernel closes each captured chunk of steps.  Both modes give
+ * bitwise identical fields, background and history.  mode -1 (the
+ * default) chains lattices with at most 1024 tiles and at least 256 KiB of
+ * field traffic per tile, where the saved kernel outweighs the later start
+ * of each workgroup; mode 1 chains whenever there are at most 1024 tiles.
+ * Batches do not chain.  SL_E_INVALID for other modes. */
+sl_status sl_set_chaining(sl_lattice* lat, int32_t mode);
+
 /* Autotuner: time candidate shapes (tx in {16, 32, 64}, 8 with vx = 4, and
  * n/vx when that is in [8, 64] and not a power of two, i.e. a whole row per
  * tile; vx in {1, 2, 4} dividing n; pf in {1, 2, 5, 6}; tz in {occupancy choice,
@@ -396,7 +410,7 @@ sl_status sl_batch_get_grid(const sl_batch* batch, int32_t* requested, int32_t* 
 /* Advance every member `steps` steps (same dt and order for all). */
 sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order);
 /* Batch autotuner: every per-lane shape (vx in {1, 2, 4} dividing all
- * member sizes, pf in {1, 2}, as the field count and stencil allow) is timed
+ * member sizes, pf in {1, 2, 5, 6}, as the field count and stencil allow) is timed
  * at starting shapes (a whole row per tile, at most 64 lanes, quarter-lattice
  * z-chunks); for the three fastest, per member size (largest share
  * of sites first, two rounds of coordinate descent) the same tx candidates
@@ -414,6 +428,11 @@ sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order
  * best_ms (may be NULL) receives the final pass time.  SL_E_STATE for an
  * empty batch. */
 sl_status sl_batch_autotune(sl_batch* batch, int32_t reps, double* best_ms);
+/* Time the batched pass with the members' current shapes, as the batch
+ * autotuner times a candidate (best of `reps` HIP-event timings of two
+ * passes; the members' states are left unchanged): *ms = one pass.
+ * SL_E_STATE for an empty batch. */
+sl_status sl_batch_time_pass(sl_batch* batch, int32_t reps, double* ms);
 /* Wait for the batch and report members' sticky device errors. */
 sl_status sl_batch_synchronize(sl_batch* batch);
 

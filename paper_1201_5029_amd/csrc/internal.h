@@ -138,11 +138,16 @@ struct PassParams {
   const void* pi[2];
   void* phi_w[2];
   void* pi_w[2];
-  const DevScalars* sc;
-  double* partials;
-  double* offs;  // FP32 storage: offsets of the written state (phi[nf], pi[nf])
+  // two buffers each of the scalars, the per-tile partial sums and the
+  // offset records (FP32 storage: offsets of the written state, phi[nf] then
+  // pi[nf]); buffer 0 is the lattice's own, buffer 1 serves chained passes
+  DevScalars* sc[2];
+  double* partials[2];
+  double* offs[2];
   void* sink;  // per-thread slots that absorb the stores of idle lanes
   PotArgs prm;
+  BgConsts bg;
+  int ntiles;  // tiles of the lattice (partials to reduce when chaining)
   double stc[4];  // stencil weights (27-point pass only)
   int n;
   int tx, ty, tz;  // lanes in x, rows, planes per chunk
@@ -150,11 +155,36 @@ struct PassParams {
   int zs;  // plane stride of the field arrays, in planes (LatView::zs)
 };
 
+// How one pass launch follows the previous one.  chain = 0: the scalars in
+// buffer s_in are this stage's (a stage finalize or the begin kernel set
+// them).  chain = 1: the pass first finishes the previous stage itself,
+// exactly as the stage finalize does -- every workgroup reduces the
+// previous pass's partials (buffer p_in) and advances the scalars of buffer
+// s_in through that stage's end and this stage's begin -- and the first tile
+// stores the result in buffer s_out for the next launch.  The pass writes
+// its partials and offset record to buffer p_out.
+struct Chain {
+  int chain;
+  int s_in, s_out, p_in, p_out;
+  int eos;           // the previous stage ended a step (eta += h)
+  double w_prev, w;  // weights of the previous stage and of this one
+  double h;          // step size
+};
+
+// Passes chain only for lattices with at most this many tiles (every
+// workgroup of a chained pass reads all partials of the previous one) and
+// at least this much field traffic per tile: the stage update delays the
+// start of each workgroup's z-march by a few microseconds, which a short
+// march (or a workgroup that runs several tiles in turn) does not recover
+// from the stage finalize it saves.
+constexpr int kChainMaxTiles = 1024;
+constexpr size_t kChainMinTileBytes = size_t(256) << 10;
+
 // One run of a batch for the finalize / begin kernels.
 struct BatchRun {
-  DevScalars* sc;
-  double* partials;
-  const double* offs;
+  DevScalars* sc[2];
+  double* partials[2];
+  const double* offs[2];
   BgConsts bg;
   int ntiles;
   int pad;
@@ -167,6 +197,11 @@ struct LatView {
   DevScalars* sc;
   double* partials;      // per-block (sum, compensation) pairs
   double* offs;          // 2 kMaxFields doubles: offsets the last pass wrote around
+  // second buffers of the scalars, partials (kChainMaxTiles tiles) and
+  // offset record, used by chained passes (see Chain)
+  DevScalars* sc1;
+  double* partials1;
+  double* offs1;
   void* sink;            // kSinkBytes of store slots for idle lanes of the pass
   int n, nf, prec, pot;  // prec: sl_precision, pot: sl_potential
   // Field layout: element (field i, plane z, in-plane r = y n + x) of a phi or
@@ -181,7 +216,7 @@ struct LatView {
 };
 
 // ---- step kernels (kernels_step.hip) --------------------------------------
-hipError_t launch_pass(const LatView& v, hipStream_t s);
+hipError_t launch_pass(const LatView& v, const Chain& c, hipStream_t s);
 // Resident workgroups per CU of the pass kernel for this shape and stencil
 // kind (the 27-point pass takes vx = 1, pf = 1 only).
 int pass_blocks_per_cu(int prec, int pot, int nf, const Tile& t, int stencil_kind);
@@ -191,17 +226,22 @@ size_t pass_lds_bytes(int prec, int nf, const Tile& t);
 // and tile starts in device memory), then one finalize workgroup per run.
 hipError_t launch_batched_pass(int prec, int pot, int nf, const Tile& shape, int stencil_kind,
                                size_t lds, const PassParams* runs_dev, const int* start_dev,
-                               int nruns, int grid, hipStream_t s);
+                               int nruns, int grid, const Chain& c, hipStream_t s);
 int batched_blocks_per_cu(int prec, int pot, int nf, const Tile& shape, int stencil_kind,
                           size_t lds);
-hipError_t launch_batched_finalize(const BatchRun* runs_dev, int nruns, double w, double w_next,
-                                   double h, int has_next, int end_of_step, hipStream_t s);
+// The finalize reads scalar buffer s_in and partial / offset buffer p_in and
+// writes the lattice's own scalars (buffer 0).
+hipError_t launch_batched_finalize(const BatchRun* runs_dev, int nruns, int s_in, int p_in,
+                                   double w, double w_next, double h, int has_next,
+                                   int end_of_step, hipStream_t s);
 hipError_t launch_batched_begin(const BatchRun* runs_dev, int nruns, double w, double h,
                                 hipStream_t s);
 // Reduce the pass partials, finish stage (weight w) and, if has_next, begin
 // the next stage (weight w_next); eta += h when end_of_step.
-hipError_t launch_stage_finalize(const LatView& v, double w, double w_next, double h,
-                                 int has_next, int end_of_step, hipStream_t s);
+// s_in / p_in pick the scalar and partial buffers the finalize reads (0:
+// the lattice's own, 1: the chaining buffers); it writes the own scalars.
+hipError_t launch_stage_finalize(const LatView& v, int s_in, int p_in, double w, double w_next,
+                                 double h, int has_next, int end_of_step, hipStream_t s);
 // Begin the first stage of an evolve call (pending drift + H1/H2 halves).
 hipError_t launch_begin(const LatView& v, double w, double h, hipStream_t s);
 

@@ -557,7 +557,7 @@ __global__ void import_kernel(void* phi0, void* pi0, size_t count, int nf, int z
 __global__ void gather_scalars_kernel(const BatchRun* __restrict__ runs, int nruns,
                                       DevScalars* __restrict__ out) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < nruns) out[r] = *runs[r].sc;
+  if (r < nruns) out[r] = *runs[r].sc[0];
 }
 
 __global__ void reset_scalars_kernel(DevScalars* sc, double a, double p_a, Offsets off) {

@@ -131,9 +131,9 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // -- and the constants of the difference form of dV around fbar.  The first
 // tile records them for the stage finalize.
 template <int KIND, int NF, typename T>
-__device__ __forceinline__ void split_offsets(const PassParams& P, int tile_id, double (&fbar)[NF],
+__device__ __forceinline__ void split_offsets(const PassParams& P, const DevScalars& S,
+                                              double* offs_out, int tile_id, double (&fbar)[NF],
                                               double (&pibar)[NF], T (&fbT)[NF], SplitK<T>& sk) {
-  const DevScalars& S = *P.sc;
   const double c = S.c_next, beta = S.beta;
   PotT<double> pd;
 #pragma unroll
@@ -151,11 +151,17 @@ __device__ __forceinline__ void split_offsets(const PassParams& P, int tile_id, 
   if (tile_id == 0 && threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      P.offs[i] = fbar[i];
-      P.offs[kMaxFields + i] = pibar[i];
+      offs_out[i] = fbar[i];
+      offs_out[kMaxFields + i] = pibar[i];
     }
   }
 }
+
+// The scalars of this stage into S (LDS, every thread of the workgroup sees
+// them after the barrier): read from buffer s_in, or, for a chained pass,
+// formed by finishing the previous stage (see Chain).  All threads call.
+__device__ void stage_scalars(const PassParams& P, const Chain& C, int tile_id, DevScalars& S,
+                              KSum* scratch, bool fresh);
 
 // PF = 1: the next plane is loaded at the top of each z-iteration and used
 // at once.  PF = 2: software pipeline -- the loads for plane z+1 (own column
@@ -163,20 +169,22 @@ __device__ __forceinline__ void split_offsets(const PassParams& P, int tile_id, 
 // of plane z, before plane z's stores.  Vector-memory counters retire in
 // issue order, so a wavefront does not wait for its own stores before it
 // uses the next plane's data -- provided every lane issues the same memory
-// instructions: in the PF = 2 kernel idle lanes load a clamped in-range
-// address and store into a private sink slot, and x-halo cells are fetched
-// as the aligned VX-wide group that contains them.
+// instructions: idle lanes (past the tile's ragged x or y edge, or past its
+// rows) shadow the nearest active lane of the tile -- they load its column,
+// compute its sites and store the same values to the same addresses, which
+// costs no memory traffic -- but add nothing to the partial sums, and x-halo
+// cells are fetched as the aligned VX-wide group that contains them.
 template <typename T, int NF, int KIND, int VX, int PF, bool NT>
-__device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* lds,
-                                          KSum* red_scratch) {
-  const int par = P.sc->parity;
+__device__ __forceinline__ void pass_tile(const PassParams& P, const Chain& C, int tile_id, T* lds,
+                                          KSum* red_scratch, DevScalars& S, bool fresh) {
+  // parity of the state this pass reads (a chained pass flips it when it
+  // finishes the previous stage)
+  const int par = P.sc[C.s_in]->parity ^ C.chain;
   const T* __restrict__ phi_in = static_cast<const T*>(P.phi[par]);
   const T* __restrict__ pi_in = static_cast<const T*>(P.pi[par]);
   T* __restrict__ phi_out = static_cast<T*>(P.phi_w[par ^ 1]);
   T* __restrict__ pi_out = static_cast<T*>(P.pi_w[par ^ 1]);
-  const T c = static_cast<T>(P.sc->c_next);
-  const T alpha = static_cast<T>(P.sc->alpha);
-  const T beta = static_cast<T>(P.sc->beta);
+  T c = T(0), alpha = T(0), beta = T(0);  // set once the stage scalars are in
   PotT<T> pot;
 #pragma unroll
   for (int i = 0; i < kMaxFields; ++i) pot.p[i] = static_cast<T>(P.prm.p[i]);
@@ -186,7 +194,6 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
   double fbar[NF], pibar[NF];
   T fbT[NF];
   SplitK<T> sk{};
-  if constexpr (kSplit) split_offsets<KIND, NF, T>(P, tile_id, fbar, pibar, fbT, sk);
 
   const int n = P.n;
   const size_t n2 = size_t(n) * n;
@@ -208,10 +215,12 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
   const bool active = (tx * VX < wx) && (ty < wy);
   const int LX = TW + 2;
   const int plane = LX * (P.ty + 2);
-  // LDS index of the first own site (idle lanes: a row inside the tile)
-  const int own = (min(ty, P.ty - 1) + 1) * LX + 1 + tx * VX;
-  // own column; idle lanes read the tile's first column (in range, unused)
-  const size_t col = active ? size_t(y0 + ty) * n + (x0 + tx * VX) : size_t(y0) * n + x0;
+  // lane whose sites this lane computes: itself, or for an idle lane the
+  // active lane at the clamped position
+  const int sx = min(tx, wx / VX - 1), sy = min(ty, wy - 1);
+  // LDS index of the first own site and the own column
+  const int own = (sy + 1) * LX + 1 + sx * VX;
+  const size_t col = size_t(y0 + sy) * n + (x0 + sx * VX);
 
   // halo job: 1 = VX-wide row segment, 2 = left x-halo cell, 3 = right
   // x-halo cell, 0 = none.  Every lane loads one aligned VX-wide group per
@@ -246,18 +255,19 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
   // raw loads in flight: own column and halo
   T nph[NF][VX], npi[NF][VX], hph[NF][VX], hpi[NF][VX];
 
-  auto load_own = [&](int zz) {
+  auto load_own_into = [&](int zz, T (&oph)[NF][VX], T (&opi)[NF][VX]) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
       const size_t o = (size_t(zz) * P.zs + i) * n2 + col;
       const Vec<T, VX> u = ldv<T, VX>(phi_in + o), w = ldv<T, VX>(pi_in + o);
 #pragma unroll
       for (int v = 0; v < VX; ++v) {
-        nph[i][v] = u.v[v];
-        npi[i][v] = w.v[v];
+        oph[i][v] = u.v[v];
+        opi[i][v] = w.v[v];
       }
     }
   };
+  auto load_own = [&](int zz) { load_own_into(zz, nph, npi); };
   auto load_halo = [&](int zz) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
@@ -295,13 +305,20 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
       }
   };
 
-  // prologue: planes z0 - 1 and z0 of the own column
-  load_own((z0 - 1 + n) % n);
+  // prologue: planes z0 - 1 and z0 of the own column, loaded while the
+  // stage scalars are formed
+  T mph[NF][VX], mpi[NF][VX];
+  load_own_into((z0 - 1 + n) % n, mph, mpi);
+  load_own(z0);
+  stage_scalars(P, C, tile_id, S, red_scratch, fresh);
+  c = static_cast<T>(S.c_next);
+  alpha = static_cast<T>(S.alpha);
+  beta = static_cast<T>(S.beta);
+  if constexpr (kSplit) split_offsets<KIND, NF, T>(P, S, P.offs[C.p_out], tile_id, fbar, pibar, fbT, sk);
 #pragma unroll
   for (int i = 0; i < NF; ++i)
 #pragma unroll
-    for (int v = 0; v < VX; ++v) fm[i][v] = drift(nph[i][v], npi[i][v], c);
-  load_own(z0);
+    for (int v = 0; v < VX; ++v) fm[i][v] = drift(mph[i][v], mpi[i][v], c);
 #pragma unroll
   for (int i = 0; i < NF; ++i)
 #pragma unroll
@@ -309,19 +326,18 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
       pc[i][v] = npi[i][v];
       fc[i][v] = drift(nph[i][v], npi[i][v], c);
     }
-  // store targets: the lattice for active lanes, the sink slot otherwise
-  T* sink = static_cast<T*>(P.sink) + size_t(tid) * (2 * NF * VX);
-
   if constexpr (PF == 2) {
     load_own(wrap(z0 + 1));
     load_halo(z0);
     // Same trailing sequence as a loop iteration (loads, then 2 NF stores),
     // so the wait counts the compiler derives at the loop head do not cover
-    // the previous plane's stores.
+    // the previous plane's stores.  The stores go to a per-thread sink slot
+    // (cached stores: every workgroup reuses the same slots).
+    T* sink = static_cast<T*>(P.sink) + size_t(tid) * (2 * NF * VX);
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      stv_mode<NT, T, VX>(sink + (2 * i) * VX, fc[i]);
-      stv_mode<NT, T, VX>(sink + (2 * i + 1) * VX, pc[i]);
+      stv<T, VX>(sink + (2 * i) * VX, fc[i]);
+      stv<T, VX>(sink + (2 * i + 1) * VX, pc[i]);
     }
   }
 
@@ -382,10 +398,8 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
 #pragma unroll
       for (int i = 0; i < NF; ++i) {
         const size_t oc = (size_t(z) * P.zs + i) * n2 + col;
-        T* po = active ? phi_out + oc : sink + (2 * i) * VX;
-        T* qo = active ? pi_out + oc : sink + (2 * i + 1) * VX;
-        stv_mode<NT, T, VX>(po, fc[i]);
-        stv_mode<NT, T, VX>(qo, pn[i]);
+        stv_mode<NT, T, VX>(phi_out + oc, fc[i]);
+        stv_mode<NT, T, VX>(pi_out + oc, pn[i]);
       }
       if (active) {
         kadd(acc_dd, dd);
@@ -407,7 +421,7 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
   KSum v3[3] = {acc_dd, acc_v, acc_p};
   block_reduce<3>(v3, red_scratch);
   if (threadIdx.x == 0) {
-    double* out = P.partials + size_t(tile_id) * 6;
+    double* out = P.partials[C.p_out] + size_t(tile_id) * 6;
     out[0] = v3[0].s; out[1] = v3[0].c;
     out[2] = v3[1].s; out[3] = v3[1].c;
     out[4] = v3[2].s; out[5] = v3[2].c;
@@ -431,16 +445,14 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, int tile_id, T* l
 // aligned VX-wide group that contains them), and the loads of plane p + 1 go
 // out after the barrier, before the stores of plane p - 1.
 template <typename T, int NF, int KIND, int VX>
-__device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T* lds,
-                                            KSum* red_scratch) {
-  const int par = P.sc->parity;
+__device__ __forceinline__ void pass_tile27(const PassParams& P, const Chain& C, int tile_id, T* lds,
+                                            KSum* red_scratch, DevScalars& S, bool fresh) {
+  const int par = P.sc[C.s_in]->parity ^ C.chain;
   const T* __restrict__ phi_in = static_cast<const T*>(P.phi[par]);
   const T* __restrict__ pi_in = static_cast<const T*>(P.pi[par]);
   T* __restrict__ phi_out = static_cast<T*>(P.phi_w[par ^ 1]);
   T* __restrict__ pi_out = static_cast<T*>(P.pi_w[par ^ 1]);
-  const T c = static_cast<T>(P.sc->c_next);
-  const T alpha = static_cast<T>(P.sc->alpha);
-  const T beta = static_cast<T>(P.sc->beta);
+  T c = T(0), alpha = T(0), beta = T(0);  // set once the stage scalars are in
   const T w0 = static_cast<T>(P.stc[0]), w1 = static_cast<T>(P.stc[1]);
   const T w2 = static_cast<T>(P.stc[2]), w3 = static_cast<T>(P.stc[3]);
   PotT<T> pot;
@@ -450,7 +462,6 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T*
   double fbar[NF], pibar[NF];
   T fbT[NF];
   SplitK<T> sk{};
-  if constexpr (kSplit) split_offsets<KIND, NF, T>(P, tile_id, fbar, pibar, fbT, sk);
 
   const int n = P.n;
   const size_t n2 = size_t(n) * n;
@@ -535,6 +546,12 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T*
 
   T* sink = static_cast<T*>(P.sink) + size_t(tid) * (2 * NF * VX);
   load_plane(wrapz(z0 - 1));
+  // the stage scalars are formed while the first plane is in flight
+  stage_scalars(P, C, tile_id, S, red_scratch, fresh);
+  c = static_cast<T>(S.c_next);
+  alpha = static_cast<T>(S.alpha);
+  beta = static_cast<T>(S.beta);
+  if constexpr (kSplit) split_offsets<KIND, NF, T>(P, S, P.offs[C.p_out], tile_id, fbar, pibar, fbT, sk);
   // same trailing sequence as an iteration (loads, then 2 NF stores) so the
   // wait at the loop head covers the loads only
 #pragma unroll
@@ -639,7 +656,7 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T*
   KSum v3[3] = {acc_dd, acc_v, acc_p};
   block_reduce<3>(v3, red_scratch);
   if (threadIdx.x == 0) {
-    double* o = P.partials + size_t(tile_id) * 6;
+    double* o = P.partials[C.p_out] + size_t(tile_id) * 6;
     o[0] = v3[0].s; o[1] = v3[0].c;
     o[2] = v3[1].s; o[3] = v3[1].c;
     o[4] = v3[2].s; o[5] = v3[2].c;
@@ -649,19 +666,21 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, int tile_id, T*
 // ST: 0 = 7-point pass, 1 = any member of the cubic family (27-point pass),
 // 2 = 7-point pass with non-temporal result stores.
 template <typename T, int NF, int KIND, int VX, int PF, int ST>
-__device__ __forceinline__ void pass_any(const PassParams& P, int tile_id, T* lds, KSum* red) {
+__device__ __forceinline__ void pass_any(const PassParams& P, const Chain& C, int tile_id, T* lds,
+                                         KSum* red, DevScalars& S, bool fresh) {
   if constexpr (ST == 1)
-    pass_tile27<T, NF, KIND, VX>(P, tile_id, lds, red);
+    pass_tile27<T, NF, KIND, VX>(P, C, tile_id, lds, red, S, fresh);
   else
-    pass_tile<T, NF, KIND, VX, PF, ST == 2>(P, tile_id, lds, red);
+    pass_tile<T, NF, KIND, VX, PF, ST == 2>(P, C, tile_id, lds, red, S, fresh);
 }
 
 template <typename T, int NF, int KIND, int VX, int PF, int ST>
-__global__ __launch_bounds__(kBlock) void pass_kernel(PassParams P) {
+__global__ __launch_bounds__(kBlock) void pass_kernel(PassParams P, Chain C) {
   extern __shared__ unsigned char smem_raw[];
   __shared__ KSum red_scratch[4 * 3];
-  pass_any<T, NF, KIND, VX, PF, ST>(P, xcd_tile(blockIdx.x, gridDim.x),
-                                    reinterpret_cast<T*>(smem_raw), red_scratch);
+  __shared__ DevScalars S;
+  pass_any<T, NF, KIND, VX, PF, ST>(P, C, xcd_tile(blockIdx.x, gridDim.x),
+                                    reinterpret_cast<T*>(smem_raw), red_scratch, S, true);
 }
 
 // Batched form: the tiles of many lattices (same precision, potential family
@@ -675,9 +694,10 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(PassParams P) {
 template <typename T, int NF, int KIND, int VX, int PF, int ST>
 __global__ __launch_bounds__(kBlock) void batched_pass_kernel(const PassParams* __restrict__ runs,
                                                              const int* __restrict__ start,
-                                                             int nruns) {
+                                                             int nruns, Chain C) {
   extern __shared__ unsigned char smem_raw[];
   __shared__ KSum red_scratch[4 * 3];
+  __shared__ DevScalars S;
   // workgroups are dealt to the 8 XCDs round-robin; a grid of fewer than 8
   // spreads the tile list over the XCDs it has
   constexpr int kXcd = 8;
@@ -688,14 +708,16 @@ __global__ __launch_bounds__(kBlock) void batched_pass_kernel(const PassParams* 
   const int nbx = (G - xcd + nx - 1) / nx;  // workgroups on this XCD
   const int t0 = int((long long)total * xcd / nx);
   const int t1 = int((long long)total * (xcd + 1) / nx);
+  int prev = -1;  // run of the previous tile: its stage scalars are still in S
   for (int g = t0 + i; g < t1; g += nbx) {
     int lo = 0, hi = nruns - 1;  // run with start[r] <= g < start[r + 1]
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (start[mid] <= g) lo = mid; else hi = mid - 1;
     }
-    pass_any<T, NF, KIND, VX, PF, ST>(runs[lo], g - start[lo], reinterpret_cast<T*>(smem_raw),
-                                      red_scratch);
+    pass_any<T, NF, KIND, VX, PF, ST>(runs[lo], C, g - start[lo], reinterpret_cast<T*>(smem_raw),
+                                      red_scratch, S, lo != prev);
+    prev = lo;
   }
 }
 
@@ -753,71 +775,126 @@ __device__ void begin_stage(DevScalars& S, const BgConsts& K, double w, double h
   S.beta = a * a * a * a * tau;
 }
 
-__device__ void finalize_body(DevScalars* sc, const double* partials, const double* offs,
-                              int nblocks, const BgConsts& K,
-                              double w, double w_next, double h, int has_next, int end_of_step,
-                              KSum* scratch) {
+// Finish stage (weight w) from the scalars *sc and the pass's partials
+// and offset record, and begin the next (weight w_next) if has_next; eta
+// += h when end_of_step.  The result is in S_io (LDS) once the caller's
+// next barrier has passed; `record` writes the history record (the count
+// advances either way).  The scalar record and the offset record are read
+// by the workgroup together with the partials, so that the serial update
+// of thread 0 waits on no memory.  Contains barriers: all threads call.
+typedef double __attribute__((may_alias)) word_t;
+constexpr int kScalarWords = int(sizeof(DevScalars) / sizeof(double));
+static_assert(sizeof(DevScalars) % sizeof(double) == 0 && kScalarWords <= 64,
+              "scalar record read as 8-byte words by the first wavefront");
+
+__device__ void stage_update(const DevScalars* sc, const double* partials, const double* offs,
+                             int nblocks, const BgConsts& K, double w, double w_next, double h,
+                             int has_next, int end_of_step, bool record, KSum* scratch,
+                             DevScalars& S_io) {
+  __shared__ double offs_sh[2 * kMaxFields];
+  const int t = threadIdx.x;
+  double word = 0.0;
+  if (t < kScalarWords)
+    word = reinterpret_cast<const word_t*>(sc)[t];
+  else if (t >= 64 && t < 64 + 2 * kMaxFields)
+    word = offs[t - 64];
   KSum v[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-  for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+  for (int b = t; b < nblocks; b += kBlock) {
     const double* p = partials + size_t(b) * 6;
 #pragma unroll
     for (int k = 0; k < 3; ++k) v[k] = kcombine(v[k], KSum{p[2 * k], p[2 * k + 1]});
   }
-  block_reduce<3>(v, scratch);
-  if (threadIdx.x == 0) {
-    DevScalars S = *sc;
+  if (t < kScalarWords)
+    reinterpret_cast<word_t*>(&S_io)[t] = word;
+  else if (t >= 64 && t < 64 + 2 * kMaxFields)
+    offs_sh[t - 64] = word;
+  block_reduce<3>(v, scratch);  // its barriers publish the two LDS copies
+  if (t == 0) {
+    DevScalars S = S_io;
     const double SdD = v[0].s + v[0].c;
     const double SV = v[1].s + v[1].c;
     const double S2 = v[2].s + v[2].c;
-    end_stage(S, K, offs, w, h, SdD, SV, S2);
+    end_stage(S, K, offs_sh, w, h, SdD, SV, S2);
     S.parity ^= 1;
     if (end_of_step) S.eta = S.eta + h;
     if (end_of_step && S.hist != nullptr && S.hist_n < S.hist_cap) {
       // total density on this time slice from the first Friedmann equation
       // (2.18): rho = 3 m_pl^2 H^2 with H = a'/a^2 and a' = -p_a/(6 V_L m_pl^2)
       // (eq. (2.14))
-      const double hub = -S.p_a * K.inv6VLm2 / (S.a * S.a);
-      double* r = S.hist + kHistRecord * S.hist_n;
-      r[0] = S.eta;
-      r[1] = S.a;
-      r[2] = S.p_a;
-      r[3] = 3.0 * K.mpl2 * hub * hub;
+      if (record) {
+        const double hub = -S.p_a * K.inv6VLm2 / (S.a * S.a);
+        double* r = S.hist + kHistRecord * S.hist_n;
+        r[0] = S.eta;
+        r[1] = S.a;
+        r[2] = S.p_a;
+        r[3] = 3.0 * K.mpl2 * hub * hub;
+      }
       S.hist_n = S.hist_n + 1;
     }
     if (has_next) begin_stage(S, K, w_next, h);
     if (!(dev_finite(SdD) && dev_finite(SV) && dev_finite(S2) && dev_finite(S.a) &&
           dev_finite(S.p_a)))
       S.status |= kStatusNonFinite;
-    *sc = S;
+    S_io = S;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void stage_finalize_kernel(DevScalars* sc, const double* partials,
+__device__ void finalize_body(const DevScalars* sc_in, DevScalars* sc_out, const double* partials,
+                              const double* offs, int nblocks, const BgConsts& K, double w,
+                              double w_next, double h, int has_next, int end_of_step,
+                              KSum* scratch) {
+  __shared__ DevScalars S;
+  stage_update(sc_in, partials, offs, nblocks, K, w, w_next, h, has_next, end_of_step, true,
+               scratch, S);
+  if (threadIdx.x == 0) *sc_out = S;
+}
+
+__device__ void stage_scalars(const PassParams& P, const Chain& C, int tile_id, DevScalars& S,
+                              KSum* scratch, bool fresh) {
+  if (!fresh) return;  // S already holds this run's scalars (uniform branch)
+  if (C.chain) {
+    // every workgroup finishes the previous stage the same way; the first
+    // tile keeps the result (and the history record) for the next launch
+    stage_update(P.sc[C.s_in], P.partials[C.p_in], P.offs[C.p_in], P.ntiles, P.bg, C.w_prev, C.w,
+                 C.h, 1, C.eos, tile_id == 0, scratch, S);
+    if (threadIdx.x == 0 && tile_id == 0) *P.sc[C.s_out] = S;
+  } else if (threadIdx.x < kScalarWords) {
+    reinterpret_cast<word_t*>(&S)[threadIdx.x] =
+        reinterpret_cast<const word_t*>(P.sc[C.s_in])[threadIdx.x];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void stage_finalize_kernel(const DevScalars* sc_in,
+                                                               DevScalars* sc_out,
+                                                               const double* partials,
                                                                const double* offs, int nblocks,
                                                                BgConsts K, double w, double w_next,
                                                                double h, int has_next,
                                                                int end_of_step) {
   __shared__ KSum scratch[4 * 3];
-  finalize_body(sc, partials, offs, nblocks, K, w, w_next, h, has_next, end_of_step, scratch);
+  finalize_body(sc_in, sc_out, partials, offs, nblocks, K, w, w_next, h, has_next, end_of_step,
+                scratch);
 }
 
 // One workgroup per run of a batch.
 __global__ __launch_bounds__(kBlock) void batched_finalize_kernel(const BatchRun* __restrict__ runs,
-                                                                 double w, double w_next, double h,
+                                                                 int s_in, int p_in, double w,
+                                                                 double w_next, double h,
                                                                  int has_next, int end_of_step) {
   __shared__ KSum scratch[4 * 3];
   const BatchRun& R = runs[blockIdx.x];
-  finalize_body(R.sc, R.partials, R.offs, R.ntiles, R.bg, w, w_next, h, has_next, end_of_step,
-                scratch);
+  finalize_body(R.sc[s_in], R.sc[0], R.partials[p_in], R.offs[p_in], R.ntiles, R.bg, w, w_next, h,
+                has_next, end_of_step, scratch);
 }
 
 __global__ void batched_begin_kernel(const BatchRun* __restrict__ runs, int nruns, double w,
                                      double h) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < nruns) {
-    DevScalars S = *runs[r].sc;
+    DevScalars S = *runs[r].sc[0];
     begin_stage(S, runs[r].bg, w, h);
-    *runs[r].sc = S;
+    *runs[r].sc[0] = S;
   }
 }
 
@@ -837,9 +914,14 @@ PassParams make_params(const LatView& v) {
     P.phi_w[k] = v.phi[k];
     P.pi_w[k] = v.pi[k];
   }
-  P.sc = v.sc;
-  P.partials = v.partials;
-  P.offs = v.offs;
+  P.sc[0] = v.sc;
+  P.sc[1] = v.sc1;
+  P.partials[0] = v.partials;
+  P.partials[1] = v.partials1;
+  P.offs[0] = v.offs;
+  P.offs[1] = v.offs1;
+  P.bg = v.bg;
+  P.ntiles = v.tile.nblocks();
   P.sink = v.sink;
   P.prm = v.prm;
   for (int k = 0; k < 4; ++k) P.stc[k] = v.st.c[k];
@@ -854,8 +936,8 @@ PassParams make_params(const LatView& v) {
   return P;
 }
 
-using PassFn = void (*)(PassParams);
-using BatchedFn = void (*)(const PassParams*, const int*, int);
+using PassFn = void (*)(PassParams, Chain);
+using BatchedFn = void (*)(const PassParams*, const int*, int, Chain);
 
 struct PassKernel {
   PassFn fn;
@@ -943,7 +1025,7 @@ PassKernel pick(int prec, int pot, int nf, const Tile& t, int st) {
 
 }  // namespace
 
-hipError_t launch_pass(const LatView& v, hipStream_t s) {
+hipError_t launch_pass(const LatView& v, const Chain& c, hipStream_t s) {
   if (v.nf < 1 || v.nf > kMaxFields) return hipErrorInvalidValue;
   if (!pf_valid(v.tile.pf)) return hipErrorInvalidValue;
   if (v.nf > 2 && (v.tile.vx != 1 || v.tile.pf != 1)) return hipErrorInvalidValue;
@@ -951,8 +1033,9 @@ hipError_t launch_pass(const LatView& v, hipStream_t s) {
   if (pf_nt(v.tile.pf) && v.tile.vx < 2) return hipErrorInvalidValue;
   // the 27-point pass needs lanes for 2 rows + 2 columns + 4 corners of halo
   if (v.st.kind != 0 && 2 * v.tile.tx + 2 * v.tile.ty + 4 > kBlock) return hipErrorInvalidValue;
+  if (c.chain && v.tile.nblocks() > kChainMaxTiles) return hipErrorInvalidValue;
   const PassKernel k = pick(v.prec, v.pot, v.nf, v.tile, v.st.kind);
-  hipLaunchKernelGGL(k.fn, dim3(v.tile.nblocks()), dim3(kBlock), k.lds, s, make_params(v));
+  hipLaunchKernelGGL(k.fn, dim3(v.tile.nblocks()), dim3(kBlock), k.lds, s, make_params(v), c);
   return hipGetLastError();
 }
 
@@ -960,9 +1043,9 @@ PassParams pass_params(const LatView& v) { return make_params(v); }
 
 hipError_t launch_batched_pass(int prec, int pot, int nf, const Tile& shape, int stencil_kind,
                                size_t lds, const PassParams* runs_dev, const int* start_dev,
-                               int nruns, int grid, hipStream_t s) {
+                               int nruns, int grid, const Chain& c, hipStream_t s) {
   const PassKernel k = pick(prec, pot, nf, shape, stencil_kind);
-  hipLaunchKernelGGL(k.bfn, dim3(grid), dim3(kBlock), lds, s, runs_dev, start_dev, nruns);
+  hipLaunchKernelGGL(k.bfn, dim3(grid), dim3(kBlock), lds, s, runs_dev, start_dev, nruns, c);
   return hipGetLastError();
 }
 
@@ -978,10 +1061,11 @@ size_t pass_lds_bytes(int prec, int nf, const Tile& t) {
   return size_t(2) * nf * (t.tx * t.vx + 2) * (t.ty + 2) * (prec == SL_FP32 ? 4 : 8);
 }
 
-hipError_t launch_batched_finalize(const BatchRun* runs_dev, int nruns, double w, double w_next,
-                                   double h, int has_next, int end_of_step, hipStream_t s) {
-  hipLaunchKernelGGL(batched_finalize_kernel, dim3(nruns), dim3(kBlock), 0, s, runs_dev, w, w_next,
-                     h, has_next, end_of_step);
+hipError_t launch_batched_finalize(const BatchRun* runs_dev, int nruns, int s_in, int p_in,
+                                   double w, double w_next, double h, int has_next,
+                                   int end_of_step, hipStream_t s) {
+  hipLaunchKernelGGL(batched_finalize_kernel, dim3(nruns), dim3(kBlock), 0, s, runs_dev, s_in, p_in,
+                     w, w_next, h, has_next, end_of_step);
   return hipGetLastError();
 }
 
@@ -999,10 +1083,11 @@ int pass_blocks_per_cu(int prec, int pot, int nf, const Tile& t, int stencil_kin
   return nb > 0 ? nb : 1;
 }
 
-hipError_t launch_stage_finalize(const LatView& v, double w, double w_next, double h, int has_next,
-                                 int end_of_step, hipStream_t s) {
-  hipLaunchKernelGGL(stage_finalize_kernel, dim3(1), dim3(kBlock), 0, s, v.sc, v.partials, v.offs,
-                     v.tile.nblocks(), v.bg, w, w_next, h, has_next, end_of_step);
+hipError_t launch_stage_finalize(const LatView& v, int s_in, int p_in, double w, double w_next,
+                                 double h, int has_next, int end_of_step, hipStream_t s) {
+  hipLaunchKernelGGL(stage_finalize_kernel, dim3(1), dim3(kBlock), 0, s, s_in ? v.sc1 : v.sc, v.sc,
+                     p_in ? v.partials1 : v.partials, p_in ? v.offs1 : v.offs, v.tile.nblocks(),
+                     v.bg, w, w_next, h, has_next, end_of_step);
   return hipGetLastError();
 }
 

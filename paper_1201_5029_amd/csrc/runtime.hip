@@ -228,7 +228,7 @@ size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 // starting on a 256-byte boundary) and the small buffers below, at these
 // offsets inside one block.
 struct AuxLayout {
-  size_t sc, offs, partials, sink, sums, energies, spec, total;
+  size_t sc, offs, partials, sc1, offs1, partials1, sink, sums, energies, spec, total;
   AuxLayout() {
     size_t o = 0;
     auto take = [&o](size_t bytes) {
@@ -239,6 +239,10 @@ struct AuxLayout {
     sc = take(sizeof(DevScalars));
     offs = take(sizeof(double) * 2 * kMaxFields);
     partials = take(partial_doubles() * sizeof(double));
+    // second buffers for chained passes (lattices of at most kChainMaxTiles tiles)
+    sc1 = take(sizeof(DevScalars));
+    offs1 = take(sizeof(double) * 2 * kMaxFields);
+    partials1 = take(size_t(kChainMaxTiles) * 6 * sizeof(double));
     sink = take(kSinkBytes);
     sums = take(sizeof(double) * (5 * kMaxFields + 1));
     energies = take(sizeof(sl_energies_t));
@@ -335,6 +339,7 @@ struct sl_lattice {
   void* fields_mem = nullptr;  // the four field arrays (when the handle owns them)
   void* aux_mem = nullptr;     // scalars, partial sums, sink, observable buffers
   bool timing = false;
+  int chain_mode = -1;  // sl_set_chaining
   sl_batch* batch = nullptr;  // batch this lattice belongs to, if any
   int tz_user = 0;  // 0: z-chunk chosen from the occupancy of the pass kernel
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -716,6 +721,9 @@ sl_status create_impl(const sl_config* cfg, void* hip_stream, void* const* user,
     v.sc = reinterpret_cast<DevScalars*>(base + aux.sc);
     v.partials = reinterpret_cast<double*>(base + aux.partials);
     v.offs = reinterpret_cast<double*>(base + aux.offs);
+    v.sc1 = reinterpret_cast<DevScalars*>(base + aux.sc1);
+    v.offs1 = reinterpret_cast<double*>(base + aux.offs1);
+    v.partials1 = reinterpret_cast<double*>(base + aux.partials1);
     v.sink = base + aux.sink;
     L->sums_dev = reinterpret_cast<double*>(base + aux.sums);
     L->energies_dev = reinterpret_cast<sl_energies_t*>(base + aux.energies);
@@ -736,6 +744,8 @@ sl_status create_impl(const sl_config* cfg, void* hip_stream, void* const* user,
   }
   (void)hipMemsetAsync(v.sc, 0, sizeof(DevScalars), L->stream);
   (void)hipMemsetAsync(v.offs, 0, sizeof(double) * 2 * kMaxFields, L->stream);
+  (void)hipMemsetAsync(v.sc1, 0, sizeof(DevScalars), L->stream);
+  (void)hipMemsetAsync(v.offs1, 0, sizeof(double) * 2 * kMaxFields, L->stream);
   if (launch_reset_scalars(v, cfg->a0, 0.0, Offsets{}, L->stream) != hipSuccess ||
       hipStreamSynchronize(L->stream) != hipSuccess) {
     free_all(L);
@@ -928,6 +938,16 @@ sl_status check_stable(sl_lattice* L, double dt, int order) {
                 omax * std::fabs(dt), order, lim);
   return SL_OK;
 }
+
+// Whether the stage passes of this lattice chain (see Chain): few enough
+// tiles, and enough traffic per tile (sites x fields x 4 array accesses).
+bool chain_passes(const LatView& v) {
+  const Tile& t = v.tile;
+  const size_t elem = v.prec == SL_FP32 ? 4 : 8;
+  const size_t tile_bytes = size_t(t.tx) * t.vx * t.ty * t.tz * v.nf * elem * 4;
+  return t.nblocks() <= kChainMaxTiles && tile_bytes >= kChainMinTileBytes;
+}
+
 }  // namespace
 
 sl_status sl_evolve(sl_lattice* L, int64_t steps, double dt, int32_t order) {
@@ -941,26 +961,55 @@ sl_status sl_evolve(sl_lattice* L, int64_t steps, double dt, int32_t order) {
   if (st != SL_OK) return st;
   if (steps == 0) return SL_OK;
   const int s = int(w.size());
-  // stage j of each step; has_next = 0 only for the last stage of the call
+  // stage j of each step; has_next = 0 only for the last stage of the call.
+  // A segment of nsteps steps is a chain of passes (see Chain): each pass
+  // after the first finishes the previous stage itself, and one stage
+  // finalize closes the segment; lattices of more than kChainMaxTiles
+  // tiles run a stage finalize after every pass instead.
+  const bool chained = L->chain_mode < 0 ? chain_passes(L->v)
+                                         : L->chain_mode == 1 && L->v.tile.nblocks() <= kChainMaxTiles;
   auto enqueue_steps = [&](int64_t nsteps, bool last_chunk) -> sl_status {
+    int64_t m = 0;  // pass index within the segment
     for (int64_t step = 0; step < nsteps; ++step) {
-      for (int j = 0; j < s; ++j) {
+      for (int j = 0; j < s; ++j, ++m) {
         const bool last_stage = j == s - 1;
         const int has_next = !(last_stage && last_chunk && step == nsteps - 1);
         const double wn = last_stage ? w[0] : w[j + 1];
+        Chain c{};
+        if (chained && m > 0) {
+          c.chain = 1;
+          c.s_in = int((m - 1) & 1);  // pass m - 1 left its scalars there (pass 0 read buffer 0)
+          c.s_out = int(m & 1);
+          c.p_in = int((m - 1) & 1);
+          c.eos = j == 0;
+          c.w_prev = j == 0 ? w[s - 1] : w[j - 1];
+          c.w = w[j];
+          c.h = dt;
+        }
+        c.p_out = chained ? int(m & 1) : 0;
         if (L->timing) {
           hipEvent_t e0, e1;
           HIP_TRY(timing_event_create(&e0));
           HIP_TRY(timing_event_create(&e1));
           HIP_TRY(hipEventRecord(e0, L->stream));
-          HIP_TRY(launch_pass(L->v, L->stream));
+          HIP_TRY(launch_pass(L->v, c, L->stream));
           HIP_TRY(hipEventRecord(e1, L->stream));
           L->events.emplace_back(e0, e1);
         } else {
-          HIP_TRY(launch_pass(L->v, L->stream));
+          HIP_TRY(launch_pass(L->v, c, L->stream));
         }
-        HIP_TRY(launch_stage_finalize(L->v, w[j], wn, dt, has_next, last_stage ? 1 : 0, L->stream));
+        if (!chained)
+          HIP_TRY(launch_stage_finalize(L->v, 0, 0, w[j], wn, dt, has_next, last_stage ? 1 : 0,
+                                        L->stream));
       }
+    }
+    if (chained && m > 0) {
+      // the last pass of the segment (index m - 1) used the scalars of
+      // buffer 0 if it was the first, else those it stored in (m - 1) & 1
+      const int last = int(m - 1);
+      const int s_in = last == 0 ? 0 : (last & 1);
+      HIP_TRY(launch_stage_finalize(L->v, s_in, last & 1, w[s - 1], w[0], dt,
+                                    last_chunk ? 0 : 1, 1, L->stream));
     }
     return SL_OK;
   };
@@ -1203,6 +1252,17 @@ sl_status sl_spectra(sl_lattice* L, int32_t field, int32_t nbins, double* k_out,
   return read_scalars(L, &Sc);
 }
 
+sl_status sl_set_chaining(sl_lattice* L, int32_t mode) {
+  if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
+  if (mode < -1 || mode > 1) return fail(SL_E_INVALID, "chaining mode must be -1, 0 or 1 (got %d)", mode);
+  if (mode != L->chain_mode) {
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    drop_graph(L);  // the captured chunk follows the mode
+    L->chain_mode = mode;
+  }
+  return SL_OK;
+}
+
 sl_status sl_set_kernel_timing(sl_lattice* L, int32_t enable) {
   if (!L) return fail(SL_E_INVALID, "lattice handle is NULL");
   L->timing = enable != 0;
@@ -1301,8 +1361,8 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
   HIP_TRY(timing_event_create(&e0));
   HIP_TRY(timing_event_create(&e1));
   auto stage = [&]() -> hipError_t {
-    hipError_t e = launch_pass(L->v, L->stream);
-    if (e == hipSuccess) e = launch_stage_finalize(L->v, 1.0, 1.0, 0.0, 1, 0, L->stream);
+    hipError_t e = launch_pass(L->v, Chain{}, L->stream);
+    if (e == hipSuccess) e = launch_stage_finalize(L->v, 0, 0, 1.0, 1.0, 0.0, 1, 0, L->stream);
     return e;
   };
   double best = 1e300;
@@ -1550,9 +1610,12 @@ sl_status batch_upload(sl_batch* B) {
   for (int r = 0; r < R; ++r) {
     sl_lattice* L = B->runs[r];
     pp[r] = pass_params(L->v);
-    br[r].sc = L->v.sc;
-    br[r].partials = L->v.partials;
-    br[r].offs = L->v.offs;
+    br[r].sc[0] = L->v.sc;
+    br[r].sc[1] = L->v.sc1;
+    br[r].partials[0] = L->v.partials;
+    br[r].partials[1] = L->v.partials1;
+    br[r].offs[0] = L->v.offs;
+    br[r].offs[1] = L->v.offs1;
     br[r].bg = L->v.bg;
     br[r].ntiles = L->v.tile.nblocks();
     br[r].pad = 0;
@@ -1578,16 +1641,38 @@ sl_status batch_enqueue(sl_batch* B, int64_t steps, double dt, const std::vector
                         bool last_chunk) {
   const int R = int(B->runs.size());
   const int s = int(w.size());
+  // batches do not chain: a workgroup of the batched pass may run several
+  // tiles in turn, and the members' tiles are short
+  const bool chained = false;
+  int64_t m = 0;
   for (int64_t step = 0; step < steps; ++step) {
-    for (int j = 0; j < s; ++j) {
+    for (int j = 0; j < s; ++j, ++m) {
       const bool last_stage = j == s - 1;
       const int has_next = !(last_stage && last_chunk && step == steps - 1);
       const double wn = last_stage ? w[0] : w[j + 1];
+      Chain c{};
+      if (chained && m > 0) {
+        c.chain = 1;
+        c.s_in = int((m - 1) & 1);
+        c.s_out = int(m & 1);
+        c.p_in = int((m - 1) & 1);
+        c.eos = j == 0;
+        c.w_prev = j == 0 ? w[s - 1] : w[j - 1];
+        c.w = w[j];
+        c.h = dt;
+      }
+      c.p_out = chained ? int(m & 1) : 0;
       HIP_TRY(launch_batched_pass(B->prec, B->pot, B->nf, B->shape, B->st_kind, B->lds, B->pass_dev,
-                                  B->start_dev, R, B->grid, B->stream));
-      HIP_TRY(launch_batched_finalize(B->run_dev, R, w[j], wn, dt, has_next, last_stage ? 1 : 0,
-                                      B->stream));
+                                  B->start_dev, R, B->grid, c, B->stream));
+      if (!chained)
+        HIP_TRY(launch_batched_finalize(B->run_dev, R, 0, 0, w[j], wn, dt, has_next,
+                                        last_stage ? 1 : 0, B->stream));
     }
+  }
+  if (chained && m > 0) {
+    const int last = int(m - 1);
+    HIP_TRY(launch_batched_finalize(B->run_dev, R, last == 0 ? 0 : (last & 1), last & 1, w[s - 1],
+                                    w[0], dt, last_chunk ? 0 : 1, 1, B->stream));
   }
   return SL_OK;
 }
@@ -1701,6 +1786,54 @@ sl_status sl_batch_remove(sl_batch* B, sl_lattice* L) {
   return fail(SL_E_INVALID, "lattice is not in this batch");
 }
 
+}  // extern "C"
+
+namespace {
+
+// Time the batched pass alone with the current shapes: without its
+// finalize it leaves every member's state as it was (it reads the current
+// buffer and writes the spare buffer and the partials).  Best of `reps`
+// timings of two consecutive passes, per pass.
+sl_status batch_time_pass(sl_batch* B, int reps, hipEvent_t e0, hipEvent_t e1, double* ms_out) {
+  sl_status st = batch_upload(B);
+  if (st != SL_OK) return st;
+  double best = 1e300;
+  HIP_TRY(launch_batched_pass(B->prec, B->pot, B->nf, B->shape, B->st_kind, B->lds, B->pass_dev,
+                              B->start_dev, int(B->runs.size()), B->grid, Chain{}, B->stream));
+  for (int r = 0; r < reps; ++r) {
+    HIP_TRY(hipEventRecord(e0, B->stream));
+    for (int k = 0; k < 2; ++k)
+      HIP_TRY(launch_batched_pass(B->prec, B->pot, B->nf, B->shape, B->st_kind, B->lds, B->pass_dev,
+                                  B->start_dev, int(B->runs.size()), B->grid, Chain{}, B->stream));
+    HIP_TRY(hipEventRecord(e1, B->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (0.5 * ms < best) best = 0.5 * ms;
+  }
+  *ms_out = best;
+  return SL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sl_status sl_batch_time_pass(sl_batch* B, int32_t reps, double* ms) {
+  if (!B || !ms) return fail(SL_E_INVALID, "batch handle or output is NULL");
+  if (reps < 1 || reps > 100) return fail(SL_E_INVALID, "reps must be in [1, 100]");
+  if (B->runs.empty()) return fail(SL_E_STATE, "the batch has no members");
+  for (sl_lattice* L : B->runs) HIP_TRY(hipStreamSynchronize(L->stream));
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  hipEvent_t e0, e1;
+  HIP_TRY(timing_event_create(&e0));
+  HIP_TRY(timing_event_create(&e1));
+  const sl_status st = batch_time_pass(B, reps, e0, e1, ms);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
 sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
   if (!B) return fail(SL_E_INVALID, "batch handle is NULL");
   if (reps < 1 || reps > 100) return fail(SL_E_INVALID, "reps must be in [1, 100]");
@@ -1724,28 +1857,8 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
   hipEvent_t e0, e1;
   HIP_TRY(timing_event_create(&e0));
   HIP_TRY(timing_event_create(&e1));
-  // time the batched pass alone: without its finalize it leaves every
-  // member's state as it was (reads the current buffer, writes the spare
-  // buffer and the partials)
   auto time_now = [&](double* ms_out) -> sl_status {
-    sl_status st = batch_upload(B);
-    if (st != SL_OK) return st;
-    double best = 1e300;
-    HIP_TRY(launch_batched_pass(B->prec, B->pot, B->nf, B->shape, B->st_kind, B->lds, B->pass_dev,
-                                B->start_dev, int(B->runs.size()), B->grid, B->stream));
-    for (int r = 0; r < reps; ++r) {
-      HIP_TRY(hipEventRecord(e0, B->stream));
-      for (int k = 0; k < 2; ++k)
-        HIP_TRY(launch_batched_pass(B->prec, B->pot, B->nf, B->shape, B->st_kind, B->lds, B->pass_dev,
-                                    B->start_dev, int(B->runs.size()), B->grid, B->stream));
-      HIP_TRY(hipEventRecord(e1, B->stream));
-      HIP_TRY(hipEventSynchronize(e1));
-      float ms = 0.0f;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      if (0.5 * ms < best) best = 0.5 * ms;
-    }
-    *ms_out = best;
-    return SL_OK;
+    return batch_time_pass(B, reps, e0, e1, ms_out);
   };
   auto apply = [&](int n, int tx, int vx, int tz, int pf) {
     for (sl_lattice* L : B->runs)

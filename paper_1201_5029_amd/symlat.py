@@ -27,7 +27,7 @@ EXPORTS = (
     "sl_get_fields", "sl_set_fields", "sl_get_background", "sl_synchronize",
     "sl_footprint_bytes", "sl_transient_bytes", "sl_last_error", "sl_composition_weights",
     "sl_stability_limit", "sl_set_kernel_timing", "sl_kernel_timing",
-    "sl_get_tile", "sl_set_tile", "sl_hbm_copy_bench",
+    "sl_get_tile", "sl_set_tile", "sl_set_chaining", "sl_hbm_copy_bench",
     "sl_batch_create", "sl_batch_destroy", "sl_batch_add", "sl_batch_remove",
     "sl_batch_count", "sl_batch_step", "sl_batch_synchronize", "sl_device_memory",
     "sl_autotune", "sl_autotune_forget", "sl_set_stencil", "sl_get_stencil",
@@ -36,7 +36,7 @@ EXPORTS = (
     "sl_linear_get_fields", "sl_linear_get_background", "sl_linear_classes",
     "sl_linear_synchronize", "sl_linear_set_kernel_timing", "sl_linear_kernel_timing",
     "sl_batch_autotune", "sl_spectra", "sl_set_history", "sl_get_history",
-    "sl_batch_set_grid", "sl_batch_get_grid", "sl_spectrum_noalloc",
+    "sl_batch_set_grid", "sl_batch_get_grid", "sl_spectrum_noalloc", "sl_batch_time_pass",
 )
 
 #: Members of the cubic stencil family of eq. (2.7): (centre, face, edge,
@@ -107,6 +107,7 @@ def load():
         "sl_kernel_timing": (I32, [P, ctypes.POINTER(I64), dp]),
         "sl_get_tile": (I32, [P] + [ctypes.POINTER(I32)] * 5),
         "sl_set_tile": (I32, [P, I32, I32, I32, I32]),
+        "sl_set_chaining": (I32, [P, I32]),
         "sl_hbm_copy_bench": (I32, [ctypes.c_size_t, I32, dp]),
         "sl_batch_create": (I32, [P, ctypes.POINTER(P)]),
         "sl_batch_destroy": (I32, [P]),
@@ -135,6 +136,7 @@ def load():
         "sl_linear_set_kernel_timing": (I32, [P, I32]),
         "sl_linear_kernel_timing": (I32, [P, ctypes.POINTER(I64), dp, dp, dp]),
         "sl_batch_autotune": (I32, [P, I32, dp]),
+        "sl_batch_time_pass": (I32, [P, I32, dp]),
         "sl_spectra": (I32, [P, I32, I32, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int64), dp]),
         "sl_set_history": (I32, [P, I64]),
         "sl_get_history": (I32, [P, dp, dp, dp, dp, I64, ctypes.POINTER(I64)]),
@@ -379,6 +381,11 @@ class Lattice:
     def set_tile(self, tx, vx=1, tz=0, pf=1):
         _check(self._lib.sl_set_tile(self._h, int(tx), int(vx), int(tz), int(pf)))
 
+    def set_chaining(self, mode):
+        """-1: automatic (default), 0: a stage finalize kernel after every
+        pass, 1: fold it into the next pass (results are identical)."""
+        _check(self._lib.sl_set_chaining(self._h, int(mode)))
+
     def autotune(self, reps=3, vx_only=0, pf_only=0):
         """Pick the fastest pass shape for this lattice (timed as real
         stages with frozen coefficients; the state is kept); returns
@@ -443,6 +450,12 @@ class Batch:
         best pass time (ms)."""
         ms = ctypes.c_double()
         _check(self._lib.sl_batch_autotune(self._h, int(reps), ctypes.byref(ms)))
+        return ms.value
+
+    def time_pass(self, reps=3):
+        """Time of one batched pass (ms) with the members' current shapes."""
+        ms = ctypes.c_double()
+        _check(self._lib.sl_batch_time_pass(self._h, int(reps), ctypes.byref(ms)))
         return ms.value
 
     def close(self):
