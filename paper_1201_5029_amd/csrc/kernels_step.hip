@@ -160,8 +160,19 @@ __device__ __forceinline__ void split_offsets(const PassParams& P, const DevScal
 // The scalars of this stage into S (LDS, every thread of the workgroup sees
 // them after the barrier): read from buffer s_in, or, for a chained pass,
 // formed by finishing the previous stage (see Chain).  All threads call.
+// A chained pass reads the previous stage's records (scalar words, offset
+// record, this thread's share of the per-tile partials) at the very start,
+// before the loads that depend on the state's parity, so that they are
+// first in the memory queue and the stage update overlaps the prologue's
+// plane loads.  Up to kChainMaxTiles = 4 x 256 tiles.
+struct ChainPre {
+  double word;
+  double p[4][6];
+};
+__device__ void chain_prefetch(const PassParams& P, const Chain& C, ChainPre& cp);
+template <bool CH>
 __device__ void stage_scalars(const PassParams& P, const Chain& C, int tile_id, DevScalars& S,
-                              KSum* scratch, bool fresh);
+                              KSum* scratch, bool fresh, const ChainPre& cp);
 
 // PF = 1: the next plane is loaded at the top of each z-iteration and used
 // at once.  PF = 2: software pipeline -- the loads for plane z+1 (own column
@@ -174,9 +185,12 @@ __device__ void stage_scalars(const PassParams& P, const Chain& C, int tile_id, 
 // compute its sites and store the same values to the same addresses, which
 // costs no memory traffic -- but add nothing to the partial sums, and x-halo
 // cells are fetched as the aligned VX-wide group that contains them.
-template <typename T, int NF, int KIND, int VX, int PF, bool NT>
+template <typename T, int NF, int KIND, int VX, int PF, bool NT, bool CH>
 __device__ __forceinline__ void pass_tile(const PassParams& P, const Chain& C, int tile_id, T* lds,
                                           KSum* red_scratch, DevScalars& S, bool fresh) {
+  ChainPre cp;
+  if constexpr (CH)
+    if (C.chain && fresh) chain_prefetch(P, C, cp);
   // parity of the state this pass reads (a chained pass flips it when it
   // finishes the previous stage)
   const int par = P.sc[C.s_in]->parity ^ C.chain;
@@ -310,7 +324,7 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, const Chain& C, i
   T mph[NF][VX], mpi[NF][VX];
   load_own_into((z0 - 1 + n) % n, mph, mpi);
   load_own(z0);
-  stage_scalars(P, C, tile_id, S, red_scratch, fresh);
+  stage_scalars<CH>(P, C, tile_id, S, red_scratch, fresh, cp);
   c = static_cast<T>(S.c_next);
   alpha = static_cast<T>(S.alpha);
   beta = static_cast<T>(S.beta);
@@ -444,9 +458,12 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, const Chain& C, i
 // column and store into the sink; x-halo and corner cells are fetched as the
 // aligned VX-wide group that contains them), and the loads of plane p + 1 go
 // out after the barrier, before the stores of plane p - 1.
-template <typename T, int NF, int KIND, int VX>
+template <typename T, int NF, int KIND, int VX, bool CH>
 __device__ __forceinline__ void pass_tile27(const PassParams& P, const Chain& C, int tile_id, T* lds,
                                             KSum* red_scratch, DevScalars& S, bool fresh) {
+  ChainPre cp;
+  if constexpr (CH)
+    if (C.chain && fresh) chain_prefetch(P, C, cp);
   const int par = P.sc[C.s_in]->parity ^ C.chain;
   const T* __restrict__ phi_in = static_cast<const T*>(P.phi[par]);
   const T* __restrict__ pi_in = static_cast<const T*>(P.pi[par]);
@@ -547,7 +564,7 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, const Chain& C,
   T* sink = static_cast<T*>(P.sink) + size_t(tid) * (2 * NF * VX);
   load_plane(wrapz(z0 - 1));
   // the stage scalars are formed while the first plane is in flight
-  stage_scalars(P, C, tile_id, S, red_scratch, fresh);
+  stage_scalars<CH>(P, C, tile_id, S, red_scratch, fresh, cp);
   c = static_cast<T>(S.c_next);
   alpha = static_cast<T>(S.alpha);
   beta = static_cast<T>(S.beta);
@@ -665,13 +682,14 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, const Chain& C,
 
 // ST: 0 = 7-point pass, 1 = any member of the cubic family (27-point pass),
 // 2 = 7-point pass with non-temporal result stores.
-template <typename T, int NF, int KIND, int VX, int PF, int ST>
+// CH: the kernel can run chained (the solo pass; batches never chain).
+template <typename T, int NF, int KIND, int VX, int PF, int ST, bool CH>
 __device__ __forceinline__ void pass_any(const PassParams& P, const Chain& C, int tile_id, T* lds,
                                          KSum* red, DevScalars& S, bool fresh) {
   if constexpr (ST == 1)
-    pass_tile27<T, NF, KIND, VX>(P, C, tile_id, lds, red, S, fresh);
+    pass_tile27<T, NF, KIND, VX, CH>(P, C, tile_id, lds, red, S, fresh);
   else
-    pass_tile<T, NF, KIND, VX, PF, ST == 2>(P, C, tile_id, lds, red, S, fresh);
+    pass_tile<T, NF, KIND, VX, PF, ST == 2, CH>(P, C, tile_id, lds, red, S, fresh);
 }
 
 template <typename T, int NF, int KIND, int VX, int PF, int ST>
@@ -679,7 +697,7 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(PassParams P, Chain C) {
   extern __shared__ unsigned char smem_raw[];
   __shared__ KSum red_scratch[4 * 3];
   __shared__ DevScalars S;
-  pass_any<T, NF, KIND, VX, PF, ST>(P, C, xcd_tile(blockIdx.x, gridDim.x),
+  pass_any<T, NF, KIND, VX, PF, ST, true>(P, C, xcd_tile(blockIdx.x, gridDim.x),
                                     reinterpret_cast<T*>(smem_raw), red_scratch, S, true);
 }
 
@@ -715,7 +733,8 @@ __global__ __launch_bounds__(kBlock) void batched_pass_kernel(const PassParams* 
       const int mid = (lo + hi + 1) >> 1;
       if (start[mid] <= g) lo = mid; else hi = mid - 1;
     }
-    pass_any<T, NF, KIND, VX, PF, ST>(runs[lo], C, g - start[lo], reinterpret_cast<T*>(smem_raw),
+    pass_any<T, NF, KIND, VX, PF, ST, false>(runs[lo], C, g - start[lo],
+                                             reinterpret_cast<T*>(smem_raw),
                                       red_scratch, S, lo != prev);
     prev = lo;
   }
@@ -775,35 +794,20 @@ __device__ void begin_stage(DevScalars& S, const BgConsts& K, double w, double h
   S.beta = a * a * a * a * tau;
 }
 
-// Finish stage (weight w) from the scalars *sc and the pass's partials
-// and offset record, and begin the next (weight w_next) if has_next; eta
-// += h when end_of_step.  The result is in S_io (LDS) once the caller's
-// next barrier has passed; `record` writes the history record (the count
-// advances either way).  The scalar record and the offset record are read
-// by the workgroup together with the partials, so that the serial update
-// of thread 0 waits on no memory.  Contains barriers: all threads call.
+// The scalar record is moved as 8-byte words, one per thread.
 typedef double __attribute__((may_alias)) word_t;
 constexpr int kScalarWords = int(sizeof(DevScalars) / sizeof(double));
 static_assert(sizeof(DevScalars) % sizeof(double) == 0 && kScalarWords <= 64,
               "scalar record read as 8-byte words by the first wavefront");
 
-__device__ void stage_update(const DevScalars* sc, const double* partials, const double* offs,
-                             int nblocks, const BgConsts& K, double w, double w_next, double h,
-                             int has_next, int end_of_step, bool record, KSum* scratch,
-                             DevScalars& S_io) {
+// Second half of a stage update: publish this thread's scalar/offset word
+// in LDS, reduce the partial sums over the workgroup, and let thread 0
+// finish the stage.
+__device__ void stage_update_finish(double word, KSum (&v)[3], const BgConsts& K, double w,
+                                    double w_next, double h, int has_next, int end_of_step,
+                                    bool record, KSum* scratch, DevScalars& S_io) {
   __shared__ double offs_sh[2 * kMaxFields];
   const int t = threadIdx.x;
-  double word = 0.0;
-  if (t < kScalarWords)
-    word = reinterpret_cast<const word_t*>(sc)[t];
-  else if (t >= 64 && t < 64 + 2 * kMaxFields)
-    word = offs[t - 64];
-  KSum v[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-  for (int b = t; b < nblocks; b += kBlock) {
-    const double* p = partials + size_t(b) * 6;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) v[k] = kcombine(v[k], KSum{p[2 * k], p[2 * k + 1]});
-  }
   if (t < kScalarWords)
     reinterpret_cast<word_t*>(&S_io)[t] = word;
   else if (t >= 64 && t < 64 + 2 * kMaxFields)
@@ -839,6 +843,36 @@ __device__ void stage_update(const DevScalars* sc, const double* partials, const
   }
 }
 
+// The word of the scalar record (threads 0 .. kScalarWords-1) or of the
+// offset record (threads 64 .. 64 + 2 kMaxFields - 1) this thread publishes.
+__device__ __forceinline__ double record_word(const DevScalars* sc, const double* offs) {
+  const int t = threadIdx.x;
+  if (t < kScalarWords) return reinterpret_cast<const word_t*>(sc)[t];
+  if (t >= 64 && t < 64 + 2 * kMaxFields) return offs[t - 64];
+  return 0.0;
+}
+
+// Finish stage (weight w) from the scalars *sc and the pass's partials
+// and offset record, and begin the next (weight w_next) if has_next; eta
+// += h when end_of_step.  The result is in S_io (LDS) once the caller's
+// next barrier has passed; `record` writes the history record (the count
+// advances either way).  The scalar record and the offset record are read
+// by the workgroup together with the partials, so that the serial update
+// of thread 0 waits on no memory.  Contains barriers: all threads call.
+__device__ void stage_update(const DevScalars* sc, const double* partials, const double* offs,
+                             int nblocks, const BgConsts& K, double w, double w_next, double h,
+                             int has_next, int end_of_step, bool record, KSum* scratch,
+                             DevScalars& S_io) {
+  const double word = record_word(sc, offs);
+  KSum v[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+    const double* p = partials + size_t(b) * 6;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = kcombine(v[k], KSum{p[2 * k], p[2 * k + 1]});
+  }
+  stage_update_finish(word, v, K, w, w_next, h, has_next, end_of_step, record, scratch, S_io);
+}
+
 __device__ void finalize_body(const DevScalars* sc_in, DevScalars* sc_out, const double* partials,
                               const double* offs, int nblocks, const BgConsts& K, double w,
                               double w_next, double h, int has_next, int end_of_step,
@@ -849,14 +883,39 @@ __device__ void finalize_body(const DevScalars* sc_in, DevScalars* sc_out, const
   if (threadIdx.x == 0) *sc_out = S;
 }
 
+static_assert(kChainMaxTiles <= 4 * kBlock, "ChainPre holds four tiles per thread");
+
+__device__ void chain_prefetch(const PassParams& P, const Chain& C, ChainPre& cp) {
+  const int t = threadIdx.x;
+  cp.word = record_word(P.sc[C.s_in], P.offs[C.p_in]);
+  const double* partials = P.partials[C.p_in];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int b = t + k * kBlock;
+    if (b < P.ntiles) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) cp.p[k][j] = partials[size_t(b) * 6 + j];
+    }
+  }
+}
+
+template <bool CH>
 __device__ void stage_scalars(const PassParams& P, const Chain& C, int tile_id, DevScalars& S,
-                              KSum* scratch, bool fresh) {
+                              KSum* scratch, bool fresh, const ChainPre& cp) {
   if (!fresh) return;  // S already holds this run's scalars (uniform branch)
-  if (C.chain) {
-    // every workgroup finishes the previous stage the same way; the first
-    // tile keeps the result (and the history record) for the next launch
-    stage_update(P.sc[C.s_in], P.partials[C.p_in], P.offs[C.p_in], P.ntiles, P.bg, C.w_prev, C.w,
-                 C.h, 1, C.eos, tile_id == 0, scratch, S);
+  if (CH && C.chain) {
+    // every workgroup finishes the previous stage the same way (the same
+    // partials combined in the same order as stage_update); the first tile
+    // keeps the result (and the history record) for the next launch
+    KSum v[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (int(threadIdx.x) + k * kBlock < P.ntiles) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) v[q] = kcombine(v[q], KSum{cp.p[k][2 * q], cp.p[k][2 * q + 1]});
+      }
+    }
+    stage_update_finish(cp.word, v, P.bg, C.w_prev, C.w, C.h, 1, C.eos, tile_id == 0, scratch, S);
     if (threadIdx.x == 0 && tile_id == 0) *P.sc[C.s_out] = S;
   } else if (threadIdx.x < kScalarWords) {
     reinterpret_cast<word_t*>(&S)[threadIdx.x] =

@@ -1639,40 +1639,20 @@ sl_status batch_upload(sl_batch* B) {
 // call's last chunk, whose drift then stays pending.
 sl_status batch_enqueue(sl_batch* B, int64_t steps, double dt, const std::vector<double>& w,
                         bool last_chunk) {
+  // batches do not chain (see Chain): a workgroup of the batched pass may
+  // run several tiles in turn, and the members' tiles are short
   const int R = int(B->runs.size());
   const int s = int(w.size());
-  // batches do not chain: a workgroup of the batched pass may run several
-  // tiles in turn, and the members' tiles are short
-  const bool chained = false;
-  int64_t m = 0;
   for (int64_t step = 0; step < steps; ++step) {
-    for (int j = 0; j < s; ++j, ++m) {
+    for (int j = 0; j < s; ++j) {
       const bool last_stage = j == s - 1;
       const int has_next = !(last_stage && last_chunk && step == steps - 1);
       const double wn = last_stage ? w[0] : w[j + 1];
-      Chain c{};
-      if (chained && m > 0) {
-        c.chain = 1;
-        c.s_in = int((m - 1) & 1);
-        c.s_out = int(m & 1);
-        c.p_in = int((m - 1) & 1);
-        c.eos = j == 0;
-        c.w_prev = j == 0 ? w[s - 1] : w[j - 1];
-        c.w = w[j];
-        c.h = dt;
-      }
-      c.p_out = chained ? int(m & 1) : 0;
       HIP_TRY(launch_batched_pass(B->prec, B->pot, B->nf, B->shape, B->st_kind, B->lds, B->pass_dev,
-                                  B->start_dev, R, B->grid, c, B->stream));
-      if (!chained)
-        HIP_TRY(launch_batched_finalize(B->run_dev, R, 0, 0, w[j], wn, dt, has_next,
-                                        last_stage ? 1 : 0, B->stream));
+                                  B->start_dev, R, B->grid, Chain{}, B->stream));
+      HIP_TRY(launch_batched_finalize(B->run_dev, R, 0, 0, w[j], wn, dt, has_next,
+                                      last_stage ? 1 : 0, B->stream));
     }
-  }
-  if (chained && m > 0) {
-    const int last = int(m - 1);
-    HIP_TRY(launch_batched_finalize(B->run_dev, R, last == 0 ? 0 : (last & 1), last & 1, w[s - 1],
-                                    w[0], dt, last_chunk ? 0 : 1, 1, B->stream));
   }
   return SL_OK;
 }
