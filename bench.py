@@ -90,23 +90,29 @@ def kernel_source_hash():
     return m.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision, tile):
+def measured_traffic(workload, precision, shape):
     """Calibrated FETCH_SIZE + WRITE_SIZE bytes per pass recorded under
-    profiles/ for this workload, precision and pass shape, or None when no
-    record matches or the kernel sources changed since it was taken."""
+    profiles/ for this workload, precision and pass shape ('tx,vx,tz,pf',
+    or 'n:tx,vx,tz,pf;...' for a batch), or None when no record matches or
+    the kernel sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "pass_kernel_traffic.txt")
     if not os.path.exists(path):
         return None
     h = kernel_source_hash()
-    tx, vx, _, tz, pf = tile
     for line in open(path):
         if line.startswith("#") or not line.strip():
             continue
         f = line.split()
-        if (f[0] == workload and f[1] == precision and [int(x) for x in f[2:6]] == [tx, vx, tz, pf]
-                and f[6] == h):
-            return int(f[7])
+        if f[0] == workload and f[1] == precision and f[2] == shape and f[3] == h:
+            return int(f[4])
     return None
+
+
+def traffic_fields(workload, precision, shape, algorithmic):
+    """'traffic' (bytes per pass, or None) and its ratio to the algorithmic
+    bytes, for a bench line."""
+    t = measured_traffic(workload, precision, shape)
+    return {"traffic": t, "traffic_ratio": None if t is None else t / algorithmic}
 
 
 def _rel_l2(a, b):
@@ -307,6 +313,9 @@ def measure_batched(sl, nruns=96, steps=100):
             "pass_ms": pass_ms, "pass_achieved_GBs": bytes_pass / (pass_ms * 1e-3) / 1e9,
             "pass_frac": bytes_pass / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "bytes_per_pass": bytes_pass, "shapes_n_tx_vx_ty_tz_pf": shapes,
+            **traffic_fields("deltaN96_order4", "f32",
+                             ";".join("%d:%d,%d,%d,%d" % (q[0], q[1], q[2], q[4], q[5])
+                                      for q in shapes), bytes_pass),
             "error_vs_fp64": dict(err, steps=10 + steps,
                                   against="one member of each size advanced alone in FP64"),
             "workgroups": {"launched": grid[1],
@@ -327,6 +336,7 @@ def measure_stencil27(sl, steps=50, warmup=5):
             "value": n3 * 2 * steps / wall, "ms_per_step": wall / steps * 1e3,
             "pass_ms": avg * 1e3, "achieved_GBs": 4 * 8 * 2 * n3 / avg / 1e9,
             "frac": 4 * 8 * 2 * n3 / avg / 1e9 / HBM_PEAK_GBS, "tile": list(tile),
+            **traffic_fields("preheat256_order6_st27", "f64", tile_str(tile), 4 * 8 * 2 * n3),
             "friedmann_residual": e["friedmann_residual"]}
 
 
@@ -381,7 +391,17 @@ def measure_linear(sl, n=256, steps=400, order=6, warmup=20):
 PAPER_256_ORDER4 = {"Tesla C2050": 2 * 256 ** 3 / 0.132, "GTX 470": 2 * 256 ** 3 / 0.152}
 
 
-def measure_config(sl, recipe, steps, key, warmup=10):
+def footprint_copy(sl, state, avg_pass_s):
+    """For a lattice whose state fits the 256 MB MALL: the rate of a plain
+    copy of the same footprint (state/2 bytes read and written, repeated, so
+    it stays MALL-resident) -- the ceiling the pass is measured against."""
+    if state > 256e6:
+        return {}
+    gbs = sl.symlat.hbm_copy_bench(state // 2, 50)
+    return {"copy_same_footprint_GBs": gbs, "frac_of_footprint_copy": state / avg_pass_s / 1e9 / gbs}
+
+
+def measure_config(sl, recipe, steps, key, workload, warmup=10):
     """One more workload on the single-lattice path: field-site-updates/s
     and the pass's HBM roofline (for lattices that fit the 256 MB MALL the
     bandwidth is effective, not HBM-only)."""
@@ -396,6 +416,8 @@ def measure_config(sl, recipe, steps, key, warmup=10):
             "ms_per_step": wall / steps * 1e3, "pass_ms": avg * 1e3,
             "achieved_GBs": state / avg / 1e9, "frac": state / avg / 1e9 / HBM_PEAK_GBS,
             "state_fits_mall": state <= 256e6, "tile": list(tile),
+            **traffic_fields(workload, recipe["precision"], tile_str(tile), state),
+            **footprint_copy(sl, state, avg),
             "friedmann_residual": e["friedmann_residual"]}
 
 
@@ -458,6 +480,7 @@ def measure_qball512(sl, steps=20, warmup=3):
             "value": n3 * 2 * steps / wall, "ms_per_step": wall / steps * 1e3,
             "pass_ms": avg * 1e3, "achieved_GBs": 4 * 4 * 2 * n3 / avg / 1e9,
             "frac": 4 * 4 * 2 * n3 / avg / 1e9 / HBM_PEAK_GBS, "tile": list(tile),
+            **traffic_fields("qball512_order6", "f32", tile_str(tile), 4 * 4 * 2 * n3),
             "friedmann_residual": e["friedmann_residual"]}
 
 
@@ -610,7 +633,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("preheat%d_order%d" % (args.n, args.order),
-                                                 args.precision, tile),
+                                                 args.precision, tile_str(tile)),
                      "kernel": "pass_kernel", "avg_launch_ms": avg_pass_s * 1e3,
                      "bytes_per_launch": bytes_per_pass},
         "friedmann_residual": e["friedmann_residual"],
@@ -640,6 +663,9 @@ def main():
         out["fp32_storage"] = {"error_vs_fp64": err,
             "value": n3 * nf * args.steps / w32, "ms_per_step": w32 / args.steps * 1e3,
             "pass_ms": ms32 / p32, "achieved_GBs": 4 * 4 * nf * n3 / (ms32 / p32 / 1e3) / 1e9,
+            "frac": 4 * 4 * nf * n3 / (ms32 / p32 / 1e3) / 1e9 / HBM_PEAK_GBS,
+            **traffic_fields("preheat%d_order%d" % (args.n, args.order), "f32", tile_str(tile32),
+                             4 * 4 * nf * n3),
             "friedmann_residual": e32["friedmann_residual"], "tile": list(tile32)}
     if not args.no_512 and args.precision == "f64" and args.n == 256:
         log("512^3 FP32 Q-ball ...")
@@ -647,14 +673,16 @@ def main():
     if not args.no_configs and args.precision == "f64" and args.n == 256:
         log("other configurations ...")
         o4 = measure_config(sl, synth.preheat(n=256, order=4, dt=0.0025, precision="f64"), 100,
-                            "preheat256_order4")
+                            "preheat256_order4", "preheat256_order4")
         o4["paper_context"] = {k: {"value": v, "ratio": o4["value"] / v}
                                for k, v in PAPER_256_ORDER4.items()}
         out["preheat256_fp64_order4"] = o4
         out["preheat128_fp64_order6"] = measure_config(
-            sl, synth.preheat(n=128, order=6, dt=0.0025, precision="f64"), 200, "preheat128")
+            sl, synth.preheat(n=128, order=6, dt=0.0025, precision="f64"), 200, "preheat128",
+            "preheat128_order6")
         osc = synth.oscillon(n=128)
-        out["oscillon128_fp32_order4"] = measure_config(sl, osc, 200, "oscillon128")
+        out["oscillon128_fp32_order4"] = measure_config(sl, osc, 200, "oscillon128",
+                                                        "oscillon128_order4")
         out["oscillon128_fp32_order4"]["error_vs_fp64"] = fp64_error(
             sl, osc, out["oscillon128_fp32_order4"]["tile"])
     if not args.no_batched and args.precision == "f64" and args.n == 256:
