@@ -319,11 +319,17 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, const Chain& C, i
       }
   };
 
-  // prologue: planes z0 - 1 and z0 of the own column, loaded while the
-  // stage scalars are formed
-  T mph[NF][VX], mpi[NF][VX];
+  // prologue: planes z0 - 1 and z0 of the own column (and for PF = 2 the
+  // first iteration's loads: own plane z0 + 1, halo of plane z0), all
+  // issued before the stage scalars are formed, so that their latency
+  // overlaps the scalar update
+  T mph[NF][VX], mpi[NF][VX], cph[NF][VX], cpi[NF][VX];
   load_own_into((z0 - 1 + n) % n, mph, mpi);
-  load_own(z0);
+  load_own_into(z0, cph, cpi);
+  if constexpr (PF == 2) {
+    load_own(wrap(z0 + 1));
+    load_halo(z0);
+  }
   stage_scalars<CH>(P, C, tile_id, S, red_scratch, fresh, cp);
   c = static_cast<T>(S.c_next);
   alpha = static_cast<T>(S.alpha);
@@ -337,12 +343,10 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, const Chain& C, i
   for (int i = 0; i < NF; ++i)
 #pragma unroll
     for (int v = 0; v < VX; ++v) {
-      pc[i][v] = npi[i][v];
-      fc[i][v] = drift(nph[i][v], npi[i][v], c);
+      pc[i][v] = cpi[i][v];
+      fc[i][v] = drift(cph[i][v], cpi[i][v], c);
     }
   if constexpr (PF == 2) {
-    load_own(wrap(z0 + 1));
-    load_halo(z0);
     // Same trailing sequence as a loop iteration (loads, then 2 NF stores),
     // so the wait counts the compiler derives at the loop head do not cover
     // the previous plane's stores.  The stores go to a per-thread sink slot
@@ -756,9 +760,13 @@ __device__ void end_stage(DevScalars& S, const BgConsts& K, const double* offs, 
   const double half = 0.5 * tau;
   if (K.split) {
     // the pass wrote the remainders around the offsets it recorded
-    for (int i = 0; i < K.nf; ++i) {
-      S.off_phi[i] = offs[i];
-      S.off_pi[i] = offs[kMaxFields + i];
+    // (constant indices: S stays in registers, not in scratch memory)
+#pragma unroll
+    for (int i = 0; i < kMaxFields; ++i) {
+      if (i < K.nf) {
+        S.off_phi[i] = offs[i];
+        S.off_pi[i] = offs[kMaxFields + i];
+      }
     }
   }
   if (K.expand) {
