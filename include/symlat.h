@@ -349,21 +349,24 @@ sl_status sl_set_tile(sl_lattice* lat, int32_t tx, int32_t vx, int32_t tz, int32
  * (mode 1): every workgroup of that pass reduces the previous pass's
  * per-tile sums and forms the same scalars before its z-march, and one
  * finalize kernel closes each captured chunk of steps.  Both modes give
- * bitwise identical fields, background and history.  mode -1 (the
- * default) chains lattices with at most 1024 tiles and at least 256 KiB of
- * field traffic per tile, where the saved kernel outweighs the later start
- * of each workgroup; mode 1 chains whenever there are at most 1024 tiles.
- * Batches do not chain.  SL_E_INVALID for other modes. */
+ * bitwise identical fields, background and history.  Modes -1 (the
+ * default) and 1 chain lattices with at most 1024 tiles (more run a
+ * finalize after every pass); mode 0 never chains.  Batches do not chain.
+ * SL_E_INVALID for other modes. */
 sl_status sl_set_chaining(sl_lattice* lat, int32_t mode);
 
 /* Autotuner: time candidate shapes (tx in {16, 32, 64}, 8 with vx = 4, and
  * n/vx when that is in [8, 64] and not a power of two, i.e. a whole row per
  * tile; vx in {1, 2, 4} dividing n; pf in {1, 2, 5, 6}; tz in {occupancy choice,
  * n/16, n/8, n/4, n/2}, at least 8, and for n <= 128 also 1, 2 and 4)
- * on the lattice's current state: best of `reps` HIP-event timings of two
- * consecutive stages (fused pass + finalize, each reading what the previous
- * wrote, as inside sl_evolve) with the drift and kick coefficients frozen at
- * zero, so the fields keep their values; the scalars are restored after.
+ * on the lattice's current state: best of `reps` HIP-event timings of six
+ * consecutive stages as sl_evolve runs them with that shape (chained
+ * passes, or fused pass + finalize where the passes do not chain; each
+ * reading what the previous wrote) with the drift and kick coefficients
+ * frozen at zero, so the fields keep their values; the scalars are restored
+ * after.  The three fastest (those within 5 % of the best) are then timed
+ * again, in turn after a warm-up, over 24 stages each, and the fastest of
+ * those wins.
  * best_ms is the time of one stage.  vx_only / pf_only
  * (0 = free) restrict the search; a batch member is tuned within its own vx
  * and pf (the batch is rebuilt at its next step).

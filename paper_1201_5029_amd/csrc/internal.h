@@ -171,14 +171,9 @@ struct Chain {
   double h;          // step size
 };
 
-// Passes chain only for lattices with at most this many tiles (every
-// workgroup of a chained pass reads all partials of the previous one) and
-// at least this much field traffic per tile: the stage update delays the
-// start of each workgroup's z-march by a few microseconds, which a short
-// march (or a workgroup that runs several tiles in turn) does not recover
-// from the stage finalize it saves.
+// Passes chain only for lattices with at most this many tiles: every
+// workgroup of a chained pass reads all partials of the previous one.
 constexpr int kChainMaxTiles = 1024;
-constexpr size_t kChainMinTileBytes = size_t(256) << 10;
 
 // One run of a batch for the finalize / begin kernels.
 struct BatchRun {

@@ -939,14 +939,8 @@ sl_status check_stable(sl_lattice* L, double dt, int order) {
   return SL_OK;
 }
 
-// Whether the stage passes of this lattice chain (see Chain): few enough
-// tiles, and enough traffic per tile (sites x fields x 4 array accesses).
-bool chain_passes(const LatView& v) {
-  const Tile& t = v.tile;
-  const size_t elem = v.prec == SL_FP32 ? 4 : 8;
-  const size_t tile_bytes = size_t(t.tx) * t.vx * t.ty * t.tz * v.nf * elem * 4;
-  return t.nblocks() <= kChainMaxTiles && tile_bytes >= kChainMinTileBytes;
-}
+// Whether the stage passes of this lattice chain (see Chain).
+bool chain_passes(const LatView& v) { return v.tile.nblocks() <= kChainMaxTiles; }
 
 }  // namespace
 
@@ -966,8 +960,7 @@ sl_status sl_evolve(sl_lattice* L, int64_t steps, double dt, int32_t order) {
   // after the first finishes the previous stage itself, and one stage
   // finalize closes the segment; lattices of more than kChainMaxTiles
   // tiles run a stage finalize after every pass instead.
-  const bool chained = L->chain_mode < 0 ? chain_passes(L->v)
-                                         : L->chain_mode == 1 && L->v.tile.nblocks() <= kChainMaxTiles;
+  const bool chained = L->chain_mode != 0 && chain_passes(L->v);
   auto enqueue_steps = [&](int64_t nsteps, bool last_chunk) -> sl_status {
     int64_t m = 0;  // pass index within the segment
     for (int64_t step = 0; step < nsteps; ++step) {
@@ -1365,28 +1358,71 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
     if (e == hipSuccess) e = launch_stage_finalize(L->v, 0, 0, 1.0, 1.0, 0.0, 1, 0, L->stream);
     return e;
   };
+  // Each timing covers kTuneStages consecutive stages (a short sequence
+  // after an idle stream favoured shapes that lose in a long run).  Shapes
+  // under which sl_evolve chains its passes are timed as chained passes
+  // (each finishing the previous frozen stage), after a plain stage that
+  // leaves partials and offsets in buffer 0.
+  constexpr int kTuneStages = 6;
+  auto chained_run = [&](int nstages) -> hipError_t {
+    Chain c{};
+    c.chain = 1;
+    c.w_prev = 1.0;
+    c.w = 1.0;
+    for (int k = 0; k < nstages; ++k) {
+      c.s_in = c.p_in = k & 1;
+      c.s_out = c.p_out = 1 - (k & 1);
+      const hipError_t e = launch_pass(L->v, c, L->stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  hipError_t err = hipSuccess;
+  // one timing of `nstages` stages of candidate c (after a plain stage in
+  // its shape), per stage
+  auto time_once = [&](const Cand& c, int nstages) -> double {
+    retile(L, c.tx, c.vx, c.tz, c.pf);
+    const bool ch = L->chain_mode != 0 && chain_passes(L->v);
+    err = stage();
+    if (err == hipSuccess) err = hipEventRecord(e0, L->stream);
+    if (err == hipSuccess) {
+      if (ch)
+        err = chained_run(nstages);
+      else
+        for (int k = 0; k < nstages && err == hipSuccess; ++k) err = stage();
+    }
+    if (err == hipSuccess) err = hipEventRecord(e1, L->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    return err == hipSuccess ? ms / nstages : 1e300;
+  };
+  std::vector<std::pair<double, int>> timed;
+  for (size_t i = 0; i < cands.size() && err == hipSuccess; ++i) {
+    double t = 1e300;
+    for (int r = 0; r < reps && err == hipSuccess; ++r) t = std::min(t, time_once(cands[i], kTuneStages));
+    timed.emplace_back(t, int(i));
+  }
+  // The fastest few are timed again, over four times as many stages and
+  // in turn (after a warm-up of the GPU), so that they see the same clock
+  // and power state: short timings of an idle GPU favoured shapes that
+  // lose by 1-2 % in a long run.
+  std::sort(timed.begin(), timed.end());
+  std::vector<int> top;
+  for (size_t i = 0; i < timed.size() && i < 3; ++i)
+    if (timed[i].first <= 1.05 * timed[0].first) top.push_back(timed[i].second);
+  std::vector<double> t_top(top.size(), 1e300);
+  if (!top.empty() && err == hipSuccess) (void)time_once(cands[top[0]], 8 * kTuneStages);
+  for (int r = 0; r < reps && err == hipSuccess; ++r)
+    for (size_t i = 0; i < top.size() && err == hipSuccess; ++i)
+      t_top[i] = std::min(t_top[i], time_once(cands[top[i]], 4 * kTuneStages));
   double best = 1e300;
   Cand win = cands[0];
-  hipError_t err = hipSuccess;
-  for (const Cand& c : cands) {
-    retile(L, c.tx, c.vx, c.tz, c.pf);
-    err = stage();
-    double t_min = 1e300;
-    for (int r = 0; r < reps && err == hipSuccess; ++r) {
-      err = hipEventRecord(e0, L->stream);
-      for (int k = 0; k < 2 && err == hipSuccess; ++k) err = stage();
-      if (err == hipSuccess) err = hipEventRecord(e1, L->stream);
-      if (err == hipSuccess) err = hipEventSynchronize(e1);
-      float ms = 0.0f;
-      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-      if (err == hipSuccess && 0.5 * ms < t_min) t_min = 0.5 * ms;
+  for (size_t i = 0; i < top.size(); ++i)
+    if (t_top[i] < best) {
+      best = t_top[i];
+      win = cands[top[i]];
     }
-    if (err != hipSuccess) break;
-    if (t_min < best) {
-      best = t_min;
-      win = c;
-    }
-  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   // the buffer saved_sc.parity names holds the state (a frozen stage writes
