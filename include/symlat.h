@@ -364,9 +364,10 @@ sl_status sl_set_chaining(sl_lattice* lat, int32_t mode);
  * passes, or fused pass + finalize where the passes do not chain; each
  * reading what the previous wrote) with the drift and kick coefficients
  * frozen at zero, so the fields keep their values; the scalars are restored
- * after.  The three fastest (those within 5 % of the best) are then timed
- * again, in turn after a warm-up, over 24 stages each, and the fastest of
- * those wins.
+ * after.  Before any timing the GPU is warmed up (0.1 s of frozen stages
+ * in the current shape).  The three fastest (those within 5 % of the best)
+ * are then timed again, in turn after a warm-up, over 24 stages each, and
+ * the fastest of those wins.
  * best_ms is the time of one stage.  vx_only / pf_only
  * (0 = free) restrict the search; a batch member is tuned within its own vx
  * and pf (the batch is rebuilt at its next step).

@@ -1397,6 +1397,16 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
     if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
     return err == hipSuccess ? ms / nstages : 1e300;
   };
+  // A GPU that has been idle runs its first ~0.1 s of work at a higher
+  // clock than it sustains, which favours latency-bound shapes: run frozen
+  // stages of the current shape for at least kWarmMs before timing anything.
+  constexpr double kWarmMs = 100.0;
+  {
+    const Cand cur{saved.tx, saved.vx, saved_tz, saved.pf};
+    double warm = 0.0;
+    for (int k = 0; k < 1000 && warm < kWarmMs && err == hipSuccess; ++k)
+      warm += kTuneStages * time_once(cur, kTuneStages);
+  }
   std::vector<std::pair<double, int>> timed;
   for (size_t i = 0; i < cands.size() && err == hipSuccess; ++i) {
     double t = 1e300;
