@@ -196,8 +196,10 @@ sl_status sl_init_fluctuations(sl_lattice* lat, const double* phi0, const double
  * the given order: 2 (eq. (2.48)), 4 (triple jump, eq. (2.43)), 6 or 8
  * (Table 1).  Each stage is one fused device pass (drift owed from the
  * previous H2 flows, Laplacian, kick, FP64 block sums) and one device-side
- * scalar update; the trailing field drift of the last stage is kept
- * pending, so evolve(a) then evolve(b) equals evolve(a + b) bit for bit.
+ * scalar update, run by the next pass itself where passes chain (see
+ * sl_set_chaining) or by a one-workgroup kernel; the trailing field drift
+ * of the last stage is kept pending, so evolve(a) then evolve(b) equals
+ * evolve(a + b) bit for bit.
  * Interior chunks of 32 steps replay a HIP graph captured on first use (the
  * same launches as the eager path; recaptured when dt, order or the launch
  * shape change); the final 1..32 steps and timed calls launch eagerly.
