@@ -73,7 +73,7 @@ struct DevScalars {
   // stored (the pending drift applies to both parts).  FP64 storage keeps
   // the offsets at 0.  A pass forms the offsets of the state it writes,
   // off_phi + c_next off_pi and off_pi - beta dV(that), and its first tile
-  // records them for the stage finalize (PassParams::offs).
+  // records them for the stage update (PassParams::offs).
   double off_phi[kMaxFields];
   double off_pi[kMaxFields];
 };

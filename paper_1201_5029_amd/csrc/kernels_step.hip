@@ -15,7 +15,9 @@
 // and sums, in FP64 with compensation, the lattice quantities the background
 // flows need: sum phi~ D phi~ and sum V (for the H3 kick of p_a) and
 // sum pi'^2 (for the H2 kicks of p_a).  The global sums make every stage a
-// grid-wide dependency, so a stage is one pass plus one small finalize.
+// grid-wide dependency: a stage is one pass plus a scalar update, which the
+// next pass runs itself (a chained pass, see Chain) or a small finalize
+// kernel runs after it.
 //
 // Data layout: in phi and pi the fields of each z-plane follow one another
 // (x fastest), planes P.zs n^2 elements apart (zs = nf, or 2 nf when phi and
@@ -129,7 +131,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // parts of the stage's drift and kick, fbar = off_phi + c off_pi and
 // pibar = off_pi - beta dV(fbar), in FP64 (every lane forms the same values)
 // -- and the constants of the difference form of dV around fbar.  The first
-// tile records them for the stage finalize.
+// tile records them for the stage update (finalize or next chained pass).
 template <int KIND, int NF, typename T>
 __device__ __forceinline__ void split_offsets(const PassParams& P, const DevScalars& S,
                                               double* offs_out, int tile_id, double (&fbar)[NF],
