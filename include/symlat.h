@@ -330,9 +330,11 @@ sl_status sl_kernel_timing(sl_lattice* lat, int64_t* passes, double* total_ms);
  * ty = floor(256/tx) rows (the remaining 256 - tx*ty lanes of the workgroup
  * idle), tz z-planes per workgroup, and the pass mode pf: the prefetch
  * depth of the z-march (1: next plane loaded each iteration; 2: own column
- * two planes and halo one plane ahead), plus 4 to write the results with
- * non-temporal stores (so they do not displace halo data in the L2; the
- * 7-point stencil with vx = 2 or 4 only), i.e. pf in {1, 2, 5, 6}.
+ * two planes and halo one plane ahead; 3: own column three planes and halo
+ * two planes ahead, with non-temporal stores only), plus 4 to write the
+ * results with non-temporal stores (so they do not displace halo data in
+ * the L2; the 7-point stencil with vx = 2 or 4 only), i.e. pf in
+ * {1, 2, 5, 6, 7}.
  * Lattices with more than two fields run with vx = 1, pf = 1; any stencil
  * other than the 7-point one runs with pf = 1 and vx = 1 or 2 (2 only up to
  * two fields; 2 tx + 2 ty + 4 <= 256 halo lanes, true for every tx).  A batch
@@ -359,7 +361,7 @@ sl_status sl_set_chaining(sl_lattice* lat, int32_t mode);
 
 /* Autotuner: time candidate shapes (tx in {16, 32, 64}, 8 with vx = 4, and
  * n/vx when that is in [8, 64] and not a power of two, i.e. a whole row per
- * tile; vx in {1, 2, 4} dividing n; pf in {1, 2, 5, 6}; tz in {occupancy choice,
+ * tile; vx in {1, 2, 4} dividing n; pf in {1, 2, 5, 6, 7}; tz in {occupancy choice,
  * n/16, n/8, n/4, n/2}, at least 8, and for n <= 128 also 1, 2 and 4)
  * on the lattice's current state: best of `reps` HIP-event timings of six
  * consecutive stages as sl_evolve runs them with that shape (chained
@@ -368,8 +370,9 @@ sl_status sl_set_chaining(sl_lattice* lat, int32_t mode);
  * frozen at zero, so the fields keep their values; the scalars are restored
  * after.  Before any timing the GPU is warmed up (0.1 s of frozen stages
  * in the current shape).  The three fastest (those within 5 % of the best)
- * are then timed again, in turn after a warm-up, over 24 stages each, and
- * the fastest of those wins.
+ * are then timed again over 24 stages each, in max(reps, 3) rounds that
+ * take them in rotating order, all enqueued back to back behind a warm-up
+ * with no host wait between them, and the lowest mean wins.
  * best_ms is the time of one stage.  vx_only / pf_only
  * (0 = free) restrict the search; a batch member is tuned within its own vx
  * and pf (the batch is rebuilt at its next step).
@@ -416,7 +419,7 @@ sl_status sl_batch_get_grid(const sl_batch* batch, int32_t* requested, int32_t* 
 /* Advance every member `steps` steps (same dt and order for all). */
 sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order);
 /* Batch autotuner: every per-lane shape (vx in {1, 2, 4} dividing all
- * member sizes, pf in {1, 2, 5, 6}, as the field count and stencil allow) is timed
+ * member sizes, pf in {1, 2, 5, 6, 7}, as the field count and stencil allow) is timed
  * at starting shapes (a whole row per tile, at most 64 lanes, quarter-lattice
  * z-chunks); for the three fastest, per member size (largest share
  * of sites first, two rounds of coordinate descent) the same tx candidates

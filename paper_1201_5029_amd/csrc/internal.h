@@ -117,17 +117,20 @@ struct Stencil {
 // Launch shape of the tiled passes: TX lanes in x (8 .. 64) each holding VX
 // consecutive sites (tile width TX*VX), TY = floor(256/TX) rows in y (the
 // last 256 - TX*TY lanes of the workgroup idle), TZ planes per z-chunk.
-// Pass mode pf: the prefetch depth of the z-march (1 or 2 planes), plus
+// Pass mode pf: the prefetch depth of the z-march (1, 2 or 3 planes), plus
 // kPfNontemporal when the results are written with non-temporal stores
-// (7-point pass, at most two fields, 2 or 4 sites per lane).
+// (7-point pass, at most two fields, 2 or 4 sites per lane).  Depth 3 comes
+// with non-temporal stores only.
 constexpr int kPfNontemporal = 4;
 inline int pf_depth(int pf) { return pf & 3; }
 inline bool pf_nt(int pf) { return (pf & kPfNontemporal) != 0; }
-inline bool pf_valid(int pf) { return pf_depth(pf) == 1 || pf_depth(pf) == 2; }
+inline bool pf_valid(int pf) {
+  return pf >= 1 && pf <= 7 && pf_depth(pf) != 0 && (pf_depth(pf) != 3 || pf_nt(pf));
+}
 
 struct Tile {
   int tx, ty, tz, vx;
-  int pf;  // pass mode: prefetch depth (1 or 2) | kPfNontemporal
+  int pf;  // pass mode: prefetch depth (1, 2 or 3) | kPfNontemporal
   int ntx, nty, ntz;
   int nblocks() const { return ntx * nty * ntz; }
 };

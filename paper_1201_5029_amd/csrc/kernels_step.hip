@@ -179,7 +179,8 @@ __device__ void stage_scalars(const PassParams& P, const Chain& C, int tile_id, 
 // PF = 1: the next plane is loaded at the top of each z-iteration and used
 // at once.  PF = 2: software pipeline -- the loads for plane z+1 (own column
 // one plane further ahead, and the halo) are issued right after the barrier
-// of plane z, before plane z's stores.  Vector-memory counters retire in
+// of plane z, before plane z's stores.  PF = 3: the same, one plane further
+// ahead again, with two register sets used in turn.  Vector-memory counters retire in
 // issue order, so a wavefront does not wait for its own stores before it
 // uses the next plane's data -- provided every lane issues the same memory
 // instructions: idle lanes (past the tile's ragged x or y edge, or past its
@@ -187,6 +188,11 @@ __device__ void stage_scalars(const PassParams& P, const Chain& C, int tile_id, 
 // compute its sites and store the same values to the same addresses, which
 // costs no memory traffic -- but add nothing to the partial sums, and x-halo
 // cells are fetched as the aligned VX-wide group that contains them.
+template <int I>
+struct Half {
+  static constexpr int value = I;
+};
+
 template <typename T, int NF, int KIND, int VX, int PF, bool NT, bool CH>
 __device__ __forceinline__ void pass_tile(const PassParams& P, const Chain& C, int tile_id, T* lds,
                                           KSum* red_scratch, DevScalars& S, bool fresh) {
@@ -284,53 +290,76 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, const Chain& C, i
     }
   };
   auto load_own = [&](int zz) { load_own_into(zz, nph, npi); };
-  auto load_halo = [&](int zz) {
+  auto load_halo_into = [&](int zz, T (&oph)[NF][VX], T (&opi)[NF][VX]) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
       const size_t o = (size_t(zz) * P.zs + i) * n2 + hcol;
       const Vec<T, VX> u = ldv<T, VX>(phi_in + o), w = ldv<T, VX>(pi_in + o);
 #pragma unroll
       for (int v = 0; v < VX; ++v) {
-        hph[i][v] = u.v[v];
-        hpi[i][v] = w.v[v];
+        oph[i][v] = u.v[v];
+        opi[i][v] = w.v[v];
       }
     }
   };
-  auto halo_to_lds = [&](T* L) {
+  auto load_halo = [&](int zz) { load_halo_into(zz, hph, hpi); };
+  auto halo_to_lds_from = [&](T* L, const T (&gph)[NF][VX], const T (&gpi)[NF][VX]) {
     if (hjob == 1) {
 #pragma unroll
       for (int i = 0; i < NF; ++i)
 #pragma unroll
-        for (int v = 0; v < VX; ++v) L[i * plane + hl + v] = drift(hph[i][v], hpi[i][v], c);
+        for (int v = 0; v < VX; ++v) L[i * plane + hl + v] = drift(gph[i][v], gpi[i][v], c);
     } else if (hjob >= 2) {
 #pragma unroll
       for (int i = 0; i < NF; ++i) {
-        const T f = hjob == 2 ? hph[i][VX - 1] : hph[i][0];
-        const T q = hjob == 2 ? hpi[i][VX - 1] : hpi[i][0];
+        const T f = hjob == 2 ? gph[i][VX - 1] : gph[i][0];
+        const T q = hjob == 2 ? gpi[i][VX - 1] : gpi[i][0];
         L[i * plane + hl] = drift(f, q, c);
       }
     }
   };
-  auto take_next = [&]() {  // fp, pp from the raw own-column loads
+  auto halo_to_lds = [&](T* L) { halo_to_lds_from(L, hph, hpi); };
+  // fp, pp from raw own-column loads
+  auto take_from = [&](const T (&oph)[NF][VX], const T (&opi)[NF][VX]) {
 #pragma unroll
     for (int i = 0; i < NF; ++i)
 #pragma unroll
       for (int v = 0; v < VX; ++v) {
-        pp[i][v] = npi[i][v];
-        fp[i][v] = drift(nph[i][v], npi[i][v], c);
+        pp[i][v] = opi[i][v];
+        fp[i][v] = drift(oph[i][v], opi[i][v], c);
       }
   };
+  auto take_next = [&]() { take_from(nph, npi); };
 
   // prologue: planes z0 - 1 and z0 of the own column (and for PF = 2 the
   // first iteration's loads: own plane z0 + 1, halo of plane z0), all
   // issued before the stage scalars are formed, so that their latency
   // overlaps the scalar update
   T mph[NF][VX], mpi[NF][VX], cph[NF][VX], cpi[NF][VX];
+  // second register set of the depth-3 pipeline (the first: nph/npi, hph/hpi)
+  [[maybe_unused]] T qph[NF][VX], qpi[NF][VX], gph[NF][VX], gpi[NF][VX];
   load_own_into((z0 - 1 + n) % n, mph, mpi);
   load_own_into(z0, cph, cpi);
   if constexpr (PF == 2) {
     load_own(wrap(z0 + 1));
     load_halo(z0);
+  }
+  if constexpr (PF == 3) {
+    // planes z0 + 1 and z0 + 2 of the own column and the halo of z0 and
+    // z0 + 1, each pair followed by 2 NF stores into the sink slot: the same
+    // trailing sequence as two loop iterations (see the PF = 2 sink below)
+    T* sink = static_cast<T*>(P.sink) + size_t(tid) * (2 * NF * VX);
+    T zero[VX];
+#pragma unroll
+    for (int v = 0; v < VX; ++v) zero[v] = T(0);
+    load_own(wrap(min(z0 + 1, zend)));
+    load_halo(z0);
+#pragma unroll
+    for (int i = 0; i < 2 * NF; ++i) stv<T, VX>(sink + i * VX, zero);
+    load_own_into(wrap(min(z0 + 2, zend)), qph, qpi);
+    load_halo_into(min(z0 + 1, zend - 1), gph, gpi);
+#pragma unroll
+    for (int i = 0; i < 2 * NF; ++i) stv<T, VX>(sink + i * VX, zero);
   }
   stage_scalars<CH>(P, C, tile_id, S, red_scratch, fresh, cp);
   c = static_cast<T>(S.c_next);
@@ -361,81 +390,125 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, const Chain& C, i
     }
   }
 
-  int buf = 0;
-  for (int z = z0; z < zend; ++z) {
-    T* L = lds + size_t(buf) * NF * plane;
-    if constexpr (PF == 1) {
-      load_own(wrap(z + 1));
-      take_next();
-      load_halo(z);
-    } else {
-      take_next();  // loads issued before the previous plane's stores
-    }
-    halo_to_lds(L);
-    if (active) {
+  // the update of plane z from the drifted plane in LDS: kick, sums, the
+  // stores of plane z, and the shift of the register planes
+  auto update_plane = [&](int z, const T* L) {
+    double dd = 0.0, p2 = 0.0, vs = 0.0;
+    T pn[NF][VX];
 #pragma unroll
-      for (int i = 0; i < NF; ++i)
-#pragma unroll
-        for (int v = 0; v < VX; ++v) L[i * plane + own + v] = fc[i][v];
-    }
-    __syncthreads();
-    if constexpr (PF == 2) {
-      // next plane's loads go out before this plane's stores; past the end
-      // of the chunk they re-read the last plane (in range, unused)
-      load_own(wrap(min(z + 2, zend)));
-      load_halo(min(z + 1, zend - 1));
-    }
-    {
-      double dd = 0.0, p2 = 0.0, vs = 0.0;
-      T pn[NF][VX];
-#pragma unroll
-      for (int v = 0; v < VX; ++v) {
-        T f[NF], D[NF], dV[NF], V;
-#pragma unroll
-        for (int i = 0; i < NF; ++i) {
-          const T* Li = L + i * plane + own + v;
-          f[i] = fc[i][v];
-          D[i] = ((Li[-1] + Li[1]) + (Li[-LX] + Li[LX])) + (fm[i][v] + fp[i][v]) - T(6) * f[i];
-        }
-        if constexpr (kSplit)
-          potential_split<KIND, NF, T>(fbT, f, pot, sk, V, dV);  // dV(fbar + f) - dV(fbar)
-        else
-          potential<KIND, NF, T>(f, pot, V, dV);
-#pragma unroll
-        for (int i = 0; i < NF; ++i) {
-          pn[i][v] = pc[i][v] + alpha * D[i] - beta * dV[i];
-          if constexpr (kSplit) {
-            dd += (fbar[i] + double(f[i])) * double(D[i]);
-            const double q = pibar[i] + double(pn[i][v]);
-            p2 += q * q;
-          } else {
-            dd += double(f[i]) * double(D[i]);
-            p2 += double(pn[i][v]) * double(pn[i][v]);
-          }
-        }
-        vs += double(V);
-      }
+    for (int v = 0; v < VX; ++v) {
+      T f[NF], D[NF], dV[NF], V;
 #pragma unroll
       for (int i = 0; i < NF; ++i) {
-        const size_t oc = (size_t(z) * P.zs + i) * n2 + col;
-        stv_mode<NT, T, VX>(phi_out + oc, fc[i]);
-        stv_mode<NT, T, VX>(pi_out + oc, pn[i]);
+        const T* Li = L + i * plane + own + v;
+        f[i] = fc[i][v];
+        D[i] = ((Li[-1] + Li[1]) + (Li[-LX] + Li[LX])) + (fm[i][v] + fp[i][v]) - T(6) * f[i];
+      }
+      if constexpr (kSplit)
+        potential_split<KIND, NF, T>(fbT, f, pot, sk, V, dV);  // dV(fbar + f) - dV(fbar)
+      else
+        potential<KIND, NF, T>(f, pot, V, dV);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        pn[i][v] = pc[i][v] + alpha * D[i] - beta * dV[i];
+        if constexpr (kSplit) {
+          dd += (fbar[i] + double(f[i])) * double(D[i]);
+          const double q = pibar[i] + double(pn[i][v]);
+          p2 += q * q;
+        } else {
+          dd += double(f[i]) * double(D[i]);
+          p2 += double(pn[i][v]) * double(pn[i][v]);
+        }
+      }
+      vs += double(V);
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const size_t oc = (size_t(z) * P.zs + i) * n2 + col;
+      stv_mode<NT, T, VX>(phi_out + oc, fc[i]);
+      stv_mode<NT, T, VX>(pi_out + oc, pn[i]);
+    }
+    if (active) {
+      kadd(acc_dd, dd);
+      kadd(acc_v, vs);
+      kadd(acc_p, p2);
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+      for (int v = 0; v < VX; ++v) {
+        fm[i][v] = fc[i][v];
+        fc[i][v] = fp[i][v];
+        pc[i][v] = pp[i][v];
+      }
+  };
+
+  if constexpr (PF != 3) {
+    int buf = 0;
+    for (int z = z0; z < zend; ++z) {
+      T* L = lds + size_t(buf) * NF * plane;
+      if constexpr (PF == 1) {
+        load_own(wrap(z + 1));
+        take_next();
+        load_halo(z);
+      } else {
+        take_next();  // loads issued before the previous plane's stores
+      }
+      halo_to_lds(L);
+      if (active) {
+#pragma unroll
+        for (int i = 0; i < NF; ++i)
+#pragma unroll
+          for (int v = 0; v < VX; ++v) L[i * plane + own + v] = fc[i][v];
+      }
+      __syncthreads();
+      if constexpr (PF == 2) {
+        // next plane's loads go out before this plane's stores; past the end
+        // of the chunk they re-read the last plane (in range, unused)
+        load_own(wrap(min(z + 2, zend)));
+        load_halo(min(z + 1, zend - 1));
+      }
+      update_plane(z, L);
+      buf ^= 1;
+    }
+  } else {
+    // Depth 3: after the barrier of plane z the loads of own plane z + 3 and
+    // of the halo of plane z + 2 go out, into the register set that plane z
+    // has just emptied (set (z - z0) & 1, as is the LDS buffer).  Planes go
+    // in pairs so that each half names its set at compile time; past the end
+    // of the chunk the loads re-read the last planes (in range, unused).
+    auto half = [&](auto h, int z) {
+      constexpr int H = decltype(h)::value;
+      T* L = lds + size_t(H) * NF * plane;
+      if constexpr (H == 0) {
+        take_from(nph, npi);
+        halo_to_lds_from(L, hph, hpi);
+      } else {
+        take_from(qph, qpi);
+        halo_to_lds_from(L, gph, gpi);
       }
       if (active) {
-        kadd(acc_dd, dd);
-        kadd(acc_v, vs);
-        kadd(acc_p, p2);
+#pragma unroll
+        for (int i = 0; i < NF; ++i)
+#pragma unroll
+          for (int v = 0; v < VX; ++v) L[i * plane + own + v] = fc[i][v];
       }
-#pragma unroll
-      for (int i = 0; i < NF; ++i)
-#pragma unroll
-        for (int v = 0; v < VX; ++v) {
-          fm[i][v] = fc[i][v];
-          fc[i][v] = fp[i][v];
-          pc[i][v] = pp[i][v];
-        }
+      __syncthreads();
+      if constexpr (H == 0) {
+        load_own_into(wrap(min(z + 3, zend)), nph, npi);
+        load_halo_into(min(z + 2, zend - 1), hph, hpi);
+      } else {
+        load_own_into(wrap(min(z + 3, zend)), qph, qpi);
+        load_halo_into(min(z + 2, zend - 1), gph, gpi);
+      }
+      update_plane(z, L);
+    };
+    int z = z0;
+    for (; z + 1 < zend; z += 2) {
+      half(Half<0>{}, z);
+      half(Half<1>{}, z + 1);
     }
-    buf ^= 1;
+    if (z < zend) half(Half<0>{}, z);
   }
 
   KSum v3[3] = {acc_dd, acc_v, acc_p};
@@ -1036,7 +1109,11 @@ PassKernel pick_t(const Tile& t, int st) {
     const int depth = pf_depth(t.pf);
     if (pf_nt(t.pf) && t.vx >= 2) {
       // non-temporal result stores (2 or 4 sites per lane)
-      if (depth == 2) {
+      if (depth == 3) {
+        k.fn = t.vx == 4 ? pass_kernel<T, NF, KIND, 4, 3, 2> : pass_kernel<T, NF, KIND, 2, 3, 2>;
+        k.bfn = t.vx == 4 ? batched_pass_kernel<T, NF, KIND, 4, 3, 2>
+                          : batched_pass_kernel<T, NF, KIND, 2, 3, 2>;
+      } else if (depth == 2) {
         k.fn = t.vx == 4 ? pass_kernel<T, NF, KIND, 4, 2, 2> : pass_kernel<T, NF, KIND, 2, 2, 2>;
         k.bfn = t.vx == 4 ? batched_pass_kernel<T, NF, KIND, 4, 2, 2>
                           : batched_pass_kernel<T, NF, KIND, 2, 2, 2>;

@@ -1310,7 +1310,7 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
   for (int vx : {1, 2, 4}) {
     if (n % vx != 0 || (many && vx != 1) || (st27 && vx > 2) || (vx_only && vx != vx_only)) continue;
     for (int tx : tx_candidates(n, vx)) {
-      for (int pf : {1, 2, 1 | kPfNontemporal, 2 | kPfNontemporal}) {
+      for (int pf : {1, 2, 1 | kPfNontemporal, 2 | kPfNontemporal, 3 | kPfNontemporal}) {
         if (((many || st27) && pf != 1) || (pf_only && pf != pf_only)) continue;
         if (pf_nt(pf) && vx < 2) continue;
         std::vector<int> tzs = {0};
@@ -1378,24 +1378,32 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
     return hipSuccess;
   };
   hipError_t err = hipSuccess;
-  // one timing of `nstages` stages of candidate c (after a plain stage in
-  // its shape), per stage
-  auto time_once = [&](const Cand& c, int nstages) -> double {
+  // `nstages` stages of candidate c (after a plain stage in its shape)
+  // between events a and b, enqueued without waiting
+  auto enqueue_timed = [&](const Cand& c, int nstages, hipEvent_t a, hipEvent_t b) {
     retile(L, c.tx, c.vx, c.tz, c.pf);
     const bool ch = L->chain_mode != 0 && chain_passes(L->v);
-    err = stage();
-    if (err == hipSuccess) err = hipEventRecord(e0, L->stream);
+    if (err == hipSuccess) err = stage();
+    if (err == hipSuccess) err = hipEventRecord(a, L->stream);
     if (err == hipSuccess) {
       if (ch)
         err = chained_run(nstages);
       else
         for (int k = 0; k < nstages && err == hipSuccess; ++k) err = stage();
     }
-    if (err == hipSuccess) err = hipEventRecord(e1, L->stream);
-    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    if (err == hipSuccess) err = hipEventRecord(b, L->stream);
+  };
+  // milliseconds per stage between two recorded events
+  auto per_stage = [&](hipEvent_t a, hipEvent_t b, int nstages) -> double {
     float ms = 0.0f;
-    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess) err = hipEventSynchronize(b);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, a, b);
     return err == hipSuccess ? ms / nstages : 1e300;
+  };
+  // one timing of `nstages` stages of candidate c, per stage
+  auto time_once = [&](const Cand& c, int nstages) -> double {
+    enqueue_timed(c, nstages, e0, e1);
+    return per_stage(e0, e1, nstages);
   };
   // A GPU that has been idle runs its first ~0.1 s of work at a higher
   // clock than it sustains, which favours latency-bound shapes: run frozen
@@ -1413,19 +1421,39 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
     for (int r = 0; r < reps && err == hipSuccess; ++r) t = std::min(t, time_once(cands[i], kTuneStages));
     timed.emplace_back(t, int(i));
   }
-  // The fastest few are timed again, over four times as many stages and
-  // in turn (after a warm-up of the GPU), so that they see the same clock
-  // and power state: short timings of an idle GPU favoured shapes that
-  // lose by 1-2 % in a long run.
+  // The fastest few are timed again over four times as many stages, in
+  // rounds that take them in rotating order, all enqueued back to back
+  // behind a warm-up and read at the end: the GPU never idles between them,
+  // as in a long run (timings separated by host waits let the clock recover
+  // in the gaps, which favoured one-workgroup-per-CU shapes that lose by
+  // 1-1.5 % in a long run).  Each keeps the mean of its rounds.
   std::sort(timed.begin(), timed.end());
   std::vector<int> top;
   for (size_t i = 0; i < timed.size() && i < 3; ++i)
     if (timed[i].first <= 1.05 * timed[0].first) top.push_back(timed[i].second);
   std::vector<double> t_top(top.size(), 1e300);
-  if (!top.empty() && err == hipSuccess) (void)time_once(cands[top[0]], 8 * kTuneStages);
-  for (int r = 0; r < reps && err == hipSuccess; ++r)
-    for (size_t i = 0; i < top.size() && err == hipSuccess; ++i)
-      t_top[i] = std::min(t_top[i], time_once(cands[top[i]], 4 * kTuneStages));
+  if (top.size() == 1) t_top[0] = timed[0].first;
+  if (top.size() > 1 && err == hipSuccess) {
+    const int rounds = std::max(reps, 3);
+    const int ns = 4 * kTuneStages;
+    std::vector<hipEvent_t> ev(2 * top.size() * rounds, nullptr);
+    for (size_t k = 0; k < ev.size() && err == hipSuccess; ++k) err = timing_event_create(&ev[k]);
+    enqueue_timed(cands[top[0]], 8 * kTuneStages, e0, e1);
+    for (int r = 0; r < rounds && err == hipSuccess; ++r)
+      for (size_t j = 0; j < top.size() && err == hipSuccess; ++j) {
+        const size_t i = (j + r) % top.size();
+        const size_t k = 2 * (size_t(r) * top.size() + i);
+        enqueue_timed(cands[top[i]], ns, ev[k], ev[k + 1]);
+      }
+    std::fill(t_top.begin(), t_top.end(), 0.0);
+    for (int r = 0; r < rounds && err == hipSuccess; ++r)
+      for (size_t i = 0; i < top.size() && err == hipSuccess; ++i) {
+        const size_t k = 2 * (size_t(r) * top.size() + i);
+        t_top[i] += per_stage(ev[k], ev[k + 1], ns) / rounds;
+      }
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
   double best = 1e300;
   Cand win = cands[0];
   for (size_t i = 0; i < top.size(); ++i)
@@ -1480,7 +1508,7 @@ sl_status sl_set_tile(sl_lattice* L, int32_t tx, int32_t vx, int32_t tz, int32_t
   if (tx < 8 || tx > 64) return fail(SL_E_INVALID, "tx must be in [8, 64]");
   if (vx != 1 && vx != 2 && vx != 4) return fail(SL_E_INVALID, "vx must be 1, 2 or 4");
   if (L->cfg.n % vx != 0) return fail(SL_E_INVALID, "vx = %d needs n divisible by %d", vx, vx);
-  if (!pf_valid(pf)) return fail(SL_E_INVALID, "pf must be 1 or 2, plus 4 for non-temporal stores");
+  if (!pf_valid(pf)) return fail(SL_E_INVALID, "pf must be 1, 2, 5, 6 or 7 (depth 1, 2 or 3, plus 4 for non-temporal stores)");
   if (L->cfg.nfields > 2 && (vx != 1 || pf != 1))
     return fail(SL_E_INVALID, "more than two fields run with vx = 1 and pf = 1 only");
   if (L->v.st.kind != 0 && (vx > 2 || pf != 1))
@@ -1908,7 +1936,7 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
   for (int vx : {1, 2, 4}) {
     bool ok = !(B->nf > 2 && vx != 1) && !(B->st_kind != 0 && vx > 2);
     for (const auto& sz : sizes) ok = ok && sz.second % vx == 0;
-    for (int pf : {1, 2, 1 | kPfNontemporal, 2 | kPfNontemporal})
+    for (int pf : {1, 2, 1 | kPfNontemporal, 2 | kPfNontemporal, 3 | kPfNontemporal})
       if (ok && !((B->nf > 2 || B->st_kind != 0) && pf != 1) && !(pf_nt(pf) && vx < 2))
         lane_shapes.push_back({vx, pf});
   }

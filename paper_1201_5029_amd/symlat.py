@@ -372,7 +372,7 @@ class Lattice:
 
     # -- launch shape and timing ---------------------------------------------
     def tile(self):
-        """(tx lanes, vx sites per lane, ty rows, tz planes, pf prefetch depth)
+        """(tx lanes, vx sites per lane, ty rows, tz planes, pf pass mode)
         of the fused pass."""
         v = [ctypes.c_int32() for _ in range(5)]
         _check(self._lib.sl_get_tile(self._h, *[ctypes.byref(x) for x in v]))
