@@ -418,7 +418,8 @@ sl_status sl_batch_set_grid(sl_batch* batch, int32_t workgroups);
 sl_status sl_batch_get_grid(const sl_batch* batch, int32_t* requested, int32_t* launched);
 /* Advance every member `steps` steps (same dt and order for all). */
 sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order);
-/* Batch autotuner: every per-lane shape (vx in {1, 2, 4} dividing all
+/* Batch autotuner: after a warm-up of the GPU (0.1 s of the batched pass
+ * in the current shapes), every per-lane shape (vx in {1, 2, 4} dividing all
  * member sizes, pf in {1, 2, 5, 6, 7}, as the field count and stencil allow) is timed
  * at starting shapes (a whole row per tile, at most 64 lanes, quarter-lattice
  * z-chunks); for the three fastest, per member size (largest share
@@ -427,8 +428,9 @@ sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order
  * z-chunks n/{1, 2, 4, 8} (and n/3, n/6 where they divide n) are tried for
  * all members of that size, timing
  * the batched pass alone (best of `reps`
- * HIP-event timings of two passes; the members' states are left
- * unchanged), and keep a shape only if it is at least 0.5 % faster; last,
+ * HIP-event timings of four consecutive passes; the members' states are
+ * left unchanged), and keep a shape only if it is at least 1 % faster (a
+ * later lane shape replaces an earlier one likewise); last,
  * with the chosen shapes, the persistent grid of the resident capacity is
  * timed against one workgroup per tile and kept only if 0.5 % faster (see
  * sl_batch_set_grid).  The chosen shapes are applied to the members
@@ -438,8 +440,9 @@ sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order
  * empty batch. */
 sl_status sl_batch_autotune(sl_batch* batch, int32_t reps, double* best_ms);
 /* Time the batched pass with the members' current shapes, as the batch
- * autotuner times a candidate (best of `reps` HIP-event timings of two
- * passes; the members' states are left unchanged): *ms = one pass.
+ * autotuner times a candidate (best of `reps` HIP-event timings of four
+ * consecutive passes; the members' states are left unchanged): *ms = one
+ * pass.
  * SL_E_STATE for an empty batch. */
 sl_status sl_batch_time_pass(sl_batch* batch, int32_t reps, double* ms);
 /* Wait for the batch and report members' sticky device errors. */

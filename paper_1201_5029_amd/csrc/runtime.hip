@@ -1848,6 +1848,11 @@ namespace {
 // finalize it leaves every member's state as it was (it reads the current
 // buffer and writes the spare buffer and the partials).  Best of `reps`
 // timings of two consecutive passes, per pass.
+// Consecutive batched passes per timing: short windows after a host wait
+// run at a recovered clock, and their noise made the batch tuner's choice
+// among near-equal shapes change from process to process.
+constexpr int kBatchTimedPasses = 4;
+
 sl_status batch_time_pass(sl_batch* B, int reps, hipEvent_t e0, hipEvent_t e1, double* ms_out) {
   sl_status st = batch_upload(B);
   if (st != SL_OK) return st;
@@ -1856,14 +1861,14 @@ sl_status batch_time_pass(sl_batch* B, int reps, hipEvent_t e0, hipEvent_t e1, d
                               B->start_dev, int(B->runs.size()), B->grid, Chain{}, B->stream));
   for (int r = 0; r < reps; ++r) {
     HIP_TRY(hipEventRecord(e0, B->stream));
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < kBatchTimedPasses; ++k)
       HIP_TRY(launch_batched_pass(B->prec, B->pot, B->nf, B->shape, B->st_kind, B->lds, B->pass_dev,
                                   B->start_dev, int(B->runs.size()), B->grid, Chain{}, B->stream));
     HIP_TRY(hipEventRecord(e1, B->stream));
     HIP_TRY(hipEventSynchronize(e1));
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    if (0.5 * ms < best) best = 0.5 * ms;
+    if (ms / kBatchTimedPasses < best) best = ms / kBatchTimedPasses;
   }
   *ms_out = best;
   return SL_OK;
@@ -1969,8 +1974,23 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
     }
   };
   // phase 1: every lane shape at its starting shapes; phase 2 refines the
-  // three best
+  // three best.  A shape (or lane shape) replaces the current one only when
+  // it is faster by more than the timing noise (kBatchGain), so that sizes
+  // with a small share of the sites keep their starting shapes and the
+  // choice is the same from process to process.
+  constexpr double kBatchGain = 0.99;
   const int orig_vx = B->shape.vx, orig_pf = B->shape.pf;
+  // An idle GPU runs its first ~0.1 s of work at a higher clock than it
+  // sustains, which favoured the lane shapes timed first: run the current
+  // shapes for at least that long before timing anything.
+  {
+    double warm = 0.0;
+    for (int k = 0; k < 1000 && warm < 100.0 && st == SL_OK; ++k) {
+      double ms = 0.0;
+      st = time_now(&ms);
+      warm += ms * (1 + kBatchTimedPasses * reps);
+    }
+  }
   std::vector<std::pair<double, int>> ranked;
   for (size_t q = 0; q < lane_shapes.size() && st == SL_OK; ++q) {
     B->shape.vx = orig_vx;
@@ -2007,7 +2027,7 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
             double ms = 0.0;
             st = time_now(&ms);
             if (st != SL_OK) break;
-            if (ms < cur * 0.995) {
+            if (ms < cur * kBatchGain) {
               cur = ms;
               btx = tx;
               btz = tz;
@@ -2020,7 +2040,7 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
       }
     }
     if (st != SL_OK) break;
-    if (cur < best_all) {
+    if (cur < best_all * kBatchGain) {
       best_all = cur;
       best_vx = vx;
       best_pf = pf;
