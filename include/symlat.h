@@ -172,7 +172,7 @@ sl_status sl_set_potential(sl_lattice* lat, int32_t kind, const double* params, 
  * 4 c3 = 1); its leading error is isotropic when c1 = 2 c2 + 8 c3, e.g.
  * the 19-point (-4, 1/3, 1/6, 0) and 27-point (-128/30, 14/30, 3/30, 1/30)
  * members.  Any member other than the 7-point one runs the 27-point pass
- * (vx = 1 or 2 sites per lane, pf = 1).  The stencil enters the kick, the
+ * (vx = 1 or 2 sites per lane, pf = 1, or pf = 5 with vx = 2).  The stencil enters the kick, the
  * p_a sums, the observables, the stability bound (largest k_eff^2 over the
  * zone) and the vacuum mode frequencies, so set it before
  * sl_init_fluctuations.  c is a host array of 4 doubles.  SL_E_INVALID for
@@ -333,11 +333,11 @@ sl_status sl_kernel_timing(sl_lattice* lat, int64_t* passes, double* total_ms);
  * two planes and halo one plane ahead; 3: own column three planes and halo
  * two planes ahead, with non-temporal stores only), plus 4 to write the
  * results with non-temporal stores (so they do not displace halo data in
- * the L2; the 7-point stencil with vx = 2 or 4 only), i.e. pf in
- * {1, 2, 5, 6, 7}.
+ * the L2; vx = 2 or 4 only), i.e. pf in {1, 2, 5, 6, 7}.
  * Lattices with more than two fields run with vx = 1, pf = 1; any stencil
- * other than the 7-point one runs with pf = 1 and vx = 1 or 2 (2 only up to
- * two fields; 2 tx + 2 ty + 4 <= 256 halo lanes, true for every tx).  A batch
+ * other than the 7-point one runs with pf = 1 and vx = 1 or 2, or pf = 5
+ * and vx = 2 (2 only up to two fields; 2 tx + 2 ty + 4 <= 256 halo lanes,
+ * true for every tx).  A batch
  * member keeps its vx and pf.  sl_get_tile reports the shape in use; sl_set_tile
  * overrides it (tz = 0: z-chunk chosen from the kernel's occupancy so the
  * grid fills whole rounds of resident workgroups).  SL_E_INVALID for

@@ -536,8 +536,9 @@ __device__ __forceinline__ void pass_tile(const PassParams& P, const Chain& C, i
 // instructions are uniform across lanes (idle lanes load the tile's first
 // column and store into the sink; x-halo and corner cells are fetched as the
 // aligned VX-wide group that contains them), and the loads of plane p + 1 go
-// out after the barrier, before the stores of plane p - 1.
-template <typename T, int NF, int KIND, int VX, bool CH>
+// out after the barrier, before the stores of plane p - 1.  NT: the results
+// (and the idle lanes' sink stores) are written with non-temporal stores.
+template <typename T, int NF, int KIND, int VX, bool NT, bool CH>
 __device__ __forceinline__ void pass_tile27(const PassParams& P, const Chain& C, int tile_id, T* lds,
                                             KSum* red_scratch, DevScalars& S, bool fresh) {
   ChainPre cp;
@@ -729,8 +730,8 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, const Chain& C,
         const size_t oc = (zo * P.zs + i) * n2 + col;
         T* po = out ? phi_out + oc : sink + (2 * i) * VX;
         T* qo = out ? pi_out + oc : sink + (2 * i + 1) * VX;
-        stv<T, VX>(po, fB[i]);
-        stv<T, VX>(qo, pn[i]);
+        stv_mode<NT, T, VX>(po, fB[i]);
+        stv_mode<NT, T, VX>(qo, pn[i]);
       }
       if (out) {
         kadd(acc_dd, dd);
@@ -760,13 +761,14 @@ __device__ __forceinline__ void pass_tile27(const PassParams& P, const Chain& C,
 }
 
 // ST: 0 = 7-point pass, 1 = any member of the cubic family (27-point pass),
-// 2 = 7-point pass with non-temporal result stores.
+// 2 = 7-point pass with non-temporal result stores, 3 = 27-point pass with
+// non-temporal result stores.
 // CH: the kernel can run chained (the solo pass; batches never chain).
 template <typename T, int NF, int KIND, int VX, int PF, int ST, bool CH>
 __device__ __forceinline__ void pass_any(const PassParams& P, const Chain& C, int tile_id, T* lds,
                                          KSum* red, DevScalars& S, bool fresh) {
-  if constexpr (ST == 1)
-    pass_tile27<T, NF, KIND, VX, CH>(P, C, tile_id, lds, red, S, fresh);
+  if constexpr (ST == 1 || ST == 3)
+    pass_tile27<T, NF, KIND, VX, ST == 3, CH>(P, C, tile_id, lds, red, S, fresh);
   else
     pass_tile<T, NF, KIND, VX, PF, ST == 2, CH>(P, C, tile_id, lds, red, S, fresh);
 }
@@ -1096,8 +1098,9 @@ PassKernel pick_t(const Tile& t, int st) {
     // sites per lane for up to two fields
     if constexpr (NF <= 2) {
       if (t.vx == 2) {
-        k.fn = pass_kernel<T, NF, KIND, 2, 1, 1>;
-        k.bfn = batched_pass_kernel<T, NF, KIND, 2, 1, 1>;
+        k.fn = pf_nt(t.pf) ? pass_kernel<T, NF, KIND, 2, 1, 3> : pass_kernel<T, NF, KIND, 2, 1, 1>;
+        k.bfn = pf_nt(t.pf) ? batched_pass_kernel<T, NF, KIND, 2, 1, 3>
+                            : batched_pass_kernel<T, NF, KIND, 2, 1, 1>;
         return k;
       }
     }
@@ -1175,7 +1178,8 @@ hipError_t launch_pass(const LatView& v, const Chain& c, hipStream_t s) {
   if (v.nf < 1 || v.nf > kMaxFields) return hipErrorInvalidValue;
   if (!pf_valid(v.tile.pf)) return hipErrorInvalidValue;
   if (v.nf > 2 && (v.tile.vx != 1 || v.tile.pf != 1)) return hipErrorInvalidValue;
-  if (v.st.kind != 0 && (v.tile.vx > 2 || v.tile.pf != 1)) return hipErrorInvalidValue;
+  if (v.st.kind != 0 && (v.tile.vx > 2 || (v.tile.pf != 1 && v.tile.pf != (1 | kPfNontemporal))))
+    return hipErrorInvalidValue;
   if (pf_nt(v.tile.pf) && v.tile.vx < 2) return hipErrorInvalidValue;
   // the 27-point pass needs lanes for 2 rows + 2 columns + 4 corners of halo
   if (v.st.kind != 0 && 2 * v.tile.tx + 2 * v.tile.ty + 4 > kBlock) return hipErrorInvalidValue;

@@ -1300,7 +1300,7 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
     pf_only = L->v.tile.pf;
   }
   // more than two fields: one site per lane, pf = 1; the 27-point pass:
-  // one or two sites per lane, pf = 1
+  // one or two sites per lane, pf = 1, or two with non-temporal stores (5)
   const bool many = L->cfg.nfields > 2;
   const bool st27 = L->v.st.kind != 0;
   struct Cand {
@@ -1311,7 +1311,9 @@ sl_status sl_autotune(sl_lattice* L, int32_t reps, int32_t vx_only, int32_t pf_o
     if (n % vx != 0 || (many && vx != 1) || (st27 && vx > 2) || (vx_only && vx != vx_only)) continue;
     for (int tx : tx_candidates(n, vx)) {
       for (int pf : {1, 2, 1 | kPfNontemporal, 2 | kPfNontemporal, 3 | kPfNontemporal}) {
-        if (((many || st27) && pf != 1) || (pf_only && pf != pf_only)) continue;
+        if ((many && pf != 1) || (st27 && pf != 1 && pf != (1 | kPfNontemporal)) ||
+            (pf_only && pf != pf_only))
+          continue;
         if (pf_nt(pf) && vx < 2) continue;
         std::vector<int> tzs = {0};
         for (int d : {16, 8, 4, 2}) {
@@ -1511,8 +1513,8 @@ sl_status sl_set_tile(sl_lattice* L, int32_t tx, int32_t vx, int32_t tz, int32_t
   if (!pf_valid(pf)) return fail(SL_E_INVALID, "pf must be 1, 2, 5, 6 or 7 (depth 1, 2 or 3, plus 4 for non-temporal stores)");
   if (L->cfg.nfields > 2 && (vx != 1 || pf != 1))
     return fail(SL_E_INVALID, "more than two fields run with vx = 1 and pf = 1 only");
-  if (L->v.st.kind != 0 && (vx > 2 || pf != 1))
-    return fail(SL_E_INVALID, "the 27-point stencil runs with vx = 1 or 2 and pf = 1");
+  if (L->v.st.kind != 0 && (vx > 2 || (pf != 1 && pf != (1 | kPfNontemporal))))
+    return fail(SL_E_INVALID, "the 27-point stencil runs with vx = 1 or 2 and pf = 1, or vx = 2 and pf = 5");
   if (pf_nt(pf) && vx < 2) return fail(SL_E_INVALID, "non-temporal stores need vx = 2 or 4");
   if (L->batch && (vx != L->v.tile.vx || pf != L->v.tile.pf))
     return fail(SL_E_STATE, "a batch member keeps its vx and pf (remove it from the batch first)");
@@ -1942,7 +1944,8 @@ sl_status sl_batch_autotune(sl_batch* B, int32_t reps, double* best_ms) {
     bool ok = !(B->nf > 2 && vx != 1) && !(B->st_kind != 0 && vx > 2);
     for (const auto& sz : sizes) ok = ok && sz.second % vx == 0;
     for (int pf : {1, 2, 1 | kPfNontemporal, 2 | kPfNontemporal, 3 | kPfNontemporal})
-      if (ok && !((B->nf > 2 || B->st_kind != 0) && pf != 1) && !(pf_nt(pf) && vx < 2))
+      if (ok && !(B->nf > 2 && pf != 1) && !(B->st_kind != 0 && pf != 1 && pf != (1 | kPfNontemporal)) &&
+          !(pf_nt(pf) && vx < 2))
         lane_shapes.push_back({vx, pf});
   }
   batch_drop_graph(B);

@@ -1,11 +1,13 @@
-"""The depth-3 pipeline of the fused pass (pass mode 7: the loads of the own
-column run three planes ahead, two register sets used in turn, non-temporal
-stores) against depth 2 (mode 6).  The arithmetic and its order are the same,
-so from one synthetic state the two must give bitwise equal fields, momenta,
-background, history and energies -- over chunk lengths 1, 2, 3, odd and
-even, ragged tiles with idle lanes, both storage precisions, the potential
-families, two and four sites per lane, chained and unchained passes.  One
-case also meets the FP64 oracle gate directly."""
+"""Pass modes that change how the fused pass moves data but not what it
+computes.  The depth-3 pipeline (pass mode 7: the loads of the own column
+run three planes ahead, two register sets used in turn, non-temporal
+stores) against depth 2 (mode 6), and the 27-point pass with non-temporal
+stores (mode 5) against its cached stores (mode 1).  The arithmetic and its
+order are the same, so from one synthetic state the two must give bitwise
+equal fields, momenta, background, history and energies -- over chunk
+lengths 1, 2, 3, odd and even, ragged tiles with idle lanes, both storage
+precisions, the potential families, two and four sites per lane, chained
+and unchained passes.  Depth 3 also meets the FP64 oracle gate directly."""
 import math
 
 import numpy as np
@@ -37,24 +39,52 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", range(len(CASES)))
-def test_depth3_equals_depth2(case):
-    kind, prec, n, (tx, vx, tz), mode = CASES[case]
+# 27-point family: (family, precision, n, stencil, (tx, vx, tz), chaining mode)
+CASES27 = [
+    ("chaotic2", "f64", 28, "27", (16, 2, 6), 1),
+    ("oscillon", "f32", 26, "19", (8, 2, 5), 0),      # ragged: idle lanes store into the sink
+    ("chaotic2", "f32", 32, "27", (32, 2, 8), 1),
+    ("qball", "f64", 24, "27", (16, 2, 4), 1),
+]
+
+
+def _pair(kind, prec, n, tile, mode, ref_pf, pf, seed, stencil=None):
     params, base, mpl = MODELS[kind]
     nf = len(base)
     scale = max(abs(b) for b in base)
-    phi, pi = synth.gaussian_state(n, nf, 4400 + case, phi_base=list(base),
+    phi, pi = synth.gaussian_state(n, nf, seed, phi_base=list(base),
                                    phi_amp=1e-3 * scale, pi_amp=1e-3 * scale)
     lats = []
-    for pf in (6, 7):
+    for p in (ref_pf, pf):
         g = gpu_lattice(n, 0.5 * n, kind, params, phi, pi, precision=prec, mpl=mpl,
-                        tile=(tx, vx, tz, pf))
+                        tile=tuple(tile) + (p,), stencil=stencil)
         g.set_chaining(mode)
         g.set_history(64)
         lats.append(g)
-    g0, g1 = lats
+    return lats
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_depth3_equals_depth2(case):
+    kind, prec, n, tile, mode = CASES[case]
+    g0, g1 = _pair(kind, prec, n, tile, mode, 6, 7, 4400 + case)
     say("depth-3 case", case, kind, prec, "n", n, "tile", g1.tile(), "chaining", mode)
     assert g1.tile()[-1] == 7
+    _same_runs(kind, prec, g0, g1)
+
+
+@pytest.mark.parametrize("case", range(len(CASES27)))
+def test_27_point_nontemporal_equals_cached(case):
+    kind, prec, n, stencil, tile, mode = CASES27[case]
+    g0, g1 = _pair(kind, prec, n, tile, mode, 1, 5, 4460 + case, stencil=stencil)
+    say("27-point case", case, kind, prec, "n", n, "stencil", stencil, "tile", g1.tile(),
+        "chaining", mode)
+    assert g1.tile()[-1] == 5
+    _same_runs(kind, prec, g0, g1)
+
+
+def _same_runs(kind, prec, g0, g1):
+    lats = [g0, g1]
     for g in lats:
         g.evolve(37, 0.005, 4)      # one captured chunk of 32 steps, 5 eager
         g.evolve(3, 0.005, 6)
