@@ -429,8 +429,9 @@ sl_status sl_batch_step(sl_batch* batch, int64_t steps, double dt, int32_t order
  * all members of that size, timing
  * the batched pass alone (best of `reps`
  * HIP-event timings of four consecutive passes; the members' states are
- * left unchanged), and keep a shape only if it is at least 1 % faster (a
- * later lane shape replaces an earlier one likewise); last,
+ * left unchanged), and keep a shape only if it is at least 1 % faster,
+ * and again when the two are timed one right after the other (a later lane
+ * shape replaces an earlier one likewise); last,
  * with the chosen shapes, the persistent grid of the resident capacity is
  * timed against one workgroup per tile and kept only if 0.5 % faster (see
  * sl_batch_set_grid).  The chosen shapes are applied to the members
