@@ -1846,14 +1846,15 @@ sl_status sl_batch_remove(sl_batch* B, sl_lattice* L) {
 
 namespace {
 
-// Time the batched pass alone with the current shapes: without its
-// finalize it leaves every member's state as it was (it reads the current
-// buffer and writes the spare buffer and the partials).  Best of `reps`
-// timings of two consecutive passes, per pass.
 // Consecutive batched passes per timing: short windows after a host wait
 // run at a recovered clock, and their noise made the batch tuner's choice
 // among near-equal shapes change from process to process.
 constexpr int kBatchTimedPasses = 4;
+
+// Time the batched pass alone with the current shapes: without its
+// finalize it leaves every member's state as it was (it reads the current
+// buffer and writes the spare buffer and the partials).  Best of `reps`
+// timings of kBatchTimedPasses consecutive passes, per pass.
 
 sl_status batch_time_pass(sl_batch* B, int reps, hipEvent_t e0, hipEvent_t e1, double* ms_out) {
   sl_status st = batch_upload(B);
